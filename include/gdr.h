@@ -1,0 +1,191 @@
+/*
+ * gdr.h -- C-ABI of the MI355X library for deflated, restarted GMRES on
+ * multiply shifted systems with multiple right-hand sides:
+ *
+ *     (A - sigma_i I) x_i^j = b^j,   i = 1..ns (shifts), j = 1..nrhs,
+ *
+ * (Darnell, Morgan, Wilcox; Sec. 1, eq. (1.1)), with A the Wilson-Dirac
+ * matrix A = I - kappa D of Sec. 4, Example 7. sigma_1 is the base shift.
+ * There is no preconditioning (Sec. 1): all shifts share one Krylov space.
+ *
+ *  - the first right-hand side is solved by GMRES-DR-Sh (Sec. 3, algorithm
+ *    GMRES-DR-Sh), which also produces the deflation pair
+ *    A V_k = V_{k+1} H_bar_k (Sec. 2.2, eq. (2.9));
+ *  - the extra right-hand side v_{k+1} and every later right-hand side are
+ *    solved by GMRES-Proj-Sh (Sec. 4, the two GMRES-Proj-Sh algorithms),
+ *    followed by the correction x_i += (v_{k+1}^H r_i) s_i (eqs. (4.3)-(4.6)).
+ *
+ * Conventions
+ *  - Complex numbers are gdr_c64 {re, im} (binary compatible with C99
+ *    double complex / numpy complex128).
+ *  - Vectors cross the boundary in the canonical layout
+ *    [t][z][y][x][spin 4][colour 3], complex128, n = 12*Lx*Ly*Lz*Lt, and
+ *    several vectors are stored one after the other. All vector pointers are
+ *    DEVICE pointers on the context's device unless stated otherwise.
+ *  - Links: [mu = x,y,z,t][t][z][y][x][a 3][b 3] complex128, row-major 3x3,
+ *    U_mu(x) multiplies psi(x + mu). No boundary phases folded in.
+ *  - D psi(x) = sum_mu (1 - gamma_mu) U_mu(x) psi(x+mu)
+ *               + (1 + gamma_mu) U_mu(x-mu)^H psi(x-mu)
+ *    in the chiral basis (gamma5 = diag(1,1,-1,-1)); a hop that wraps in
+ *    direction mu is multiplied by bc[mu].
+ *  - Every call is synchronous on return: work is ordered on the context's
+ *    HIP stream and the call waits for it. No caller pointer is retained.
+ *  - Return codes: GDR_OK (0), GDR_NOT_CONVERGED (1, outputs valid and
+ *    residuals filled), or a negative error; gdr_last_error() describes it.
+ *  - One context per host thread; calls on one context must not overlap.
+ */
+#ifndef GDR_H
+#define GDR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { double re, im; } gdr_c64;
+typedef struct gdr_ctx_s* gdr_ctx;
+typedef struct gdr_op_s* gdr_op;
+typedef struct gdr_defl_s* gdr_defl;
+
+#define GDR_OK 0
+#define GDR_NOT_CONVERGED 1
+#define GDR_ERR_ARG (-1)       /* invalid argument (sizes, null pointers, m <= k, ...) */
+#define GDR_ERR_HIP (-2)       /* a HIP runtime call failed */
+#define GDR_ERR_OOM (-3)       /* device allocation failed */
+#define GDR_ERR_BREAKDOWN (-4) /* singular small system: (Q^H s)_{m+1} = 0, 1 - gamma_i = 0,
+                                  or H_k - sigma_i I singular (Secs. 2.1, 4) */
+#define GDR_ERR_STATE (-5)     /* handle used inconsistently (wrong op, shift list mismatch) */
+
+/* arithmetic of a solve or an operator application */
+#define GDR_PREC_F64 0   /* everything in FP64 */
+#define GDR_PREC_MIXED 1 /* FP32 matvecs, Gram-Schmidt and basis; FP64 small problems,
+                            solution accumulation and true residuals (refinement) */
+#define GDR_PREC_F32 1   /* gdr_op_apply only: FP32 arithmetic */
+
+/* storage of the gauge links used by the FP32 operator */
+#define GDR_LINKS_F64 0
+#define GDR_LINKS_F32 1
+#define GDR_LINKS_F16 2
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device`; all work is queued on
+ * `hip_stream` (a hipStream_t, or NULL for the default stream). The library
+ * owns *out until gdr_ctx_destroy. Errors: ARG (null out, bad device), HIP. */
+int gdr_ctx_create(int device, void* hip_stream, gdr_ctx* out);
+void gdr_ctx_destroy(gdr_ctx ctx);
+/* Last error message of the context (static storage owned by the context). */
+const char* gdr_last_error(gdr_ctx ctx);
+
+/* --------------------------------------------------------------- operator */
+
+/* The Wilson-Dirac matrix A = I - kappa D (Sec. 4, Example 7) on an
+ * Lx x Ly x Lz x Lt lattice, dims = {Lx, Ly, Lz, Lt}, every extent even and
+ * >= 2. bc[mu] is +1 (periodic) or -1 (antiperiodic). `links` is host memory
+ * (links_on_device = 0) or device memory (1) in the canonical link layout;
+ * it is copied into internal even-odd layouts (FP64 always, plus FP32 or
+ * FP16 per link_storage for the FP32 operator) and not retained.
+ * Errors: ARG, OOM, HIP. */
+int gdr_wilson_create(gdr_ctx ctx, const int dims[4], const int bc[4], double kappa,
+                      const gdr_c64* links, int links_on_device, int link_storage,
+                      gdr_op* out);
+void gdr_op_destroy(gdr_op op);
+/* Number of complex unknowns n = 12 * volume. */
+int64_t gdr_op_size(gdr_op op);
+
+/* y_v = (A - sigma I) x_v for v = 0..nvec-1 (eq. (1.1)), canonical layout,
+ * device pointers, x and y each nvec*n complex128 (must not overlap).
+ * precision GDR_PREC_F64 or GDR_PREC_F32 (FP32 arithmetic with the op's
+ * link storage; input rounded to FP32, output widened). Errors: ARG, HIP. */
+int gdr_op_apply(gdr_op op, gdr_c64 sigma, const gdr_c64* x, gdr_c64* y, int nvec,
+                 int precision);
+
+/* Test hook: the even-odd index of every lexicographic site
+ * (eo = parity*V/2 + lex/2, lex = x + Lx(y + Ly(z + Lz t))), the neighbour
+ * table nbr[eo][d] in even-odd positions for hops d = +x,+y,+z,+t,-x,-y,-z,-t
+ * and sign[eo][d] = -1 where the hop crosses the time boundary. Host buffers
+ * of V, 8V and 8V entries, computed on the device. Errors: ARG, HIP. */
+int gdr_op_tables(gdr_op op, int32_t* eo_of_lex, int32_t* nbr, int8_t* sign);
+
+/* ------------------------------------------------------------ parameters */
+
+typedef struct {
+    int m_dr;          /* GMRES-DR(m, k) subspace size for the first RHS (Sec. 2.2), m <= 64 */
+    int k;             /* number of deflated harmonic Ritz vectors, 0 <= k < m_dr */
+    int m_proj;        /* GMRES(m)-Proj(k) cycle length for later RHS (Sec. 2.3), k < m_proj <= 64 */
+    double tol;        /* relative residual ||b - (A - sigma_i) x_i|| / ||b|| per (shift, RHS) */
+    double tol_extra;  /* tolerance of the extra right-hand side v_{k+1} (Sec. 4, Example 6);
+                          <= 0 selects sqrt(tol) */
+    int max_cycles;    /* cap on restart cycles per phase */
+    int precision;     /* GDR_PREC_F64 or GDR_PREC_MIXED */
+    int batch;         /* 1: later RHS run as one batch (one matvec launch per step) */
+    int related_rhs;   /* 1: project over earlier solutions first (Sec. 5, eq. (5.2)) */
+    int max_refine;    /* mixed precision: cap on refinement rounds of the cleanup */
+} gdr_params;
+
+/* Fill defaults: m_dr 40, k 15, m_proj 40, tol 1e-8, tol_extra sqrt(tol),
+ * max_cycles 1000, FP64, batch 1, related 0, max_refine 8. */
+void gdr_params_default(gdr_params* p);
+
+typedef struct {
+    int cycles_dr, cycles_extra, cycles_proj, cycles_cleanup;
+    int64_t mvp_dr;      /* operator applications of the GMRES-DR-Sh phase */
+    int64_t mvp_extra;   /* ... of the extra right-hand side */
+    int64_t mvp_proj;    /* ... of the later right-hand sides (sum over RHS) */
+    int64_t mvp_fp64;    /* FP64 true-residual applications (correction, replacement, checks) */
+    int64_t mvp_cleanup; /* ... of the mixed-precision cleanup solves */
+    double t_total;      /* seconds */
+    double t_phase[8];   /* seconds: 0 DR, 1 extra, 2 proj, 3 correction, 4 cleanup, 5 verify */
+    double* resid;       /* caller host array [nrhs][ns] or NULL: true FP64 relative residuals */
+    double* hist;        /* caller host array [hist_cap][5] or NULL: per cycle
+                            (phase, cycle, mvps, ||r_1||/||b||, max_i |beta_i| ||r_1||/||b||);
+                            phase 0 DR, 1 extra, 2+j later RHS j (max over the batch) */
+    int hist_cap, hist_len;
+    gdr_c64* theta;      /* caller host array [theta_cap] or NULL: the k harmonic Ritz values
+                            kept at every GMRES-DR restart, in selection order */
+    int theta_cap, theta_len;
+} gdr_stats;
+
+/* ---------------------------------------------------------------- solvers */
+
+/* First right-hand side by GMRES-DR(m_dr, k)-Sh (Sec. 3). sigma: host array
+ * of ns shifts, sigma[0] the base (should be the slowest to converge,
+ * Sec. 3, Example 3). b: device n-vector. x: device ns*n output (zero
+ * initial guess, Sec. 5). If defl_out is not NULL it receives the deflation
+ * pair (V_{k+1}, H_bar_k) (eq. (2.9)), owned by the caller until
+ * gdr_defl_destroy. Errors: ARG, OOM, HIP, BREAKDOWN; NOT_CONVERGED. */
+int gdr_solve_dr_sh(gdr_op op, int ns, const gdr_c64* sigma, const gdr_c64* b, gdr_c64* x,
+                    const gdr_params* p, gdr_stats* st, gdr_defl* defl_out);
+
+/* Right-hand sides B (device, nrhs*n) by GMRES(m_proj)-Proj(k)-Sh with the
+ * correction (Sec. 4). X: device nrhs*ns*n output. On first use with a
+ * shift list the extra right-hand side v_{k+1} is solved and its solutions
+ * s_i cached in defl; a different shift list recomputes them.
+ * Errors: ARG, STATE (defl from another operator), OOM, HIP, BREAKDOWN. */
+int gdr_solve_proj_sh(gdr_op op, gdr_defl defl, int ns, const gdr_c64* sigma, int nrhs,
+                      const gdr_c64* B, gdr_c64* X, const gdr_params* p, gdr_stats* st);
+
+/* Whole problem in the paper's order of use (Sec. 4): RHS 0 by GMRES-DR-Sh,
+ * then the extra RHS, then RHS 1..nrhs-1 by GMRES-Proj-Sh and correction;
+ * mixed precision adds an FP64-refined cleanup. X: device nrhs*ns*n. */
+int gdr_solve(gdr_op op, int ns, const gdr_c64* sigma, int nrhs, const gdr_c64* B,
+              gdr_c64* X, const gdr_params* p, gdr_stats* st);
+
+/* ------------------------------------------------------- deflation handle */
+
+/* Number k of deflation vectors (V holds k+1 columns). */
+int gdr_defl_k(gdr_defl d);
+/* Copy out V_{k+1} (device, (k+1)*n canonical complex128) and H_bar_k (host,
+ * (k+1) x k, column-major complex128); either pointer may be NULL. */
+int gdr_defl_export(gdr_defl d, gdr_c64* V, gdr_c64* Hbar);
+/* Build a handle from an exported pair (same layouts) for operator op;
+ * precision selects the basis storage (F64 or MIXED = FP32). */
+int gdr_defl_import(gdr_op op, int k, const gdr_c64* V, const gdr_c64* Hbar, int precision,
+                    gdr_defl* out);
+void gdr_defl_destroy(gdr_defl d);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GDR_H */

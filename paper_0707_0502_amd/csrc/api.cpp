@@ -1,0 +1,427 @@
+// The C-ABI of include/gdr.h: argument checks, canonical <-> internal layout
+// conversion at the boundary, and error reporting.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "engine.h"
+
+using namespace gdr;
+
+namespace {
+
+int fail(gdr_ctx_s* c, int code, const std::string& msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+struct Timer {
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+    double sec() const {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+};
+
+bool check_params(gdr_ctx_s* c, const gdr_params* p, int ns, bool need_dr) {
+    if (!p) {
+        c->err = "params is NULL";
+        return false;
+    }
+    if (ns < 1 || ns > MAXNS) {
+        c->err = "ns must be in 1..16";
+        return false;
+    }
+    if (need_dr && !(p->m_dr >= 1 && p->m_dr <= MAXM && p->k >= 0 && p->k < p->m_dr)) {
+        c->err = "need 0 <= k < m_dr <= 64";
+        return false;
+    }
+    if (!(p->m_proj >= 1 && p->m_proj <= MAXM)) {
+        c->err = "need 1 <= m_proj <= 64";
+        return false;
+    }
+    if (!(p->tol > 0) || p->max_cycles < 1 || p->max_refine < 0) {
+        c->err = "need tol > 0, max_cycles >= 1, max_refine >= 0";
+        return false;
+    }
+    if (p->precision != GDR_PREC_F64 && p->precision != GDR_PREC_MIXED) {
+        c->err = "precision must be GDR_PREC_F64 or GDR_PREC_MIXED";
+        return false;
+    }
+    return true;
+}
+
+void stats_reset(gdr_stats* st) {
+    if (!st) return;
+    st->cycles_dr = st->cycles_extra = st->cycles_proj = st->cycles_cleanup = 0;
+    st->mvp_dr = st->mvp_extra = st->mvp_proj = st->mvp_fp64 = st->mvp_cleanup = 0;
+    st->t_total = 0;
+    for (double& t : st->t_phase) t = 0;
+    st->hist_len = 0;
+    st->theta_len = 0;
+}
+
+}  // namespace
+
+#define API_TRY(c) try {
+#define API_CATCH(c)                                                \
+    }                                                               \
+    catch (const GdrError& e) {                                     \
+        (void)hipStreamSynchronize((c)->st);                        \
+        return fail((c), e.code, e.what());                         \
+    }                                                               \
+    catch (const std::exception& e) {                               \
+        return fail((c), GDR_ERR_HIP, e.what());                    \
+    }
+
+extern "C" {
+
+int gdr_ctx_create(int device, void* hip_stream, gdr_ctx* out) {
+    if (!out) return GDR_ERR_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess) return GDR_ERR_HIP;
+    if (device < 0 || device >= ndev) return GDR_ERR_ARG;
+    if (hipSetDevice(device) != hipSuccess) return GDR_ERR_HIP;
+    gdr_ctx_s* c = new gdr_ctx_s;
+    c->device = device;
+    c->st = (hipStream_t)hip_stream;
+    *out = c;
+    return GDR_OK;
+}
+
+void gdr_ctx_destroy(gdr_ctx c) { delete c; }
+
+const char* gdr_last_error(gdr_ctx c) { return c ? c->err.c_str() : "null context"; }
+
+void gdr_params_default(gdr_params* p) {
+    if (!p) return;
+    p->m_dr = 40;
+    p->k = 15;
+    p->m_proj = 40;
+    p->tol = 1e-8;
+    p->tol_extra = 0;
+    p->max_cycles = 1000;
+    p->precision = GDR_PREC_F64;
+    p->batch = 1;
+    p->related_rhs = 0;
+    p->max_refine = 8;
+}
+
+int gdr_wilson_create(gdr_ctx c, const int dims[4], const int bc[4], double kappa,
+                      const gdr_c64* links, int links_on_device, int link_storage, gdr_op* out) {
+    if (!c) return GDR_ERR_ARG;
+    if (!dims || !bc || !links || !out) return fail(c, GDR_ERR_ARG, "null argument");
+    *out = nullptr;
+    for (int mu = 0; mu < 4; ++mu) {
+        if (dims[mu] < 2 || dims[mu] % 2) return fail(c, GDR_ERR_ARG, "lattice extents must be even and >= 2");
+        if (bc[mu] != 1 && bc[mu] != -1) return fail(c, GDR_ERR_ARG, "bc must be +1 or -1");
+    }
+    if (link_storage < GDR_LINKS_F64 || link_storage > GDR_LINKS_F16)
+        return fail(c, GDR_ERR_ARG, "link_storage must be F64, F32 or F16");
+    if (!std::isfinite(kappa)) return fail(c, GDR_ERR_ARG, "kappa not finite");
+    const int64_t vol = (int64_t)dims[0] * dims[1] * dims[2] * dims[3];
+    if (vol > (int64_t)1 << 30) return fail(c, GDR_ERR_ARG, "lattice too large");
+    gdr_op_s* op = new gdr_op_s;
+    API_TRY(c)
+    HIPCHK(hipSetDevice(c->device));
+    op->ctx = c;
+    for (int mu = 0; mu < 4; ++mu) {
+        op->g.L[mu] = dims[mu];
+        op->bc[mu] = bc[mu];
+    }
+    op->g.vol = (int)vol;
+    op->g.vh = (int)(vol / 2);
+    op->g.hx = dims[0] / 2;
+    op->kappa = kappa;
+    op->n = 12 * vol;
+    op->lst = link_storage == GDR_LINKS_F64 ? GDR_LINKS_F32 : link_storage;
+    const size_t nl = (size_t)36 * vol;
+    HIPCHK(hipMalloc(&op->u64, nl * sizeof(double2)));
+    HIPCHK(hipMalloc(&op->ulo, nl * (op->lst == GDR_LINKS_F16 ? sizeof(__half2) : sizeof(float2))));
+    const double2* src = (const double2*)links;
+    double2* tmp = nullptr;
+    if (!links_on_device) {
+        HIPCHK(hipMalloc(&tmp, nl * sizeof(double2)));
+        HIPCHK(hipMemcpyAsync(tmp, links, nl * sizeof(double2), hipMemcpyHostToDevice, c->st));
+        src = tmp;
+    }
+    pack_links(src, op->u64, GDR_LINKS_F64, op->g, bc, c->st);
+    pack_links(src, op->ulo, op->lst, op->g, bc, c->st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->st));
+    if (tmp) (void)hipFree(tmp);
+    *out = op;
+    return GDR_OK;
+    }
+    catch (const GdrError& e) {
+        if (op->u64) (void)hipFree(op->u64);
+        if (op->ulo) (void)hipFree(op->ulo);
+        delete op;
+        return fail(c, e.code, e.what());
+    }
+}
+
+void gdr_op_destroy(gdr_op op) {
+    if (!op) return;
+    if (op->u64) (void)hipFree(op->u64);
+    if (op->ulo) (void)hipFree(op->ulo);
+    delete op;
+}
+
+int64_t gdr_op_size(gdr_op op) { return op ? op->n : 0; }
+
+int gdr_op_apply(gdr_op op, gdr_c64 sigma, const gdr_c64* x, gdr_c64* y, int nvec, int precision) {
+    if (!op) return GDR_ERR_ARG;
+    gdr_ctx_s* c = op->ctx;
+    if (!x || !y || nvec < 0) return fail(c, GDR_ERR_ARG, "null vector or negative nvec");
+    if (precision != GDR_PREC_F64 && precision != GDR_PREC_F32)
+        return fail(c, GDR_ERR_ARG, "precision must be F64 or F32");
+    if (nvec == 0) return GDR_OK;
+    API_TRY(c)
+    HIPCHK(hipSetDevice(c->device));
+    const int64_t n = op->n;
+    DMem mem;
+    const int chunk = std::min(nvec, DSLASH_MAXV);
+    DiagList dl{};
+    for (int v = 0; v < DSLASH_MAXV; ++v) {
+        dl.d[v] = make_double2(1.0 - sigma.re, -sigma.im);
+        dl.alpha[v] = 1;
+    }
+    if (precision == GDR_PREC_F64) {
+        double2* a = mem.get<double2>((size_t)chunk * n);
+        double2* b = mem.get<double2>((size_t)chunk * n);
+        for (int v0 = 0; v0 < nvec; v0 += chunk) {
+            const int nb = std::min(chunk, nvec - v0);
+            pack_spinor<double>((const double2*)x + v0 * n, a, n, op->g, nb, c->st);
+            dslash<double>(a, n, b, n, nullptr, 0, op->u64, GDR_LINKS_F64, op->g, op->kappa, dl, nb,
+                           c->st);
+            unpack_spinor<double>(b, n, (double2*)y + v0 * n, op->g, nb, c->st);
+        }
+    } else {
+        float2* a = mem.get<float2>((size_t)chunk * n);
+        float2* b = mem.get<float2>((size_t)chunk * n);
+        for (int v0 = 0; v0 < nvec; v0 += chunk) {
+            const int nb = std::min(chunk, nvec - v0);
+            pack_spinor<float>((const double2*)x + v0 * n, a, n, op->g, nb, c->st);
+            dslash<float>(a, n, b, n, nullptr, 0, op->ulo, op->lst, op->g, op->kappa, dl, nb, c->st);
+            unpack_spinor<float>(b, n, (double2*)y + v0 * n, op->g, nb, c->st);
+        }
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->st));
+    return GDR_OK;
+    API_CATCH(c)
+}
+
+int gdr_op_tables(gdr_op op, int32_t* eo_of_lex, int32_t* nbr, int8_t* sign) {
+    if (!op) return GDR_ERR_ARG;
+    gdr_ctx_s* c = op->ctx;
+    if (!eo_of_lex || !nbr || !sign) return fail(c, GDR_ERR_ARG, "null table buffer");
+    API_TRY(c)
+    HIPCHK(hipSetDevice(c->device));
+    DMem mem;
+    const int64_t vol = op->g.vol;
+    int32_t* e = mem.get<int32_t>(vol);
+    int32_t* nb = mem.get<int32_t>(8 * vol);
+    int8_t* sg = mem.get<int8_t>(8 * vol);
+    build_tables(e, nb, sg, op->g, op->bc[3], c->st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(eo_of_lex, e, vol * sizeof(int32_t), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipMemcpyAsync(nbr, nb, 8 * vol * sizeof(int32_t), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipMemcpyAsync(sign, sg, 8 * vol, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    return GDR_OK;
+    API_CATCH(c)
+}
+
+static void finish_stats(gdr_op op, gdr_stats* st, int ns, const double2* sig, int nrhs,
+                         const double2* Beo, const double2* Xeo, const Timer& t, double t_verify0) {
+    if (!st) return;
+    if (st->resid) {
+        Timer tv;
+        std::vector<double> r;
+        true_residuals(op, ns, sig, nrhs, Beo, Xeo, r);
+        std::memcpy(st->resid, r.data(), r.size() * sizeof(double));
+        st->t_phase[5] += tv.sec();
+        st->mvp_fp64 += (int64_t)ns * nrhs;
+    }
+    (void)t_verify0;
+    st->t_total = t.sec();
+}
+
+int gdr_solve_dr_sh(gdr_op op, int ns, const gdr_c64* sigma, const gdr_c64* b, gdr_c64* x,
+                    const gdr_params* p, gdr_stats* st, gdr_defl* defl_out) {
+    if (!op) return GDR_ERR_ARG;
+    gdr_ctx_s* c = op->ctx;
+    if (!sigma || !b || !x) return fail(c, GDR_ERR_ARG, "null argument");
+    if (defl_out) *defl_out = nullptr;
+    if (!check_params(c, p, ns, true)) return GDR_ERR_ARG;
+    stats_reset(st);
+    API_TRY(c)
+    HIPCHK(hipSetDevice(c->device));
+    Timer t;
+    const int64_t n = op->n;
+    DMem mem;
+    double2* beo = mem.get<double2>(n);
+    double2* Xeo = mem.get<double2>((size_t)ns * n);
+    pack_spinor<double>((const double2*)b, beo, n, op->g, 1, c->st);
+    Stats S{st};
+    gdr_defl_s* d = nullptr;
+    bool conv = false;
+    Timer tdr;
+    int rc = solve_dr_sh(op, ns, (const double2*)sigma, beo, Xeo, *p, S, &d, &conv);
+    if (st) st->t_phase[0] += tdr.sec();
+    if (p->precision == GDR_PREC_MIXED) {
+        Timer tc;
+        rc = cleanup(op, d, ns, (const double2*)sigma, 1, beo, Xeo, *p, S);
+        if (st) st->t_phase[4] += tc.sec();
+    }
+    finish_stats(op, st, ns, (const double2*)sigma, 1, beo, Xeo, t, 0);
+    unpack_spinor<double>(Xeo, n, (double2*)x, op->g, ns, c->st);
+    HIPCHK(hipStreamSynchronize(c->st));
+    if (st) st->t_total = t.sec();
+    if (defl_out) *defl_out = d;
+    else delete d;
+    return rc;
+    API_CATCH(c)
+}
+
+int gdr_solve_proj_sh(gdr_op op, gdr_defl defl, int ns, const gdr_c64* sigma, int nrhs,
+                      const gdr_c64* B, gdr_c64* X, const gdr_params* p, gdr_stats* st) {
+    if (!op) return GDR_ERR_ARG;
+    gdr_ctx_s* c = op->ctx;
+    if (!defl || !sigma || !B || !X || nrhs < 1) return fail(c, GDR_ERR_ARG, "null argument or nrhs < 1");
+    if (defl->op != op) return fail(c, GDR_ERR_STATE, "deflation handle belongs to another operator");
+    if (!check_params(c, p, ns, false)) return GDR_ERR_ARG;
+    stats_reset(st);
+    API_TRY(c)
+    HIPCHK(hipSetDevice(c->device));
+    Timer t;
+    const int64_t n = op->n;
+    DMem mem;
+    double2* Beo = mem.get<double2>((size_t)nrhs * n);
+    double2* Xeo = mem.get<double2>((size_t)nrhs * ns * n);
+    pack_spinor<double>((const double2*)B, Beo, n, op->g, nrhs, c->st);
+    Stats S{st};
+    int rc = solve_proj_batch(op, defl, ns, (const double2*)sigma, nrhs, Beo, Xeo, *p, S);
+    if (p->precision == GDR_PREC_MIXED) {
+        Timer tc;
+        rc = cleanup(op, defl, ns, (const double2*)sigma, nrhs, Beo, Xeo, *p, S);
+        if (st) st->t_phase[4] += tc.sec();
+    }
+    finish_stats(op, st, ns, (const double2*)sigma, nrhs, Beo, Xeo, t, 0);
+    unpack_spinor<double>(Xeo, n, (double2*)X, op->g, nrhs * ns, c->st);
+    HIPCHK(hipStreamSynchronize(c->st));
+    if (st) st->t_total = t.sec();
+    return rc;
+    API_CATCH(c)
+}
+
+int gdr_solve(gdr_op op, int ns, const gdr_c64* sigma, int nrhs, const gdr_c64* B, gdr_c64* X,
+              const gdr_params* p, gdr_stats* st) {
+    if (!op) return GDR_ERR_ARG;
+    gdr_ctx_s* c = op->ctx;
+    if (!sigma || !B || !X || nrhs < 1) return fail(c, GDR_ERR_ARG, "null argument or nrhs < 1");
+    if (!check_params(c, p, ns, true)) return GDR_ERR_ARG;
+    stats_reset(st);
+    API_TRY(c)
+    HIPCHK(hipSetDevice(c->device));
+    Timer t;
+    const int64_t n = op->n;
+    DMem mem;
+    double2* Beo = mem.get<double2>((size_t)nrhs * n);
+    double2* Xeo = mem.get<double2>((size_t)nrhs * ns * n);
+    pack_spinor<double>((const double2*)B, Beo, n, op->g, nrhs, c->st);
+    Stats S{st};
+    gdr_defl_s* d = nullptr;
+    bool conv = false;
+    Timer tdr;
+    int rc = solve_dr_sh(op, ns, (const double2*)sigma, Beo, Xeo, *p, S, &d, &conv);
+    HIPCHK(hipStreamSynchronize(c->st));
+    if (st) st->t_phase[0] += tdr.sec();
+    struct Guard {
+        gdr_defl_s* d;
+        ~Guard() { delete d; }
+    } guard{d};
+    if (nrhs > 1) {
+        if (!d) throw GdrError(GDR_ERR_BREAKDOWN, "first solve ended in a lucky breakdown: no deflation space");
+        int rc2 = solve_proj_batch(op, d, ns, (const double2*)sigma, nrhs - 1, Beo + n,
+                                   Xeo + (int64_t)ns * n, *p, S);
+        if (rc2 != GDR_OK) rc = rc2;
+    }
+    if (p->precision == GDR_PREC_MIXED) {
+        Timer tc;
+        rc = cleanup(op, d, ns, (const double2*)sigma, nrhs, Beo, Xeo, *p, S);
+        if (st) st->t_phase[4] += tc.sec();
+    }
+    finish_stats(op, st, ns, (const double2*)sigma, nrhs, Beo, Xeo, t, 0);
+    unpack_spinor<double>(Xeo, n, (double2*)X, op->g, nrhs * ns, c->st);
+    HIPCHK(hipStreamSynchronize(c->st));
+    if (st) st->t_total = t.sec();
+    return rc;
+    API_CATCH(c)
+}
+
+int gdr_defl_k(gdr_defl d) { return d ? d->k : -1; }
+
+int gdr_defl_export(gdr_defl d, gdr_c64* V, gdr_c64* Hbar) {
+    if (!d) return GDR_ERR_ARG;
+    gdr_op_s* op = d->op;
+    gdr_ctx_s* c = op->ctx;
+    API_TRY(c)
+    HIPCHK(hipSetDevice(c->device));
+    if (V) {
+        if (d->prec == GDR_PREC_MIXED)
+            unpack_spinor<float>((const float2*)d->V, op->n, (double2*)V, op->g, d->k + 1, c->st);
+        else
+            unpack_spinor<double>((const double2*)d->V, op->n, (double2*)V, op->g, d->k + 1, c->st);
+    }
+    if (Hbar && d->k > 0)
+        std::memcpy(Hbar, d->Hk_host.data(), d->Hk_host.size() * sizeof(double2));
+    HIPCHK(hipStreamSynchronize(c->st));
+    return GDR_OK;
+    API_CATCH(c)
+}
+
+int gdr_defl_import(gdr_op op, int k, const gdr_c64* V, const gdr_c64* Hbar, int precision,
+                    gdr_defl* out) {
+    if (!op) return GDR_ERR_ARG;
+    gdr_ctx_s* c = op->ctx;
+    if (!out || !V || (k > 0 && !Hbar) || k < 0 || k > MAXK)
+        return fail(c, GDR_ERR_ARG, "bad deflation import arguments");
+    if (precision != GDR_PREC_F64 && precision != GDR_PREC_MIXED)
+        return fail(c, GDR_ERR_ARG, "precision must be F64 or MIXED");
+    *out = nullptr;
+    gdr_defl_s* d = new gdr_defl_s;
+    API_TRY(c)
+    HIPCHK(hipSetDevice(c->device));
+    d->op = op;
+    d->k = k;
+    d->prec = precision;
+    const int64_t n = op->n;
+    if (precision == GDR_PREC_MIXED) {
+        HIPCHK(hipMalloc(&d->V, (size_t)(k + 1) * n * sizeof(float2)));
+        pack_spinor<float>((const double2*)V, (float2*)d->V, n, op->g, k + 1, c->st);
+    } else {
+        HIPCHK(hipMalloc(&d->V, (size_t)(k + 1) * n * sizeof(double2)));
+        pack_spinor<double>((const double2*)V, (double2*)d->V, n, op->g, k + 1, c->st);
+    }
+    if (k > 0) {
+        d->Hk_host.assign((const double2*)Hbar, (const double2*)Hbar + (size_t)(k + 1) * k);
+        HIPCHK(hipMalloc(&d->Hk, (size_t)(k + 1) * k * sizeof(double2)));
+        HIPCHK(hipMemcpyAsync(d->Hk, d->Hk_host.data(), d->Hk_host.size() * sizeof(double2),
+                              hipMemcpyHostToDevice, c->st));
+    }
+    HIPCHK(hipStreamSynchronize(c->st));
+    *out = d;
+    return GDR_OK;
+    }
+    catch (const GdrError& e) {
+        delete d;
+        return fail(c, e.code, e.what());
+    }
+}
+
+void gdr_defl_destroy(gdr_defl d) { delete d; }
+
+}  // extern "C"

@@ -1,0 +1,829 @@
+// Solver drivers: GMRES-DR-Sh for the first right-hand side (Sec. 3), the
+// batched GMRES-Proj-Sh phase for the extra right-hand side v_{k+1} and the
+// later right-hand sides with the correction (Sec. 4), and the FP64-refined
+// cleanup of the mixed-precision path.
+//
+// Host code only orders kernels on the context stream and reads back one
+// small record per restart cycle (the shortcut residual norm, the new
+// beta_i, flags and the kept harmonic Ritz values).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <limits>
+
+#include "engine.h"
+
+gdr_defl_s::~gdr_defl_s() {
+    if (V) (void)hipFree(V);
+    if (Hk) (void)hipFree(Hk);
+    if (S) (void)hipFree(S);
+}
+
+namespace gdr {
+
+static inline double2 z(double r, double i = 0) { return make_double2(r, i); }
+static inline double zabs(double2 a) { return std::hypot(a.x, a.y); }
+
+template <typename T>
+static const void* links_for(gdr_op_s* op) {
+    return std::is_same<T, double>::value ? (const void*)op->u64 : op->ulo;
+}
+template <typename T>
+static int lst_for(gdr_op_s* op) {
+    return std::is_same<T, double>::value ? GDR_LINKS_F64 : op->lst;
+}
+
+double vec_norm(gdr_op_s* op, const double2* x) {
+    DMem mem;
+    hipStream_t st = op->ctx->st;
+    const int nblk = cgs_nblk(op->n);
+    double2* part = mem.get<double2>(nblk);
+    double2* out = mem.get<double2>(1);
+    cgs_pass<double, double>(CGS_DOT, nullptr, 0, 0, 0, x, 0, nullptr, 0, nullptr, 0, part, nblk,
+                             op->n, 1, st);
+    reduce_cols(part, nblk, 1, out, 1, nullptr, 0, 1, st);
+    double2 h;
+    HIPCHK(hipMemcpyAsync(&h, out, sizeof(h), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return std::sqrt(h.x);
+}
+
+// ---------------------------------------------------------------------------
+// Batched Arnoldi step (eq. (2.2)) with CGS2: one operator launch and three
+// sweeps over each member's basis per step.
+template <typename T>
+struct Arnoldi {
+    using C = typename CT<T>::t;
+    gdr_op_s* op = nullptr;
+    hipStream_t st = nullptr;
+    int m = 0, nmem = 0;
+    int64_t n = 0;
+    C* V = nullptr;
+    int64_t vms = 0;
+    C* w = nullptr;
+    double2* wd = nullptr;
+    double2* H = nullptr;
+    int64_t hms = 0;
+    double2* h2 = nullptr;
+    double* inv = nullptr;
+    int* brk = nullptr;
+    double2* partial = nullptr;
+    int nblk = 0;
+    DiagList dl{};
+
+    void init(DMem& mem, gdr_op_s* op_, int m_, int nmem_, C* Vbuf, int64_t vms_) {
+        op = op_;
+        st = op->ctx->st;
+        m = m_;
+        nmem = nmem_;
+        n = op->n;
+        V = Vbuf;
+        vms = vms_;
+        w = mem.get<C>(n * nmem);
+        wd = mem.get<double2>(n * nmem);
+        hms = (int64_t)(m + 1) * m;
+        H = mem.get<double2>(hms * nmem);
+        h2 = mem.get<double2>(80 * nmem);
+        inv = mem.get<double>(nmem);
+        brk = mem.get<int>(nmem);
+        nblk = cgs_nblk(n);
+        partial = mem.get<double2>((size_t)80 * nblk * nmem);
+        for (int v = 0; v < DSLASH_MAXV; ++v) {
+            dl.d[v] = z(1);
+            dl.alpha[v] = 1;
+        }
+    }
+
+    void step(int j, const int* act) {
+        for (int b0 = 0; b0 < nmem; b0 += DSLASH_MAXV) {
+            const int nb = std::min(DSLASH_MAXV, nmem - b0);
+            dslash<T>(V + b0 * vms + (int64_t)j * n, vms, w + b0 * n, n, nullptr, 0,
+                      links_for<T>(op), lst_for<T>(op), op->g, op->kappa, dl, nb, st,
+                      act ? act + b0 : nullptr);
+        }
+        double2* Hj = H + (int64_t)j * (m + 1);
+        cgs_pass<T, T>(CGS_DOT, V, n, vms, j + 1, w, n, nullptr, 0, nullptr, 0, partial, nblk, n,
+                       nmem, st, act);
+        reduce_cols(partial, nblk, j + 2, Hj, hms, nullptr, 0, nmem, st, act);
+        cgs_pass<T, T>(CGS_UPDATE_DOT, V, n, vms, j + 1, w, n, wd, n, Hj, hms, partial, nblk, n,
+                       nmem, st, act);
+        reduce_cols(partial, nblk, j + 1, h2, 80, Hj, hms, nmem, st, act);
+        cgs_pass<T, T>(CGS_UPDATE_NORM, V, n, vms, j + 1, (const C*)nullptr, 0, wd, n, h2, 80,
+                       partial, nblk, n, nmem, st, act);
+        norm_finish(partial, nblk, H, m + 1, hms, j, Hj + j + 1, hms, inv, brk, 1e-14, nmem, st,
+                    act);
+        scale_store<T>(wd, n, inv, V + (int64_t)(j + 1) * n, vms, n, nmem, st, act);
+    }
+};
+
+// Orthonormalise column k of Vb against columns 0..k-1 (CGS2) in place.
+template <typename T>
+static void orth_column(gdr_op_s* op, typename CT<T>::t* Vb, int k, double2* wd, double2* partial,
+                        int nblk, double2* tH, double* tinv, int* tbrk) {
+    using C = typename CT<T>::t;
+    hipStream_t st = op->ctx->st;
+    const int64_t n = op->n;
+    C* col = Vb + (int64_t)k * n;
+    fill_int(tbrk, -1, 1, st);
+    cgs_pass<T, T>(CGS_DOT, Vb, n, 0, k, col, 0, nullptr, 0, nullptr, 0, partial, nblk, n, 1, st);
+    reduce_cols(partial, nblk, k + 1, tH, 0, nullptr, 0, 1, st);   // tH[k] = ||col||^2
+    if (k > 0) {
+        cgs_pass<T, T>(CGS_UPDATE_DOT, Vb, n, 0, k, col, 0, wd, 0, tH, 0, partial, nblk, n, 1, st);
+        reduce_cols(partial, nblk, k, tH + 80, 0, nullptr, 0, 1, st);
+    } else {
+        cgs_pass<T, T>(CGS_UPDATE, Vb, n, 0, 0, col, 0, wd, 0, tH, 0, partial, nblk, n, 1, st);
+    }
+    cgs_pass<T, T>(CGS_UPDATE_NORM, Vb, n, 0, k, (const C*)nullptr, 0, wd, 0, tH + 80, 0, partial,
+                   nblk, n, 1, st);
+    norm_finish(partial, nblk, tH + 160, 0, 0, 0, tH + k, 0, tinv, tbrk, 0.0, 1, st);
+    scale_store<T>(wd, 0, tinv, col, 0, n, 1, st);
+}
+
+// ---------------------------------------------------------------------------
+// GMRES-DR(m,k)-Sh on one right-hand side (algorithm GMRES-DR-Sh, Sec. 3)
+template <typename T>
+static int dr_run(gdr_op_s* op, int ns, const double2* sig_h, const double2* b_eo, double2* X,
+                  const gdr_params& p, Stats& S, gdr_defl_s** defl_out, bool* conv_out) {
+    using C = typename CT<T>::t;
+    constexpr bool mixed = std::is_same<T, float>::value;
+    hipStream_t st = op->ctx->st;
+    const int64_t n = op->n;
+    const int m = p.m_dr, k = p.k;
+    DMem mem;
+    C* Va = mem.get<C>((size_t)(m + 1) * n);
+    C* Vb = mem.get<C>((size_t)(m + 1) * n);
+    Arnoldi<T> A;
+    A.init(mem, op, m, 1, Va, 0);
+    double2* Hn = mem.get<double2>((size_t)(m + 1) * m);
+    double2* c0 = mem.get<double2>(m + 1);
+    double2* c1 = mem.get<double2>(m + 1);
+    double2* coef = mem.get<double2>((size_t)(m + 1) * (ns + 1));
+    double2* P = mem.get<double2>((size_t)(m + 1) * (k + 1));
+    CycleOut* outs = mem.get<CycleOut>(2);
+    double2* sig = mem.get<double2>(ns);
+    double2* tH = mem.get<double2>(256);
+    double* tinv = mem.get<double>(2);
+    int* tbrk = mem.get<int>(2);
+    double* dsc = mem.get<double>(2);
+    double2* rtrue = mixed ? mem.get<double2>(n) : nullptr;
+    HIPCHK(hipMemcpyAsync(sig, sig_h, ns * sizeof(double2), hipMemcpyHostToDevice, st));
+
+    const double bnorm = vec_norm(op, b_eo);
+    HIPCHK(hipMemsetAsync(X, 0, (size_t)ns * n * sizeof(double2), st));
+    if (!(bnorm > 0)) {
+        *conv_out = true;
+        if (defl_out) *defl_out = nullptr;
+        HIPCHK(hipStreamSynchronize(st));
+        return GDR_OK;
+    }
+    CycleOut init{};
+    init.snorm = bnorm;
+    for (int i = 0; i < MAXNS; ++i) init.beta[i] = z(1);
+    HIPCHK(hipMemcpyAsync(&outs[0], &init, sizeof(CycleOut), hipMemcpyHostToDevice, st));
+    std::vector<double2> ch(m + 1, z(0));
+    ch[0] = z(bnorm);
+    HIPCHK(hipMemcpyAsync(c0, ch.data(), (m + 1) * sizeof(double2), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemsetAsync(Hn, 0, (size_t)(m + 1) * m * sizeof(double2), st));
+    HIPCHK(hipMemsetAsync(A.H, 0, (size_t)(m + 1) * m * sizeof(double2), st));
+    const double invb = 1.0 / bnorm;
+    HIPCHK(hipMemcpyAsync(dsc, &invb, sizeof(double), hipMemcpyHostToDevice, st));
+    convert_scale<T>(b_eo, 0, dsc, 0, Va, 0, n, 1, st);
+
+    int cur = 1, prv = 0;
+    C* Vc = Va;
+    C* Vn = Vb;
+    double2* Hc = A.H;
+    double2* Hx = Hn;
+    double2* cc = c0;
+    double2* cx = c1;
+    int j0 = 0, cycles = 0, brk = -1;
+    int64_t mvps = 0;
+    bool conv = false;
+    double best_true = std::numeric_limits<double>::infinity();
+    int stall = 0;
+    const unsigned allx = ns >= 32 ? 0xffffffffu : ((1u << ns) - 1u);
+    for (int cyc = 0; cyc < p.max_cycles; ++cyc) {
+        ++cycles;
+        A.V = Vc;
+        A.H = Hc;
+        fill_int(A.brk, -1, 1, st);
+        for (int j = j0; j < m; ++j) A.step(j, nullptr);
+        mvps += m - j0;
+        HIPCHK(hipMemsetAsync(&outs[cur].flags, 0, sizeof(int), st));
+        CycleArgs a{};
+        a.H = Hc;
+        a.c = cc;
+        a.sigma = sig;
+        a.beta = outs[prv].beta;
+        a.brk = A.brk;
+        a.coef = coef;
+        a.out = &outs[cur];
+        a.restart = 1;
+        a.k = k;
+        a.P = P;
+        a.Hnew = Hx;
+        a.cnew = cx;
+        a.m = m;
+        a.ns = ns;
+        cycle_small(a, 1, st);
+        vcombine<T>(Vc, n, 0, m, coef, m + 1, 0, ns, X, n, 0, allx, n, 1, st);
+        double rtn = 0;
+        if (mixed) {
+            DiagList dl{};
+            dl.d[0] = z(1.0 - sig_h[0].x, -sig_h[0].y);
+            dl.alpha[0] = -1;
+            dslash<double>(X, 0, rtrue, 0, b_eo, 0, op->u64, GDR_LINKS_F64, op->g, op->kappa, dl, 1,
+                           st);
+            if (S.st) S.st->mvp_fp64 += 1;
+        }
+        CycleOut o;
+        HIPCHK(hipMemcpyAsync(&o, &outs[cur], sizeof(CycleOut), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(&brk, A.brk, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (mixed) rtn = vec_norm(op, rtrue);
+        if (o.flags & 1) throw GdrError(GDR_ERR_BREAKDOWN, "GMRES-DR-Sh: singular shifted system ((Q^H s)_{m+1} = 0)");
+        if (o.flags & 2) throw GdrError(GDR_ERR_BREAKDOWN, "GMRES-DR-Sh: harmonic Ritz eigensolver did not converge");
+        const double r1 = (mixed ? rtn : o.snorm) / bnorm;
+        double bmax = 1;
+        for (int i = 1; i < ns; ++i) bmax = std::max(bmax, zabs(o.beta[i]));
+        const double rmax = r1 * bmax;
+        S.hist(0, cycles, mvps, o.snorm / bnorm, rmax);
+        conv = rmax <= p.tol || brk >= 0;
+        bool stop = conv;
+        if (mixed && !conv) {
+            // FP32 recursion has lost track of the true residual: leave the rest
+            // to the FP64-refined cleanup
+            const double gap = std::fabs(rtn - o.snorm) / rtn;
+            if (rtn < 0.9 * best_true) {
+                best_true = rtn;
+                stall = 0;
+            } else {
+                ++stall;
+            }
+            if (gap > 0.5 || stall >= 3) stop = true;
+        }
+        if (brk >= 0) break;   // lucky breakdown: solved exactly, no deflation space
+        S.theta(o.theta, k);
+        vrecombine<T>(Vc, n, m + 1, P, m + 1, k + 1, Vn, n, n, st);
+        orth_column<T>(op, Vn, k, A.wd, A.partial, A.nblk, tH, tinv, tbrk);
+        if (mixed) {
+            // residual replacement: coordinates of the FP64 true residual in V_{k+1}
+            cgs_pass<T, double>(CGS_DOT, Vn, n, 0, k + 1, rtrue, 0, nullptr, 0, nullptr, 0,
+                                A.partial, A.nblk, n, 1, st);
+            reduce_cols(A.partial, A.nblk, k + 2, tH, 0, nullptr, 0, 1, st);
+            HIPCHK(hipMemcpyAsync(cx, tH, (k + 1) * sizeof(double2), hipMemcpyDeviceToDevice, st));
+        }
+        if (stop) break;
+        std::swap(Vc, Vn);
+        std::swap(Hc, Hx);
+        std::swap(cc, cx);
+        std::swap(cur, prv);
+        j0 = k;
+    }
+    if (S.st) {
+        S.st->cycles_dr += cycles;
+        S.st->mvp_dr += mvps;
+    }
+    if (defl_out) {
+        *defl_out = nullptr;
+        if (brk < 0) {
+            gdr_defl_s* d = new gdr_defl_s;
+            d->op = op;
+            d->k = k;
+            d->prec = mixed ? GDR_PREC_MIXED : GDR_PREC_F64;
+            try {
+                HIPCHK(hipMalloc(&d->V, (size_t)(k + 1) * n * sizeof(C)));
+                HIPCHK(hipMemcpyAsync(d->V, Vn, (size_t)(k + 1) * n * sizeof(C),
+                                      hipMemcpyDeviceToDevice, st));
+                if (k > 0) {
+                    HIPCHK(hipMalloc(&d->Hk, (size_t)(k + 1) * k * sizeof(double2)));
+                    HIPCHK(hipMemcpy2DAsync(d->Hk, (k + 1) * sizeof(double2), Hx,
+                                            (m + 1) * sizeof(double2), (k + 1) * sizeof(double2),
+                                            k, hipMemcpyDeviceToDevice, st));
+                    d->Hk_host.resize((size_t)(k + 1) * k);
+                    HIPCHK(hipMemcpyAsync(d->Hk_host.data(), d->Hk,
+                                          (size_t)(k + 1) * k * sizeof(double2),
+                                          hipMemcpyDeviceToHost, st));
+                }
+                HIPCHK(hipStreamSynchronize(st));
+            } catch (...) {
+                delete d;
+                throw;
+            }
+            *defl_out = d;
+        }
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    *conv_out = conv;
+    return conv ? GDR_OK : GDR_NOT_CONVERGED;
+}
+
+int solve_dr_sh(gdr_op_s* op, int ns, const double2* sig, const double2* b_eo, double2* X_eo,
+                const gdr_params& p, Stats& S, gdr_defl_s** defl_out, bool* converged) {
+    if (p.precision == GDR_PREC_MIXED)
+        return dr_run<float>(op, ns, sig, b_eo, X_eo, p, S, defl_out, converged);
+    return dr_run<double>(op, ns, sig, b_eo, X_eo, p, S, defl_out, converged);
+}
+
+// ---------------------------------------------------------------------------
+// GMRES(m)-Proj(k)-Sh over a batch of members (Sec. 4, GMRES-Proj-Sh steps
+// 2-6). Member b solves (A - sig[b][i]) x_i = B[b] for i < ns; its state
+// block W[b] holds x_0 .. x_{ns-1} and the base residual r (FP64).
+struct ProjResult {
+    std::vector<int64_t> mvps;
+    std::vector<int> cycles;
+    std::vector<int> conv;
+    std::vector<double2> beta, gam;   // at the end, per member ns
+};
+
+template <typename T>
+static void proj_run(gdr_op_s* op, gdr_defl_s* defl, int nmem, int ns,
+                     const std::vector<double2>& sig_h, const double2* Bm, double2* W,
+                     const std::vector<double>& tol, const std::vector<double>& bnorm, int m,
+                     int max_cycles, Stats& S, const std::vector<int>& phase, ProjResult& R) {
+    using C = typename CT<T>::t;
+    constexpr bool mixed = std::is_same<T, float>::value;
+    hipStream_t st = op->ctx->st;
+    const int64_t n = op->n;
+    const int k = defl ? defl->k : 0;
+    const C* Vd = defl ? (const C*)defl->V : nullptr;
+    DMem mem;
+    const int64_t vms = (int64_t)(m + 1) * n;
+    const int64_t wms = (int64_t)(ns + 1) * n;
+    C* Vb = mem.get<C>((size_t)vms * nmem);
+    Arnoldi<T> A;
+    A.init(mem, op, m, nmem, Vb, vms);
+    double2* sig = mem.get<double2>((size_t)nmem * ns);
+    double2* Cb = mem.get<double2>((size_t)80 * nmem);
+    double2* cvec = mem.get<double2>((size_t)(m + 1) * nmem);
+    const int64_t cpms = (int64_t)(k + 1) * (ns + 1);
+    const int64_t ccms = (int64_t)(m + 1) * (ns + 1);
+    double2* coefP = mem.get<double2>((size_t)cpms * nmem);
+    double2* coefC = mem.get<double2>((size_t)ccms * nmem);
+    double2* gam = mem.get<double2>((size_t)ns * nmem);
+    double2* rn2 = mem.get<double2>((size_t)nmem);
+    CycleOut* outs = mem.get<CycleOut>((size_t)2 * nmem);
+    int* act = mem.get<int>(nmem);
+    int* pflags = mem.get<int>(nmem);
+    const int64_t bms = (int64_t)(sizeof(CycleOut) / sizeof(double2));
+    static_assert(sizeof(CycleOut) % sizeof(double2) == 0, "CycleOut layout");
+
+    HIPCHK(hipMemcpyAsync(sig, sig_h.data(), (size_t)nmem * ns * sizeof(double2),
+                          hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemsetAsync(W, 0, (size_t)wms * nmem * sizeof(double2), st));
+    copy_vec(Bm, n, W + (int64_t)ns * n, wms, n, nmem, st);   // r = b
+    std::vector<CycleOut> init(2 * nmem);
+    for (auto& o : init) {
+        o = CycleOut{};
+        for (int i = 0; i < MAXNS; ++i) o.beta[i] = z(1);
+    }
+    HIPCHK(hipMemcpyAsync(outs, init.data(), 2 * nmem * sizeof(CycleOut), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemsetAsync(gam, 0, (size_t)ns * nmem * sizeof(double2), st));
+    HIPCHK(hipMemsetAsync(pflags, 0, nmem * sizeof(int), st));
+    HIPCHK(hipMemsetAsync(A.H, 0, (size_t)A.hms * nmem * sizeof(double2), st));
+    std::vector<int> acth(nmem, 1);
+    HIPCHK(hipMemcpyAsync(act, acth.data(), nmem * sizeof(int), hipMemcpyHostToDevice, st));
+
+    R.mvps.assign(nmem, 0);
+    R.cycles.assign(nmem, 0);
+    R.conv.assign(nmem, 0);
+    R.beta.assign((size_t)nmem * ns, z(1));
+    R.gam.assign((size_t)nmem * ns, z(0));
+    const unsigned keep_all = (1u << (ns + 1)) - 1u;
+    const unsigned keep_x = (1u << ns) - 1u;
+    int cur = 1, prv = 0;
+    std::vector<CycleOut> oh(nmem);
+    std::vector<double2> rnh(nmem);
+    for (int cyc = 0; cyc < max_cycles; ++cyc) {
+        // ---- minres projection over V_k with v_{k+1} tracking
+        if (k > 0) {
+            cgs_pass<T, double>(CGS_DOT, Vd, n, 0, k + 1, W + (int64_t)ns * n, wms, nullptr, 0,
+                                nullptr, 0, A.partial, A.nblk, n, nmem, st, act);
+            reduce_cols(A.partial, A.nblk, k + 2, Cb, 80, nullptr, 0, nmem, st, act);
+            ProjArgs pa{};
+            pa.Hk = defl->Hk;
+            pa.k = k;
+            pa.C = Cb;
+            pa.c_ms = 80;
+            pa.sigma = sig;
+            pa.sig_ms = ns;
+            pa.beta = outs[prv * nmem].beta;
+            pa.beta_ms = bms;
+            pa.gam = gam;
+            pa.gam_ms = ns;
+            pa.coef = coefP;
+            pa.coef_ms = cpms;
+            pa.flags = pflags;
+            pa.ns = ns;
+            pa.act = act;
+            proj_small(pa, nmem, st);
+            vcombine<T>(Vd, n, 0, k + 1, coefP, k + 1, cpms, ns + 1, W, n, wms, keep_all, n, nmem,
+                        st, act);
+        }
+        // ---- one GMRES(m)-Sh cycle from r
+        cgs_pass<double, double>(CGS_DOT, nullptr, 0, 0, 0, W + (int64_t)ns * n, wms, nullptr, 0,
+                                 nullptr, 0, A.partial, A.nblk, n, nmem, st, act);
+        reduce_cols(A.partial, A.nblk, 1, rn2, 1, nullptr, 0, nmem, st, act);
+        start_cycle(rn2, 1, cvec, m + 1, m, A.inv, nmem, st, act);
+        convert_scale<T>(W + (int64_t)ns * n, wms, A.inv, 1, Vb, vms, n, nmem, st, act);
+        fill_int(A.brk, -1, nmem, st);
+        for (int j = 0; j < m; ++j) A.step(j, act);
+        HIPCHK(hipMemcpyAsync(outs + cur * nmem, init.data(), nmem * sizeof(CycleOut),
+                              hipMemcpyHostToDevice, st));
+        CycleArgs a{};
+        a.H = A.H;
+        a.h_ms = A.hms;
+        a.c = cvec;
+        a.c_ms = m + 1;
+        a.sigma = sig;
+        a.sig_ms = ns;
+        a.beta = outs[prv * nmem].beta;
+        a.beta_ms = bms;
+        a.brk = A.brk;
+        a.coef = coefC;
+        a.coef_ms = ccms;
+        a.out = outs + cur * nmem;
+        a.restart = 0;
+        a.k = 0;
+        a.m = m;
+        a.ns = ns;
+        a.act = act;
+        cycle_small(a, nmem, st);
+        // x_i += V_m d_i ; r = V_{m+1} s
+        vcombine<T>(Vb, n, vms, m + 1, coefC, m + 1, ccms, ns + 1, W, n, wms, keep_x, n, nmem, st,
+                    act);
+        if (mixed) {
+            // base residual replaced by the FP64 true residual of shift 1
+            for (int b0 = 0; b0 < nmem; b0 += DSLASH_MAXV) {
+                const int nb = std::min(DSLASH_MAXV, nmem - b0);
+                DiagList dl{};
+                for (int v = 0; v < nb; ++v) {
+                    const double2 s1 = sig_h[(size_t)(b0 + v) * ns];
+                    dl.d[v] = z(1.0 - s1.x, -s1.y);
+                    dl.alpha[v] = -1;
+                }
+                dslash<double>(W + b0 * wms, wms, W + b0 * wms + (int64_t)ns * n, wms,
+                               Bm + b0 * n, n, op->u64, GDR_LINKS_F64, op->g, op->kappa, dl, nb,
+                               st, act + b0);
+            }
+            cgs_pass<double, double>(CGS_DOT, nullptr, 0, 0, 0, W + (int64_t)ns * n, wms, nullptr,
+                                     0, nullptr, 0, A.partial, A.nblk, n, nmem, st, act);
+            reduce_cols(A.partial, A.nblk, 1, rn2, 1, nullptr, 0, nmem, st, act);
+            HIPCHK(hipMemcpyAsync(rnh.data(), rn2, nmem * sizeof(double2), hipMemcpyDeviceToHost, st));
+        }
+        HIPCHK(hipMemcpyAsync(oh.data(), outs + cur * nmem, nmem * sizeof(CycleOut),
+                              hipMemcpyDeviceToHost, st));
+        int pf_any = 0;
+        std::vector<int> pfl(nmem);
+        HIPCHK(hipMemcpyAsync(pfl.data(), pflags, nmem * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        int nact = 0;
+        double worst = 0, worst_r1 = 0;
+        int64_t step_mvps = 0;
+        for (int b = 0; b < nmem; ++b) {
+            if (!acth[b]) continue;
+            pf_any |= pfl[b];
+            if (oh[b].flags) pf_any |= 4;
+            R.mvps[b] += m;
+            step_mvps += m;
+            R.cycles[b] += 1;
+            const double rn = mixed ? std::sqrt(rnh[b].x) : oh[b].snorm;
+            double bmax = 1;
+            for (int i = 1; i < ns; ++i) bmax = std::max(bmax, zabs(oh[b].beta[i]));
+            const double r1 = rn / bnorm[b];
+            const double rmax = r1 * bmax;
+            worst = std::max(worst, rmax);
+            worst_r1 = std::max(worst_r1, r1);
+            for (int i = 0; i < ns; ++i) R.beta[(size_t)b * ns + i] = oh[b].beta[i];
+            if (rmax <= tol[b]) {
+                acth[b] = 0;
+                R.conv[b] = 1;
+            } else {
+                ++nact;
+            }
+        }
+        if (pf_any & 1) throw GdrError(GDR_ERR_BREAKDOWN, "GMRES-Proj-Sh: singular H_k - sigma_i I");
+        if (pf_any & 4) throw GdrError(GDR_ERR_BREAKDOWN, "GMRES-Proj-Sh: singular shifted system in a GMRES-Sh cycle");
+        // history: one record per distinct phase of the batch (max over its members)
+        {
+            std::vector<int> seen;
+            for (int b = 0; b < nmem; ++b) {
+                if (std::find(seen.begin(), seen.end(), phase[b]) != seen.end()) continue;
+                seen.push_back(phase[b]);
+                double w1 = 0, wm = 0;
+                int64_t mv = 0;
+                bool any = false;
+                for (int c = 0; c < nmem; ++c)
+                    if (phase[c] == phase[b] && R.cycles[c] == cyc + 1) {
+                        any = true;
+                        const double rn = mixed ? std::sqrt(rnh[c].x) : oh[c].snorm;
+                        double bmax = 1;
+                        for (int i = 1; i < ns; ++i) bmax = std::max(bmax, zabs(oh[c].beta[i]));
+                        w1 = std::max(w1, rn / bnorm[c]);
+                        wm = std::max(wm, bmax * rn / bnorm[c]);
+                        mv = std::max(mv, R.mvps[c]);
+                    }
+                if (any) S.hist(phase[b], cyc + 1, mv, w1, wm);
+            }
+        }
+        (void)worst;
+        (void)worst_r1;
+        (void)step_mvps;
+        HIPCHK(hipMemcpyAsync(act, acth.data(), nmem * sizeof(int), hipMemcpyHostToDevice, st));
+        std::swap(cur, prv);
+        if (nact == 0) break;
+    }
+    std::vector<double2> gh((size_t)nmem * ns);
+    HIPCHK(hipMemcpyAsync(gh.data(), gam, gh.size() * sizeof(double2), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    R.gam = gh;
+}
+
+// T -> FP64 copy of the defl's v_{k+1}
+template <typename T>
+static void vk1_to_f64(gdr_defl_s* d, double2* out) {
+    using C = typename CT<T>::t;
+    gdr_op_s* op = d->op;
+    DMem mem;
+    double2* one = mem.get<double2>(1);
+    const double2 o = z(1);
+    HIPCHK(hipMemcpyAsync(one, &o, sizeof(o), hipMemcpyHostToDevice, op->ctx->st));
+    vcombine<T>((const C*)d->V + (int64_t)d->k * op->n, op->n, 0, 1, one, 1, 0, 1, out, op->n, 0,
+                0u, op->n, 1, op->ctx->st);
+    HIPCHK(hipStreamSynchronize(op->ctx->st));
+}
+
+// gamma_hat_i = v_{k+1}^H (rhs - (A - sigma_i) x_i) for i = 1..ns-1 of one
+// member; returns host values (index i-1) and leaves nothing else changed.
+template <typename T>
+static std::vector<double2> vk1_dot_residuals(gdr_defl_s* d, int ns, const double2* sig_h,
+                                              const double2* xs, const double2* rhs,
+                                              double2* Rt, double2* part, int nblk, double2* g) {
+    using C = typename CT<T>::t;
+    gdr_op_s* op = d->op;
+    hipStream_t st = op->ctx->st;
+    const int64_t n = op->n;
+    DiagList dl{};
+    for (int i = 1; i < ns; ++i) {
+        dl.d[i - 1] = z(1.0 - sig_h[i].x, -sig_h[i].y);
+        dl.alpha[i - 1] = -1;
+    }
+    dslash<double>(xs + n, n, Rt, n, rhs, 0, op->u64, GDR_LINKS_F64, op->g, op->kappa, dl, ns - 1,
+                   st);
+    cgs_pass<T, double>(CGS_DOT, (const C*)d->V + (int64_t)d->k * n, n, 0, 1, Rt, n, nullptr, 0,
+                        nullptr, 0, part, nblk, n, ns - 1, st);
+    reduce_cols(part, nblk, 2, g, 2, nullptr, 0, ns - 1, st);
+    std::vector<double2> gh(2 * (ns - 1));
+    HIPCHK(hipMemcpyAsync(gh.data(), g, gh.size() * sizeof(double2), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    std::vector<double2> out(ns - 1);
+    for (int i = 0; i < ns - 1; ++i) out[i] = gh[2 * i];
+    return out;
+}
+
+template <typename T>
+static int proj_batch(gdr_op_s* op, gdr_defl_s* d, int ns, const double2* sig_h, int nrhs,
+                      const double2* B_eo, double2* X_eo, const gdr_params& p, Stats& S) {
+    hipStream_t st = op->ctx->st;
+    const int64_t n = op->n;
+    const int m = p.m_proj;
+    const double tol_extra = p.tol_extra > 0 ? p.tol_extra : std::sqrt(p.tol);
+    bool need_extra = ns > 1 && d->k > 0;
+    if (need_extra && d->S && (int)d->extra_sig.size() == ns) {
+        need_extra = false;
+        for (int i = 0; i < ns; ++i)
+            if (d->extra_sig[i].x != sig_h[i].x || d->extra_sig[i].y != sig_h[i].y) need_extra = true;
+    }
+    const int chunk = p.batch ? 16 : 1;
+    DMem mem;
+    const int nblk = cgs_nblk(n);
+    double2* Rt = mem.get<double2>((size_t)std::max(ns - 1, 1) * n);
+    double2* part = mem.get<double2>((size_t)2 * nblk * std::max(ns, 1));
+    double2* g = mem.get<double2>((size_t)2 * std::max(ns, 1));
+    double2* fac = mem.get<double2>(std::max(ns, 1));
+    std::vector<double2> sigl(sig_h, sig_h + ns);
+    bool all_conv = true;
+    // members: -1 = extra right-hand side, 0..nrhs-1 = B columns
+    std::vector<int> todo;
+    if (need_extra) todo.push_back(-1);
+    for (int j = 0; j < nrhs; ++j) todo.push_back(j);
+    size_t pos = 0;
+    while (pos < todo.size()) {
+        const int nmem = (int)std::min<size_t>(chunk, todo.size() - pos);
+        std::vector<int> ids(todo.begin() + pos, todo.begin() + pos + nmem);
+        pos += nmem;
+        DMem cm;
+        double2* Bm = cm.get<double2>((size_t)nmem * n);
+        double2* W = cm.get<double2>((size_t)nmem * (ns + 1) * n);
+        std::vector<double> tol(nmem), bnorm(nmem);
+        std::vector<int> phase(nmem);
+        std::vector<double2> sgm((size_t)nmem * ns);
+        for (int b = 0; b < nmem; ++b) {
+            if (ids[b] < 0) {
+                if (d->prec == GDR_PREC_MIXED) vk1_to_f64<float>(d, Bm + b * n);
+                else vk1_to_f64<double>(d, Bm + b * n);
+                tol[b] = tol_extra;
+                phase[b] = 1;
+            } else {
+                HIPCHK(hipMemcpyAsync(Bm + b * n, B_eo + (int64_t)ids[b] * n, n * sizeof(double2),
+                                      hipMemcpyDeviceToDevice, st));
+                tol[b] = p.tol;
+                phase[b] = 2 + ids[b];
+            }
+            bnorm[b] = vec_norm(op, Bm + b * n);
+            if (!(bnorm[b] > 0)) bnorm[b] = 1;
+            for (int i = 0; i < ns; ++i) sgm[(size_t)b * ns + i] = sig_h[i];
+        }
+        ProjResult R;
+        using clock = std::chrono::steady_clock;
+        auto t0 = clock::now();
+        if (d->prec == GDR_PREC_MIXED)
+            proj_run<float>(op, d, nmem, ns, sgm, Bm, W, tol, bnorm, m, p.max_cycles, S, phase, R);
+        else
+            proj_run<double>(op, d, nmem, ns, sgm, Bm, W, tol, bnorm, m, p.max_cycles, S, phase, R);
+        HIPCHK(hipStreamSynchronize(st));
+        auto t1 = clock::now();
+        if (S.st) S.st->t_phase[2] += std::chrono::duration<double>(t1 - t0).count();
+        const int64_t wms = (int64_t)(ns + 1) * n;
+        for (int b = 0; b < nmem; ++b) {
+            if (ids[b] < 0) {
+                if (S.st) {
+                    S.st->mvp_extra += R.mvps[b];
+                    S.st->cycles_extra += R.cycles[b];
+                }
+                d->mvp_extra = R.mvps[b];
+                d->cycles_extra = R.cycles[b];
+            } else if (S.st) {
+                S.st->mvp_proj += R.mvps[b];
+                S.st->cycles_proj += R.cycles[b];
+            }
+            if (!R.conv[b]) all_conv = false;
+        }
+        auto t2 = clock::now();
+        // ---- extra right-hand side correction: s_i = s~_i / (1 - gamma_i)
+        for (int b = 0; b < nmem; ++b) {
+            if (ids[b] >= 0) continue;
+            double2* xs = W + b * wms;
+            auto gh = d->prec == GDR_PREC_MIXED
+                          ? vk1_dot_residuals<float>(d, ns, sig_h, xs, Bm + b * n, Rt, part, nblk, g)
+                          : vk1_dot_residuals<double>(d, ns, sig_h, xs, Bm + b * n, Rt, part, nblk, g);
+            if (S.st) S.st->mvp_fp64 += ns - 1;
+            std::vector<double2> f(ns, z(1));
+            for (int i = 1; i < ns; ++i) {
+                const double2 om = z(1.0 - gh[i - 1].x, -gh[i - 1].y);
+                const double den = om.x * om.x + om.y * om.y;
+                if (!(std::sqrt(den) > 1e-12))
+                    throw GdrError(GDR_ERR_BREAKDOWN, "extra right-hand side: 1 - gamma_i = 0");
+                f[i] = z(om.x / den, -om.y / den);
+            }
+            if (!d->S) HIPCHK(hipMalloc(&d->S, (size_t)ns * n * sizeof(double2)));
+            else if ((int)d->extra_sig.size() < ns) {
+                (void)hipFree(d->S);
+                d->S = nullptr;
+                HIPCHK(hipMalloc(&d->S, (size_t)ns * n * sizeof(double2)));
+            }
+            HIPCHK(hipMemcpyAsync(d->S, xs, (size_t)ns * n * sizeof(double2), hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpyAsync(fac, f.data(), ns * sizeof(double2), hipMemcpyHostToDevice, st));
+            scal_dev(d->S + n, n, fac + 1, n, ns - 1, st);
+            d->extra_sig = sigl;
+            HIPCHK(hipStreamSynchronize(st));
+        }
+        // ---- correction of every right-hand side: x_i += (v_{k+1}^H r_i) s_i
+        for (int b = 0; b < nmem; ++b) {
+            if (ids[b] < 0) continue;
+            double2* xs = W + b * wms;
+            if (ns > 1 && d->k > 0) {
+                auto gh = d->prec == GDR_PREC_MIXED
+                              ? vk1_dot_residuals<float>(d, ns, sig_h, xs, Bm + b * n, Rt, part, nblk, g)
+                              : vk1_dot_residuals<double>(d, ns, sig_h, xs, Bm + b * n, Rt, part, nblk, g);
+                if (S.st) S.st->mvp_fp64 += ns - 1;
+                HIPCHK(hipMemcpyAsync(fac, gh.data(), (ns - 1) * sizeof(double2), hipMemcpyHostToDevice, st));
+                axpy_dev(xs + n, n, d->S + n, n, fac, 1, n, ns - 1, st);
+            }
+            HIPCHK(hipMemcpyAsync(X_eo + (int64_t)ids[b] * ns * n, xs, (size_t)ns * n * sizeof(double2),
+                                  hipMemcpyDeviceToDevice, st));
+        }
+        HIPCHK(hipStreamSynchronize(st));
+        auto t3 = clock::now();
+        if (S.st) S.st->t_phase[3] += std::chrono::duration<double>(t3 - t2).count();
+    }
+    return all_conv ? GDR_OK : GDR_NOT_CONVERGED;
+}
+
+int solve_proj_batch(gdr_op_s* op, gdr_defl_s* defl, int ns, const double2* sig, int nrhs,
+                     const double2* B_eo, double2* X_eo, const gdr_params& p, Stats& S) {
+    if (defl->prec == GDR_PREC_MIXED) return proj_batch<float>(op, defl, ns, sig, nrhs, B_eo, X_eo, p, S);
+    return proj_batch<double>(op, defl, ns, sig, nrhs, B_eo, X_eo, p, S);
+}
+
+// ---------------------------------------------------------------------------
+static void residual_vectors(gdr_op_s* op, int ns, const double2* sig, const double2* b,
+                             const double2* xs, double2* R) {
+    hipStream_t st = op->ctx->st;
+    const int64_t n = op->n;
+    for (int i0 = 0; i0 < ns; i0 += DSLASH_MAXV) {
+        const int nb = std::min(DSLASH_MAXV, ns - i0);
+        DiagList dl{};
+        for (int v = 0; v < nb; ++v) {
+            dl.d[v] = z(1.0 - sig[i0 + v].x, -sig[i0 + v].y);
+            dl.alpha[v] = -1;
+        }
+        dslash<double>(xs + (int64_t)i0 * n, n, R + (int64_t)i0 * n, n, b, 0, op->u64,
+                       GDR_LINKS_F64, op->g, op->kappa, dl, nb, st);
+    }
+}
+
+static std::vector<double> norms(gdr_op_s* op, const double2* R, int nv) {
+    hipStream_t st = op->ctx->st;
+    DMem mem;
+    const int nblk = cgs_nblk(op->n);
+    double2* part = mem.get<double2>((size_t)nblk * nv);
+    double2* out = mem.get<double2>(nv);
+    cgs_pass<double, double>(CGS_DOT, nullptr, 0, 0, 0, R, op->n, nullptr, 0, nullptr, 0, part,
+                             nblk, op->n, nv, st);
+    reduce_cols(part, nblk, 1, out, 1, nullptr, 0, nv, st);
+    std::vector<double2> h(nv);
+    HIPCHK(hipMemcpyAsync(h.data(), out, nv * sizeof(double2), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    std::vector<double> r(nv);
+    for (int i = 0; i < nv; ++i) r[i] = std::sqrt(h[i].x);
+    return r;
+}
+
+void true_residuals(gdr_op_s* op, int ns, const double2* sig, int nrhs, const double2* B_eo,
+                    const double2* X_eo, std::vector<double>& resid) {
+    DMem mem;
+    const int64_t n = op->n;
+    double2* R = mem.get<double2>((size_t)ns * n);
+    resid.assign((size_t)nrhs * ns, 0);
+    for (int j = 0; j < nrhs; ++j) {
+        const double bn = vec_norm(op, B_eo + (int64_t)j * n);
+        residual_vectors(op, ns, sig, B_eo + (int64_t)j * n, X_eo + (int64_t)j * ns * n, R);
+        auto rn = norms(op, R, ns);
+        for (int i = 0; i < ns; ++i) resid[(size_t)j * ns + i] = bn > 0 ? rn[i] / bn : rn[i];
+    }
+}
+
+int cleanup(gdr_op_s* op, gdr_defl_s* defl, int ns, const double2* sig, int nrhs,
+            const double2* B_eo, double2* X_eo, const gdr_params& p, Stats& S) {
+    hipStream_t st = op->ctx->st;
+    const int64_t n = op->n;
+    DMem mem;
+    double2* R = mem.get<double2>((size_t)ns * n);
+    std::vector<double> bn(nrhs);
+    for (int j = 0; j < nrhs; ++j) bn[j] = vec_norm(op, B_eo + (int64_t)j * n);
+    bool done = false;
+    for (int round = 0; round < p.max_refine && !done; ++round) {
+        // pairs above tolerance
+        struct Pair { int j, i; double res; };
+        std::vector<Pair> todo;
+        for (int j = 0; j < nrhs; ++j) {
+            residual_vectors(op, ns, sig, B_eo + (int64_t)j * n, X_eo + (int64_t)j * ns * n, R);
+            auto rn = norms(op, R, ns);
+            if (S.st) S.st->mvp_fp64 += ns;
+            for (int i = 0; i < ns; ++i) {
+                const double rel = bn[j] > 0 ? rn[i] / bn[j] : 0;
+                if (rel > p.tol) todo.push_back({j, i, rel});
+            }
+        }
+        if (todo.empty()) {
+            done = true;
+            break;
+        }
+        for (size_t pos = 0; pos < todo.size(); pos += 16) {
+            const int nmem = (int)std::min<size_t>(16, todo.size() - pos);
+            DMem cm;
+            double2* Bm = cm.get<double2>((size_t)nmem * n);
+            double2* W = cm.get<double2>((size_t)nmem * 2 * n);
+            std::vector<double> tol(nmem), bnorm(nmem);
+            std::vector<int> phase(nmem, 8);
+            std::vector<double2> sgm(nmem);
+            for (int b = 0; b < nmem; ++b) {
+                const Pair& q = todo[pos + b];
+                residual_vectors(op, 1, sig + q.i, B_eo + (int64_t)q.j * n,
+                                 X_eo + ((int64_t)q.j * ns + q.i) * n, Bm + b * n);
+                bnorm[b] = q.res * bn[q.j];
+                tol[b] = std::min(0.5, std::max(0.3 * p.tol / q.res, 1e-5));
+                sgm[b] = sig[q.i];
+            }
+            ProjResult Rr;
+            if (defl && defl->prec == GDR_PREC_F64)
+                proj_run<double>(op, defl, nmem, 1, sgm, Bm, W, tol, bnorm, p.m_proj, p.max_cycles, S, phase, Rr);
+            else
+                proj_run<float>(op, defl, nmem, 1, sgm, Bm, W, tol, bnorm, p.m_proj, p.max_cycles, S, phase, Rr);
+            for (int b = 0; b < nmem; ++b) {
+                const Pair& q = todo[pos + b];
+                axpy_dev(X_eo + ((int64_t)q.j * ns + q.i) * n, 0, W + (int64_t)b * 2 * n, 0,
+                         nullptr, 0, n, 1, st);
+                if (S.st) {
+                    S.st->mvp_cleanup += Rr.mvps[b];
+                    S.st->cycles_cleanup += Rr.cycles[b];
+                }
+            }
+            HIPCHK(hipStreamSynchronize(st));
+        }
+    }
+    return done ? GDR_OK : GDR_NOT_CONVERGED;
+}
+
+}  // namespace gdr

@@ -1,0 +1,105 @@
+// Host engine: handles behind the C-ABI and the solver drivers.
+#pragma once
+
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "gdr.h"
+#include "kernels.h"
+#include "small.h"
+
+struct GdrError : std::runtime_error {
+    int code;
+    GdrError(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCHK(x)                                                                         \
+    do {                                                                                  \
+        hipError_t e_ = (x);                                                              \
+        if (e_ != hipSuccess)                                                             \
+            throw GdrError(e_ == hipErrorOutOfMemory ? GDR_ERR_OOM : GDR_ERR_HIP,         \
+                           std::string(#x) + ": " + hipGetErrorString(e_));               \
+    } while (0)
+
+struct gdr_ctx_s {
+    int device = 0;
+    hipStream_t st = nullptr;
+    std::string err;
+};
+
+struct gdr_op_s {
+    gdr_ctx_s* ctx = nullptr;
+    gdr::Geom g{};
+    int bc[4] = {1, 1, 1, -1};
+    double kappa = 0;
+    int64_t n = 0;          // 12 * volume
+    double2* u64 = nullptr; // FP64 links (internal layout)
+    void* ulo = nullptr;    // FP32 or FP16 links
+    int lst = GDR_LINKS_F32;
+};
+
+struct gdr_defl_s {
+    gdr_op_s* op = nullptr;
+    int k = 0;
+    int prec = GDR_PREC_F64;      // basis storage: F64 (double2) or MIXED (float2)
+    void* V = nullptr;            // (k+1) columns of n, internal layout
+    double2* Hk = nullptr;        // device (k+1) x k column-major
+    std::vector<double2> Hk_host;
+    std::vector<double2> extra_sig;   // shift list the extra solutions belong to
+    double2* S = nullptr;             // ns x n FP64 (index 0 unused): (A - s_i) S_i = v_{k+1}
+    int64_t mvp_extra = 0;
+    int cycles_extra = 0;
+    ~gdr_defl_s();
+};
+
+namespace gdr {
+
+// device allocation list freed on scope exit
+struct DMem {
+    std::vector<void*> ptrs;
+    ~DMem() {
+        for (void* p : ptrs) (void)hipFree(p);
+    }
+    template <class X>
+    X* get(size_t count) {
+        void* p = nullptr;
+        if (count == 0) count = 1;
+        HIPCHK(hipMalloc(&p, count * sizeof(X)));
+        ptrs.push_back(p);
+        return (X*)p;
+    }
+};
+
+struct Stats {
+    gdr_stats* st = nullptr;
+    void hist(int phase, int cycle, int64_t mvps, double r1, double rmax) {
+        if (!st || !st->hist || st->hist_len >= st->hist_cap) return;
+        double* h = st->hist + 5 * st->hist_len++;
+        h[0] = phase;
+        h[1] = cycle;
+        h[2] = (double)mvps;
+        h[3] = r1;
+        h[4] = rmax;
+    }
+    void theta(const double2* t, int k) {
+        if (!st || !st->theta) return;
+        for (int i = 0; i < k && st->theta_len < st->theta_cap; ++i)
+            st->theta[st->theta_len++] = gdr_c64{t[i].x, t[i].y};
+    }
+};
+
+// whole-problem solver (internal layouts); returns GDR_OK / GDR_NOT_CONVERGED
+int solve_dr_sh(gdr_op_s* op, int ns, const double2* sig, const double2* b_eo, double2* X_eo,
+                const gdr_params& p, Stats& S, gdr_defl_s** defl_out, bool* converged);
+int solve_proj_batch(gdr_op_s* op, gdr_defl_s* defl, int ns, const double2* sig, int nrhs,
+                     const double2* B_eo, double2* X_eo, const gdr_params& p, Stats& S);
+// true FP64 residual norms ||b_j - (A - s_i) x_ij|| / ||b_j||, resid[j*ns + i]
+void true_residuals(gdr_op_s* op, int ns, const double2* sig, int nrhs, const double2* B_eo,
+                    const double2* X_eo, std::vector<double>& resid);
+// mixed-precision cleanup: FP64-refined single-shift GMRES(m)-Proj(k) per (shift, RHS)
+int cleanup(gdr_op_s* op, gdr_defl_s* defl, int ns, const double2* sig, int nrhs,
+            const double2* B_eo, double2* X_eo, const gdr_params& p, Stats& S);
+double vec_norm(gdr_op_s* op, const double2* x);
+
+}  // namespace gdr

@@ -1,0 +1,115 @@
+// Host-side launchers of the HIP kernels (all asynchronous on `st`).
+#pragma once
+
+#include "common.h"
+
+namespace gdr {
+
+// ------------------------------------------------------------ layout (layout.hip)
+// canonical complex128 [v][t][z][y][x][4][3]  <->  internal even-odd SoA of type T,
+// vector v at eo + v*eo_stride (elements)
+template <typename T>
+void pack_spinor(const double2* canon, typename CT<T>::t* eo, int64_t eo_stride, const Geom& g,
+                 int nvec, hipStream_t st);
+template <typename T>
+void unpack_spinor(const typename CT<T>::t* eo, int64_t eo_stride, double2* canon, const Geom& g,
+                   int nvec, hipStream_t st);
+// storage: 0 FP64 (double2), 1 FP32 (float2), 2 FP16 (__half2 per complex)
+void pack_links(const double2* canon, void* out, int storage, const Geom& g, const int bc[4],
+                hipStream_t st);
+void build_tables(int32_t* eo_of_lex, int32_t* nbr, int8_t* sign, const Geom& g, int bc_t,
+                  hipStream_t st);
+
+// ------------------------------------------------------------ Dslash (dslash.hip)
+constexpr int DSLASH_MAXV = 16;
+struct DiagList {
+    double2 d[DSLASH_MAXV];   // per-vector diagonal factor (1 - sigma_v)
+    double alpha[DSLASH_MAXV];
+};
+// out_v = alpha_v * ((1 - sigma_v) in_v - kappa D in_v) [+ add_v]   for v < nvec
+// TS spinor type; link storage per `link_storage`; compute in TS.
+template <typename TS>
+void dslash(const typename CT<TS>::t* in, int64_t in_stride, typename CT<TS>::t* out,
+            int64_t out_stride, const typename CT<TS>::t* add, int64_t add_stride,
+            const void* links, int link_storage, const Geom& g, double kappa, const DiagList& dl,
+            int nvec, hipStream_t st, const int* act = nullptr);
+
+// ------------------------------------------------------------ BLAS (blas.hip)
+// Block-partial buffers: partial[(member*ncols_tot + col)*nblk + blk] (double2)
+int cgs_nblk(int64_t n);
+
+enum CgsMode { CGS_DOT = 0, CGS_UPDATE_DOT = 1, CGS_UPDATE_NORM = 2, CGS_UPDATE = 3 };
+
+// Batched over members b < nmem (blockIdx.y). Per member:
+//   V  = Vb + b*v_mstride, column j at V + j*ldv (type T), ncols columns
+//   DOT        : partial[0..ncols) = V^H win, partial[ncols] = ||win||^2 (win type T)
+//   UPDATE_DOT : wd = win - V h ; partial = V^H wd               (win T, wd double)
+//   UPDATE_NORM: wd = wd - V h ; partial[0] = ||wd||^2
+//   UPDATE     : wd = wd - V h (or win - V h if win != null)
+// h: double2 [ncols] at h + b*h_mstride (device).
+// TW: type of win (T, or double for the FP64 residual against an FP32 basis in DOT mode)
+template <typename T, typename TW>
+void cgs_pass(int mode, const typename CT<T>::t* V, int64_t ldv, int64_t v_mstride, int ncols,
+              const typename CT<TW>::t* win, int64_t win_mstride, double2* wd, int64_t wd_mstride,
+              const double2* h, int64_t h_mstride, double2* partial, int nblk, int64_t n, int nmem,
+              hipStream_t st, const int* act = nullptr);
+
+// out[b*out_mstride + c] (+)= sum_blk partial[(b*ncols + c)*nblk + blk], c < ncols
+void reduce_cols(const double2* partial, int nblk, int ncols, double2* out, int64_t out_mstride,
+                 double2* add_to, int64_t add_mstride, int nmem, hipStream_t st,
+                 const int* act = nullptr);
+
+// Norm finish for Arnoldi step j of every member: ||w|| = sqrt(sum partial[..].x);
+// H[(j*ldh) + j+1] = ||w||, inv[b] = 1/||w|| or 0 on breakdown (||w|| <= tol_rel*sqrt(w0sq)),
+// brk[b] = j when breakdown happens first. w0sq = ||A v_j||^2 from the DOT pass (out of
+// reduce_cols at h1[ncols]).
+void norm_finish(const double2* partial, int nblk, double2* H, int64_t ldh, int64_t h_mstride,
+                 int j, const double2* w0, int64_t w0_mstride, double* inv, int* brk,
+                 double tol_rel, int nmem, hipStream_t st, const int* act = nullptr);
+
+// v = (T)(wd * inv[b]) batched
+template <typename T>
+void scale_store(const double2* wd, int64_t wd_mstride, const double* inv,
+                 typename CT<T>::t* v, int64_t v_mstride, int64_t n, int nmem, hipStream_t st,
+                 const int* act = nullptr);
+
+// out_s = beta_s * out_s + sum_{l<ncols} V_l * coef[l + s*ldc]   (FP64 outputs)
+// member b: V + b*v_mstride, coef + b*c_mstride, out + b*o_mstride + s*o_stride.
+// keep_mask bit s set: accumulate (beta 1); clear: overwrite (beta 0).
+template <typename T>
+void vcombine(const typename CT<T>::t* V, int64_t ldv, int64_t v_mstride, int ncols,
+              const double2* coef, int ldc, int64_t c_mstride, int nout, double2* out,
+              int64_t o_stride, int64_t o_mstride, unsigned keep_mask, int64_t n, int nmem,
+              hipStream_t st, const int* act = nullptr);
+
+// Basis recombination W_j = sum_{l<ncols} V_l P[l + j*ldp], j < nout, written as type T
+template <typename T>
+void vrecombine(const typename CT<T>::t* V, int64_t ldv, int ncols, const double2* P, int ldp,
+                int nout, typename CT<T>::t* W, int64_t ldw, int64_t n, hipStream_t st);
+
+// y_b = (T) (x_b * scal[b])  (scal device, may be null -> 1)  FP64 -> T conversion
+template <typename T>
+void convert_scale(const double2* x, int64_t x_mstride, const double* scal, int sc_stride,
+                   typename CT<T>::t* y, int64_t y_mstride, int64_t n, int nmem, hipStream_t st,
+                   const int* act = nullptr);
+
+// x_b += coef[b*cstride] * y_b  (coef device double2; null -> 1)
+void axpy_dev(double2* x, int64_t x_mstride, const double2* y, int64_t y_mstride,
+              const double2* coef, int cstride, int64_t n, int nmem, hipStream_t st,
+              const int* act = nullptr);
+// start of a GMRES cycle per member: rn2[b*rs] = ||r||^2 ->
+// c[b*cs + 0] = ||r||, c[b*cs + 1..m] = 0, inv[b] = 1/||r|| (0 if ||r|| = 0)
+void start_cycle(const double2* rn2, int64_t rs, double2* c, int64_t cs, int m, double* inv,
+                 int nmem, hipStream_t st, const int* act = nullptr);
+// fill n ints with v
+void fill_int(int* p, int v, int n, hipStream_t st);
+// x_b *= coef[b]
+void scal_dev(double2* x, int64_t x_mstride, const double2* coef, int64_t n, int nmem,
+              hipStream_t st);
+// y_b = x_b (double)
+void copy_vec(const double2* x, int64_t x_mstride, double2* y, int64_t y_mstride, int64_t n,
+              int nmem, hipStream_t st);
+
+// ------------------------------------------------------------ small dense FP64 (small.hip)
+struct SmallArgs;   // defined in small.h
+}  // namespace gdr

@@ -1,0 +1,146 @@
+// Canonical <-> even-odd SoA layout conversion, link packing and the
+// lattice tables (checked bit for bit against the oracle's tables).
+#include "kernels.h"
+
+namespace gdr {
+
+__device__ __forceinline__ void lex_coords(const Geom& g, int lex, int& x, int& y, int& z, int& t) {
+    x = lex % g.L[0];
+    int r = lex / g.L[0];
+    y = r % g.L[1];
+    r /= g.L[1];
+    z = r % g.L[2];
+    t = r / g.L[2];
+}
+
+__device__ __forceinline__ int lex_of(const Geom& g, int x, int y, int z, int t) {
+    return x + g.L[0] * (y + g.L[1] * (z + g.L[2] * t));
+}
+
+__device__ __forceinline__ int eo_of(const Geom& g, int lex, int x, int y, int z, int t) {
+    int p = (x + y + z + t) & 1;
+    return p * g.vh + (lex >> 1);
+}
+
+template <typename T>
+__global__ void k_pack_spinor(const double2* __restrict__ canon, typename CT<T>::t* __restrict__ eo,
+                              int64_t eo_stride, Geom g) {
+    int lex = blockIdx.x * blockDim.x + threadIdx.x;
+    int v = blockIdx.y;
+    if (lex >= g.vol) return;
+    int x, y, z, t;
+    lex_coords(g, lex, x, y, z, t);
+    int p = (x + y + z + t) & 1;
+    int s = lex >> 1;
+    const double2* src = canon + ((int64_t)v * g.vol + lex) * 12;
+    typename CT<T>::t* dst = eo + v * eo_stride + (int64_t)p * 12 * g.vh + s;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) dst[(int64_t)c * g.vh] = from_d<T>(src[c]);
+}
+
+template <typename T>
+__global__ void k_unpack_spinor(const typename CT<T>::t* __restrict__ eo, int64_t eo_stride,
+                                double2* __restrict__ canon, Geom g) {
+    int lex = blockIdx.x * blockDim.x + threadIdx.x;
+    int v = blockIdx.y;
+    if (lex >= g.vol) return;
+    int x, y, z, t;
+    lex_coords(g, lex, x, y, z, t);
+    int p = (x + y + z + t) & 1;
+    int s = lex >> 1;
+    const typename CT<T>::t* src = eo + v * eo_stride + (int64_t)p * 12 * g.vh + s;
+    double2* dst = canon + ((int64_t)v * g.vol + lex) * 12;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) dst[c] = to_d(src[(int64_t)c * g.vh]);
+}
+
+template <typename T>
+void pack_spinor(const double2* canon, typename CT<T>::t* eo, int64_t eo_stride, const Geom& g,
+                 int nvec, hipStream_t st) {
+    dim3 grid((g.vol + 255) / 256, nvec);
+    hipLaunchKernelGGL(k_pack_spinor<T>, grid, dim3(256), 0, st, canon, eo, eo_stride, g);
+}
+template <typename T>
+void unpack_spinor(const typename CT<T>::t* eo, int64_t eo_stride, double2* canon, const Geom& g,
+                   int nvec, hipStream_t st) {
+    dim3 grid((g.vol + 255) / 256, nvec);
+    hipLaunchKernelGGL(k_unpack_spinor<T>, grid, dim3(256), 0, st, eo, eo_stride, canon, g);
+}
+template void pack_spinor<double>(const double2*, double2*, int64_t, const Geom&, int, hipStream_t);
+template void pack_spinor<float>(const double2*, float2*, int64_t, const Geom&, int, hipStream_t);
+template void unpack_spinor<double>(const double2*, int64_t, double2*, const Geom&, int, hipStream_t);
+template void unpack_spinor<float>(const float2*, int64_t, double2*, const Geom&, int, hipStream_t);
+
+struct BC4 {
+    int v[4];
+};
+
+// links internal: [p][mu][e = a*3+b][vh], bc[mu] folded into U_mu(x) at x_mu = L_mu - 1
+__global__ void k_pack_links(const double2* __restrict__ canon, void* __restrict__ out, int storage,
+                             Geom g, BC4 bc) {
+    int lex = blockIdx.x * blockDim.x + threadIdx.x;
+    if (lex >= g.vol) return;
+    int c[4];
+    lex_coords(g, lex, c[0], c[1], c[2], c[3]);
+    int p = (c[0] + c[1] + c[2] + c[3]) & 1;
+    int s = lex >> 1;
+    for (int mu = 0; mu < 4; ++mu) {
+        double f = (c[mu] == g.L[mu] - 1) ? (double)bc.v[mu] : 1.0;
+        const double2* src = canon + ((int64_t)mu * g.vol + lex) * 9;
+        int64_t base = ((int64_t)(p * 4 + mu) * 9) * g.vh + s;
+        for (int e = 0; e < 9; ++e) {
+            double2 u = cscale(src[e], f);
+            int64_t o = base + (int64_t)e * g.vh;
+            if (storage == 0) {
+                ((double2*)out)[o] = u;
+            } else if (storage == 1) {
+                ((float2*)out)[o] = make_float2((float)u.x, (float)u.y);
+            } else {
+                ((__half2*)out)[o] = __floats2half2_rn((float)u.x, (float)u.y);
+            }
+        }
+    }
+}
+
+void pack_links(const double2* canon, void* out, int storage, const Geom& g, const int bc[4],
+                hipStream_t st) {
+    BC4 b{{bc[0], bc[1], bc[2], bc[3]}};
+    hipLaunchKernelGGL(k_pack_links, dim3((g.vol + 255) / 256), dim3(256), 0, st, canon, out,
+                       storage, g, b);
+}
+
+__global__ void k_tables(int32_t* __restrict__ eo_of_lex, int32_t* __restrict__ nbr,
+                         int8_t* __restrict__ sign, Geom g) {
+    int lex = blockIdx.x * blockDim.x + threadIdx.x;
+    if (lex >= g.vol) return;
+    int c[4];
+    lex_coords(g, lex, c[0], c[1], c[2], c[3]);
+    int eo = eo_of(g, lex, c[0], c[1], c[2], c[3]);
+    eo_of_lex[lex] = eo;
+    for (int d = 0; d < 8; ++d) {
+        int mu = d & 3;
+        int step = d < 4 ? 1 : -1;
+        int cc[4] = {c[0], c[1], c[2], c[3]};
+        cc[mu] += step;
+        int8_t sg = 1;
+        if (cc[mu] == g.L[mu]) {
+            cc[mu] = 0;
+            if (mu == 3) sg = -1;
+        } else if (cc[mu] < 0) {
+            cc[mu] = g.L[mu] - 1;
+            if (mu == 3) sg = -1;
+        }
+        int nl = lex_of(g, cc[0], cc[1], cc[2], cc[3]);
+        nbr[(int64_t)eo * 8 + d] = eo_of(g, nl, cc[0], cc[1], cc[2], cc[3]);
+        sign[(int64_t)eo * 8 + d] = sg;
+    }
+}
+
+void build_tables(int32_t* eo_of_lex, int32_t* nbr, int8_t* sign, const Geom& g, int bc_t,
+                  hipStream_t st) {
+    (void)bc_t;
+    hipLaunchKernelGGL(k_tables, dim3((g.vol + 255) / 256), dim3(256), 0, st, eo_of_lex, nbr,
+                       sign, g);
+}
+
+}  // namespace gdr

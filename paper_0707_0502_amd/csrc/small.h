@@ -1,0 +1,63 @@
+// Small dense FP64 problems of every restart cycle, solved on the device by
+// one 64-lane wavefront per problem with the matrices resident in LDS.
+#pragma once
+
+#include "common.h"
+
+namespace gdr {
+
+// Per-cycle results read back by the host (one small copy per cycle).
+struct CycleOut {
+    double snorm;               // ||s|| = ||r_1|| (shortcut norm, eq. (2.6))
+    int flags;                  // bit0 breakdown in a shift solve, bit1 Schur failed
+    int pad;
+    double2 beta[MAXNS];        // beta_i^new
+    double2 theta[MAXM];        // kept harmonic Ritz values (restart only)
+};
+
+struct CycleArgs {
+    const double2* H;   // (m+1) x m column-major, ldh = m+1   (per member: + b*h_ms)
+    int64_t h_ms;
+    const double2* c;   // m+1                                (per member: + b*c_ms)
+    int64_t c_ms;
+    const double2* sigma;   // ns shifts                       (per member: + b*sig_ms)
+    int64_t sig_ms;
+    const double2* beta;    // ns current beta_i               (per member: + b*beta_ms)
+    int64_t beta_ms;
+    const int* brk;         // per member first breakdown step or -1
+    double2* coef;          // (m+1) x (ns+1) column-major: d_i padded, last column s
+    int64_t coef_ms;
+    CycleOut* out;          // per member
+    // restart (block 0 of member 0 only, when k > 0 or restart requested)
+    int restart;
+    int k;
+    double2* P;             // (m+1) x (k+1), ldp = m+1
+    double2* Hnew;          // (m+1) x m zero except the leading (k+1) x k block
+    double2* cnew;          // m+1
+    int m;
+    int ns;
+    const int* act;         // per member active flag (nullable)
+};
+
+struct ProjArgs {
+    const double2* Hk;      // (k+1) x k column-major (ld k+1)
+    int k;
+    const double2* C;       // per member k+1 coefficients V_{k+1}^H r (+ b*c_ms)
+    int64_t c_ms;
+    const double2* sigma;   // shifts of member b: sigma + b*sig_ms
+    int64_t sig_ms;
+    const double2* beta;    // per member ns
+    int64_t beta_ms;
+    double2* gam;           // per member ns (accumulated gamma_i)
+    int64_t gam_ms;
+    double2* coef;          // per member (k+1) x (ns+1): D padded with zero row, last column -y
+    int64_t coef_ms;
+    int* flags;             // per member: bit0 singular shifted k x k system
+    int ns;
+    const int* act;         // per member active flag (nullable)
+};
+
+void cycle_small(const CycleArgs& a, int nmem, hipStream_t st);
+void proj_small(const ProjArgs& a, int nmem, hipStream_t st);
+
+}  // namespace gdr

@@ -1,0 +1,561 @@
+// Small dense FP64 problems of a restart cycle, on the device.
+//
+// One 64-lane wavefront per problem, matrices in LDS (column-major, odd
+// leading dimension so that both row- and column-strided lane accesses are
+// bank-conflict free). Per cycle (Sec. 2.1 and the GMRES-DR-Sh algorithm):
+//   * base shift: min ||c - (H_bar - sigma_1 I_bar) d_1|| by Householder QR,
+//     s = c - (H_bar - sigma_1 I_bar) d_1;
+//   * shift i >= 2: QR of H_bar - sigma_i I_bar applied to c and s; the last
+//     row fixes beta_i^new = beta_i (Q^H c)_{m+1} / (Q^H s)_{m+1}, the first
+//     m rows give d_i by back substitution;
+//   * GMRES-DR restart (block 0): harmonic Ritz values of the base-shifted
+//     matrix as the eigenvalues of G = H_m + |h_{m+1,m}|^2 H_m^{-H} e_m e_m^H
+//     (Hessenberg reduction, then complex shifted-QR Schur form
+//     G = Z T Z^H); the k eigenvalues of smallest |theta| (ties by Re, then
+//     Im) are moved to the top of T by adjacent Givens swaps, so the first k
+//     Schur vectors are an orthonormal basis of their eigenvectors' span.
+//     P_{k+1} = [Z_k; 0 | s orthogonalised against them], H_bar_new =
+//     P_{k+1}^H H_bar P_k, c_new = P_{k+1}^H s.
+// Projection step of GMRES-Proj-Sh (Sec. 4): min ||c - (H_bar_k - sigma_1
+// I_bar) d_1||, then (H_k - sigma_i I) d_i = beta_i (H_k - sigma_1 I) d_1 and
+// gamma_i += h_{k+1,:} (beta_i d_1 - d_i) (eq. (4.2)).
+#include "small.h"
+
+namespace gdr {
+
+constexpr int LD = 65;
+#define AT(M, r, c) (M)[(c) * LD + (r)]
+
+__device__ __forceinline__ double wred(double v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+__device__ __forceinline__ double2 csqrt_(double2 z) {
+    double r = cabs(z);
+    double a = sqrt(fmax(0.5 * (r + z.x), 0.0));
+    double b = sqrt(fmax(0.5 * (r - z.x), 0.0));
+    return mk(a, z.y < 0 ? -b : b);
+}
+
+// lexicographic key (|theta|, Re, Im)
+__device__ __forceinline__ bool key_less(double2 a, double2 b) {
+    double aa = cabs(a), ab = cabs(b);
+    if (aa != ab) return aa < ab;
+    if (a.x != b.x) return a.x < b.x;
+    return a.y < b.y;
+}
+
+// Householder QR of the first `cols` columns of the rows x ctot LDS matrix A;
+// the remaining columns receive Q^H. R is left in the upper triangle.
+__device__ void hh_qr(double2* A, int rows, int cols, int ctot, double2* hv) {
+    const int lane = threadIdx.x;
+    for (int j = 0; j < cols && j < rows; ++j) {
+        double ss = 0;
+        for (int r = j + lane; r < rows; r += 64) ss += cabs2(AT(A, r, j));
+        ss = wred(ss);
+        const double alpha = sqrt(ss);
+        const double2 x0 = AT(A, j, j);
+        const double ax0 = cabs(x0);
+        __syncthreads();
+        if (!(alpha > 0.0)) continue;
+        const double2 ph = ax0 > 0 ? cscale(x0, 1.0 / ax0) : mk(1, 0);
+        for (int r = j + lane; r < rows; r += 64)
+            hv[r] = (r == j) ? cadd(x0, cscale(ph, alpha)) : AT(A, r, j);
+        const double tau = 1.0 / (alpha * (alpha + ax0));   // 2 / ||v||^2
+        __syncthreads();
+        for (int c = j + 1 + lane; c < ctot; c += 64) {
+            double2 d = mk(0, 0);
+            for (int r = j; r < rows; ++r) d = cadd(d, cjmul(hv[r], AT(A, r, c)));
+            d = cscale(d, tau);
+            for (int r = j; r < rows; ++r) AT(A, r, c) = csub(AT(A, r, c), cmul(hv[r], d));
+        }
+        for (int r = j + lane; r < rows; r += 64) AT(A, r, j) = (r == j) ? cscale(ph, -alpha) : mk(0, 0);
+        __syncthreads();
+    }
+}
+
+// Solve R y = y in place (R upper triangular nn x nn in A). Returns false if
+// a pivot is zero or tiny relative to the largest.
+__device__ bool back_sub(const double2* A, int nn, double2* y) {
+    const int lane = threadIdx.x;
+    double rmax = 0;
+    for (int j = 0; j < nn; ++j) rmax = fmax(rmax, cabs(AT(A, j, j)));
+    bool ok = true;
+    for (int j = nn - 1; j >= 0; --j) {
+        __syncthreads();
+        const double2 piv = AT(A, j, j);
+        if (!(cabs(piv) > 1e-14 * rmax)) ok = false;
+        const double2 dj = cdiv(y[j], piv);
+        __syncthreads();
+        if (lane == 0) y[j] = dj;
+        for (int r = lane; r < j; r += 64) y[r] = csub(y[r], cmul(AT(A, r, j), dj));
+    }
+    __syncthreads();
+    return ok;
+}
+
+__device__ __forceinline__ void givens(double2 x, double2 y, double& c, double2& s) {
+    const double ax = cabs(x), ay = cabs(y);
+    if (ay == 0.0) {
+        c = 1.0;
+        s = mk(0, 0);
+    } else if (ax == 0.0) {
+        c = 0.0;
+        s = cscale(cconj(y), 1.0 / ay);
+    } else {
+        const double rho = hypot(ax, ay);
+        c = ax / rho;
+        s = cscale(cmul(cscale(x, 1.0 / ax), cconj(y)), 1.0 / rho);
+    }
+}
+
+// rows p, p+1, columns [c0, c1): [rp; rq] <- [[c, s], [-conj(s), c]] [rp; rq]
+__device__ __forceinline__ void rot_rows(double2* M, int p, int c0, int c1, double c, double2 s) {
+    for (int col = c0 + (int)threadIdx.x; col < c1; col += 64) {
+        const double2 a = AT(M, p, col), b = AT(M, p + 1, col);
+        AT(M, p, col) = cadd(cscale(a, c), cmul(s, b));
+        AT(M, p + 1, col) = csub(cscale(b, c), cjmul(s, a));
+    }
+}
+// columns p, p+1, rows [r0, r1): M <- M G^H
+__device__ __forceinline__ void rot_cols(double2* M, int p, int r0, int r1, double c, double2 s) {
+    for (int r = r0 + (int)threadIdx.x; r < r1; r += 64) {
+        const double2 a = AT(M, r, p), b = AT(M, r, p + 1);
+        AT(M, r, p) = cadd(cscale(a, c), cjmul(s, b));
+        AT(M, r, p + 1) = csub(cscale(b, c), cmul(s, a));
+    }
+}
+
+// Reduce T (nn x nn) to upper Hessenberg form by Householder similarity,
+// accumulating Z <- Z H (Z enters as the identity).
+__device__ void hessenberg(double2* T, double2* Z, int nn, double2* hv) {
+    const int lane = threadIdx.x;
+    for (int j = 0; j + 2 < nn; ++j) {
+        double ss = 0;
+        for (int r = j + 1 + lane; r < nn; r += 64) ss += cabs2(AT(T, r, j));
+        ss = wred(ss);
+        const double2 x0 = AT(T, j + 1, j);
+        const double ax0 = cabs(x0);
+        const double tail = ss - ax0 * ax0;
+        const double alpha = sqrt(ss);
+        __syncthreads();
+        if (!(tail > 0.0)) continue;   // already Hessenberg in this column
+        const double2 ph = ax0 > 0 ? cscale(x0, 1.0 / ax0) : mk(1, 0);
+        for (int r = j + 1 + lane; r < nn; r += 64)
+            hv[r] = (r == j + 1) ? cadd(x0, cscale(ph, alpha)) : AT(T, r, j);
+        const double tau = 1.0 / (alpha * (alpha + ax0));
+        __syncthreads();
+        // left: T[j+1:, j:] -= tau v (v^H T)
+        for (int c = j + lane; c < nn; c += 64) {
+            double2 d = mk(0, 0);
+            for (int r = j + 1; r < nn; ++r) d = cadd(d, cjmul(hv[r], AT(T, r, c)));
+            d = cscale(d, tau);
+            for (int r = j + 1; r < nn; ++r) AT(T, r, c) = csub(AT(T, r, c), cmul(hv[r], d));
+        }
+        __syncthreads();
+        // right: T[:, j+1:] -= tau (T v) v^H ; Z likewise
+        for (int r = lane; r < nn; r += 64) {
+            double2 d = mk(0, 0), e = mk(0, 0);
+            for (int c = j + 1; c < nn; ++c) {
+                d = cadd(d, cmul(AT(T, r, c), hv[c]));
+                e = cadd(e, cmul(AT(Z, r, c), hv[c]));
+            }
+            d = cscale(d, tau);
+            e = cscale(e, tau);
+            for (int c = j + 1; c < nn; ++c) {
+                AT(T, r, c) = csub(AT(T, r, c), cmul(d, cconj(hv[c])));
+                AT(Z, r, c) = csub(AT(Z, r, c), cmul(e, cconj(hv[c])));
+            }
+        }
+        __syncthreads();
+        for (int r = j + 2 + lane; r < nn; r += 64) AT(T, r, j) = mk(0, 0);
+        __syncthreads();
+    }
+}
+
+// Complex Schur form of the upper Hessenberg T by single-shift QR with
+// Wilkinson shifts; Z accumulates. Returns 0 on success.
+__device__ int schur(double2* T, double2* Z, int nn) {
+    const int lane = threadIdx.x;
+    const double eps = 2.220446049250313e-16;
+    double fro = 0;
+    for (int c = 0; c < nn; ++c)
+        for (int r = lane; r < nn; r += 64) fro += cabs2(AT(T, r, c));
+    fro = sqrt(wred(fro));
+    __syncthreads();
+    int hi = nn - 1, iter = 0, total = 0;
+    while (hi > 0) {
+        if (total > 60 * nn) return 1;
+        int l = hi;
+        for (; l > 0; --l) {
+            double tst = cabs(AT(T, l - 1, l - 1)) + cabs(AT(T, l, l));
+            if (tst == 0.0) tst = fro;
+            if (cabs(AT(T, l, l - 1)) <= eps * tst) break;
+        }
+        __syncthreads();
+        if (l > 0 && lane == 0) AT(T, l, l - 1) = mk(0, 0);
+        __syncthreads();
+        if (l == hi) {
+            --hi;
+            iter = 0;
+            continue;
+        }
+        const int lo = l;
+        double2 mu;
+        if (iter > 0 && iter % 10 == 0) {
+            mu = cadd(AT(T, hi, hi), mk(0.75 * cabs(AT(T, hi, hi - 1)), 0));
+        } else {
+            const double2 a = AT(T, hi - 1, hi - 1), b = AT(T, hi - 1, hi);
+            const double2 cc = AT(T, hi, hi - 1), d = AT(T, hi, hi);
+            const double2 half = cscale(csub(a, d), 0.5);
+            const double2 sq = csqrt_(cadd(cmul(half, half), cmul(b, cc)));
+            const double2 mid = cscale(cadd(a, d), 0.5);
+            const double2 e1 = cadd(mid, sq), e2 = csub(mid, sq);
+            mu = cabs(csub(e1, d)) <= cabs(csub(e2, d)) ? e1 : e2;
+        }
+        for (int kk = lo; kk < hi; ++kk) {
+            double2 x, y;
+            if (kk == lo) {
+                x = csub(AT(T, lo, lo), mu);
+                y = AT(T, lo + 1, lo);
+            } else {
+                x = AT(T, kk, kk - 1);
+                y = AT(T, kk + 1, kk - 1);
+            }
+            double c;
+            double2 s;
+            givens(x, y, c, s);
+            __syncthreads();
+            rot_rows(T, kk, kk > lo ? kk - 1 : lo, nn, c, s);
+            __syncthreads();
+            rot_cols(T, kk, 0, min(kk + 3, hi + 1), c, s);
+            rot_cols(Z, kk, 0, nn, c, s);
+            __syncthreads();
+            if (kk > lo && lane == 0) AT(T, kk + 1, kk - 1) = mk(0, 0);
+            __syncthreads();
+        }
+        ++iter;
+        ++total;
+    }
+    return 0;
+}
+
+// swap the adjacent diagonal entries p, p+1 of the triangular T (and Z)
+__device__ void schur_swap(double2* T, double2* Z, int nn, int p) {
+    const double2 t11 = AT(T, p, p), t22 = AT(T, p + 1, p + 1), t12 = AT(T, p, p + 1);
+    double c;
+    double2 s;
+    givens(t12, csub(t22, t11), c, s);
+    __syncthreads();
+    rot_rows(T, p, p, nn, c, s);
+    __syncthreads();
+    rot_cols(T, p, 0, p + 2, c, s);
+    rot_cols(Z, p, 0, nn, c, s);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        AT(T, p, p) = t22;
+        AT(T, p + 1, p + 1) = t11;
+        AT(T, p + 1, p) = mk(0, 0);
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_cycle_small(CycleArgs a) {
+    const int lane = threadIdx.x;
+    const int role = blockIdx.x;   // 0: base (+ restart), i >= 1: shift i
+    const int b = blockIdx.y;
+    if (a.act && !a.act[b]) return;
+    const int m = a.m;
+    const int ns = a.ns;
+    const double2* H = a.H + b * a.h_ms;
+    const double2* cg = a.c + b * a.c_ms;
+    const double2* sig = a.sigma + b * a.sig_ms;
+    const double2* beta = a.beta + b * a.beta_ms;
+    double2* coef = a.coef + b * a.coef_ms;
+    CycleOut* out = a.out + b;
+    const int ldh = m + 1;
+    const int brk = a.brk[b];
+    const int p = brk >= 0 ? brk + 1 : m;   // columns of this cycle
+
+    __shared__ double2 A[(MAXM + 2) * LD];
+    __shared__ double2 Zs[MAXM * LD];
+    __shared__ double2 hv[LD + 1], sv[LD + 1], dv[LD + 1], fv[LD + 1];
+
+    // ---- base least squares: [Hs | c], Hs = H - sigma_1 I_bar, (p+1) x p
+    const double2 s1 = sig[0];
+    for (int c = 0; c <= p; ++c)
+        for (int r = lane; r <= p; r += 64) {
+            double2 v = c < p ? H[c * ldh + r] : cg[r];
+            if (c < p && r == c) v = csub(v, s1);
+            AT(A, r, c) = v;
+        }
+    __syncthreads();
+    hh_qr(A, p + 1, p, p + 1, hv);
+    for (int r = lane; r < p; r += 64) dv[r] = AT(A, r, p);
+    __syncthreads();
+    back_sub(A, p, dv);
+    // s = c - Hs d_1 (from the original entries)
+    for (int r = lane; r <= p; r += 64) {
+        double2 acc = cg[r];
+        for (int c = 0; c < p; ++c) {
+            double2 h = H[c * ldh + r];
+            if (r == c) h = csub(h, s1);
+            acc = csub(acc, cmul(h, dv[c]));
+        }
+        sv[r] = acc;
+    }
+    __syncthreads();
+    double sn = 0, cn = 0;
+    for (int r = lane; r <= p; r += 64) {
+        sn += cabs2(sv[r]);
+        cn += cabs2(cg[r]);
+    }
+    sn = sqrt(wred(sn));
+    cn = sqrt(wred(cn));
+    const bool exact = !(sn > 1e-14 * cn);
+    __syncthreads();
+
+    if (role == 0) {
+        for (int r = lane; r <= m; r += 64) {
+            coef[r] = r < p ? dv[r] : mk(0, 0);
+            coef[ns * (m + 1) + r] = r <= p ? sv[r] : mk(0, 0);
+        }
+        if (lane == 0) {
+            out->snorm = sn;
+            out->beta[0] = mk(1, 0);
+        }
+        if (!a.restart || exact || p < m) return;
+        // ---------------- GMRES-DR restart (harmonic Ritz, base shift)
+        const int k = a.k;
+        __syncthreads();
+        if (k > 0) {
+        // f = Hm^{-H} e_m :  A = [Hm^H | e_m]
+        for (int c = 0; c <= m; ++c)
+            for (int r = lane; r < m; r += 64) {
+                double2 v;
+                if (c < m) {
+                    v = H[r * ldh + c];                       // Hm[c][r]
+                    if (r == c) v = csub(v, s1);
+                    v = cconj(v);
+                } else {
+                    v = mk(r == m - 1 ? 1.0 : 0.0, 0);
+                }
+                AT(A, r, c) = v;
+            }
+        __syncthreads();
+        hh_qr(A, m, m, m + 1, hv);
+        for (int r = lane; r < m; r += 64) fv[r] = AT(A, r, m);
+        __syncthreads();
+        back_sub(A, m, fv);
+        const double h2 = cabs2(H[(m - 1) * ldh + m]);
+        // G = Hm + h2 f e_m^H  into A (m x m); Z = I
+        for (int c = 0; c < m; ++c)
+            for (int r = lane; r < m; r += 64) {
+                double2 v = H[c * ldh + r];
+                if (r == c) v = csub(v, s1);
+                if (c == m - 1) v = cadd(v, cscale(fv[r], h2));
+                AT(A, r, c) = v;
+                AT(Zs, r, c) = mk(r == c ? 1.0 : 0.0, 0);
+            }
+        __syncthreads();
+        hessenberg(A, Zs, m, hv);
+        int fail = schur(A, Zs, m);
+        if (fail) {
+            if (lane == 0) out->flags |= 2;
+            return;
+        }
+        // selection: k smallest |theta| moved to the top, in order
+        for (int pos = 0; pos < k; ++pos) {
+            int best = pos;
+            for (int j = pos + 1; j < m; ++j)
+                if (key_less(AT(A, j, j), AT(A, best, best))) best = j;
+            __syncthreads();
+            for (int q = best - 1; q >= pos; --q) schur_swap(A, Zs, m, q);
+            if (lane == 0) out->theta[pos] = AT(A, pos, pos);
+            __syncthreads();
+        }
+        }  // k > 0
+        // p_{k+1}: s orthogonalised twice against [Z_k; 0], normalised
+        for (int rep = 0; rep < 2; ++rep) {
+            for (int j = lane; j < k; j += 64) {
+                double2 d = mk(0, 0);
+                for (int r = 0; r < m; ++r) d = cadd(d, cjmul(AT(Zs, r, j), sv[r]));
+                hv[j] = d;
+            }
+            __syncthreads();
+            for (int r = lane; r < m; r += 64) {
+                double2 acc = sv[r];
+                for (int j = 0; j < k; ++j) acc = csub(acc, cmul(AT(Zs, r, j), hv[j]));
+                sv[r] = acc;
+            }
+            __syncthreads();
+        }
+        double pn = 0;
+        for (int r = lane; r <= m; r += 64) pn += cabs2(sv[r]);
+        pn = sqrt(wred(pn));
+        __syncthreads();
+        for (int r = lane; r <= m; r += 64) dv[r] = cscale(sv[r], 1.0 / pn);   // p_{k+1}
+        __syncthreads();
+        // P to global
+        for (int j = 0; j <= k; ++j)
+            for (int r = lane; r <= m; r += 64)
+                a.P[j * (m + 1) + r] = j < k ? (r < m ? AT(Zs, r, j) : mk(0, 0)) : dv[r];
+        // Y = H P_k into A ((m+1) x k), H unshifted
+        for (int r = lane; r <= m; r += 64)
+            for (int j = 0; j < k; ++j) {
+                double2 acc = mk(0, 0);
+                for (int l = 0; l < m; ++l) acc = cadd(acc, cmul(H[l * ldh + r], AT(Zs, l, j)));
+                AT(A, r, j) = acc;
+            }
+        __syncthreads();
+        // Hnew = P^H Y ((k+1) x k), zero elsewhere; c_new = P^H s_orig
+        for (int t = lane; t < (m + 1) * m; t += 64) a.Hnew[t] = mk(0, 0);
+        __syncthreads();
+        for (int t = lane; t < (k + 1) * k; t += 64) {
+            const int i = t % (k + 1), j = t / (k + 1);
+            double2 acc = mk(0, 0);
+            if (i < k) {
+                for (int r = 0; r < m; ++r) acc = cadd(acc, cjmul(AT(Zs, r, i), AT(A, r, j)));
+            } else {
+                for (int r = 0; r <= m; ++r) acc = cadd(acc, cjmul(dv[r], AT(A, r, j)));
+            }
+            a.Hnew[j * (m + 1) + i] = acc;
+        }
+        // original s: recompute from coef column (written above)
+        for (int i = lane; i <= m; i += 64) {
+            double2 acc = mk(0, 0);
+            if (i < k) {
+                for (int r = 0; r < m; ++r) acc = cadd(acc, cjmul(AT(Zs, r, i), coef[ns * (m + 1) + r]));
+            } else if (i == k) {
+                for (int r = 0; r <= m; ++r) acc = cadd(acc, cjmul(dv[r], coef[ns * (m + 1) + r]));
+            }
+            a.cnew[i] = acc;
+        }
+        return;
+    }
+
+    // ---------------- shift `role`: [H - sigma_i I_bar | c | s]
+    const int i = role;
+    if (i >= ns) return;
+    const double2 si = sig[i];
+    const double2 bi = beta[i];
+    for (int c = 0; c < p + 2; ++c)
+        for (int r = lane; r <= p; r += 64) {
+            double2 v;
+            if (c < p) {
+                v = H[c * ldh + r];
+                if (r == c) v = csub(v, si);
+            } else if (c == p) {
+                v = cg[r];
+            } else {
+                v = sv[r];
+            }
+            AT(A, r, c) = v;
+        }
+    __syncthreads();
+    hh_qr(A, p + 1, p, p + 2, hv);
+    double2 bnew;
+    bool bad = false;
+    if (exact) {
+        bnew = mk(0, 0);
+    } else {
+        const double2 qc = AT(A, p, p), qs = AT(A, p, p + 1);
+        if (!(cabs(qs) > 1e-14 * sn)) bad = true;
+        bnew = cmul(bi, cdiv(qc, qs));
+    }
+    for (int r = lane; r < p; r += 64)
+        dv[r] = csub(cmul(bi, AT(A, r, p)), cmul(bnew, AT(A, r, p + 1)));
+    __syncthreads();
+    if (!back_sub(A, p, dv)) bad = true;
+    for (int r = lane; r <= m; r += 64) coef[i * (m + 1) + r] = r < p ? dv[r] : mk(0, 0);
+    if (lane == 0) {
+        out->beta[i] = bnew;
+        if (bad) atomicOr(&out->flags, 1);
+    }
+}
+
+void cycle_small(const CycleArgs& a, int nmem, hipStream_t st) {
+    hipLaunchKernelGGL(k_cycle_small, dim3(a.ns, nmem), dim3(64), 0, st, a);
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_proj_small(ProjArgs a) {
+    const int lane = threadIdx.x;
+    const int b = blockIdx.x;
+    if (a.act && !a.act[b]) return;
+    const int k = a.k;
+    const int ns = a.ns;
+    const int ldk = k + 1;
+    const double2* C = a.C + b * a.c_ms;
+    const double2* sig = a.sigma + b * a.sig_ms;
+    const double2* beta = a.beta + b * a.beta_ms;
+    double2* gam = a.gam + b * a.gam_ms;
+    double2* coef = a.coef + b * a.coef_ms;
+    __shared__ double2 A[(MAXM + 2) * LD];
+    __shared__ double2 hv[LD + 1], d1[LD + 1], y[LD + 1], di[LD + 1];
+    const double2 s1 = sig[0];
+    // [Hk - sigma_1 I_bar | C]
+    for (int c = 0; c <= k; ++c)
+        for (int r = lane; r <= k; r += 64) {
+            double2 v = c < k ? a.Hk[c * ldk + r] : C[r];
+            if (c < k && r == c) v = csub(v, s1);
+            AT(A, r, c) = v;
+        }
+    __syncthreads();
+    hh_qr(A, k + 1, k, k + 1, hv);
+    for (int r = lane; r < k; r += 64) d1[r] = AT(A, r, k);
+    __syncthreads();
+    bool bad = !back_sub(A, k, d1);
+    // y = (Hk - sigma_1 I_bar) d1
+    for (int r = lane; r <= k; r += 64) {
+        double2 acc = mk(0, 0);
+        for (int c = 0; c < k; ++c) {
+            double2 h = a.Hk[c * ldk + r];
+            if (r == c) h = csub(h, s1);
+            acc = cadd(acc, cmul(h, d1[c]));
+        }
+        y[r] = acc;
+    }
+    __syncthreads();
+    for (int r = lane; r <= k; r += 64) {
+        coef[r] = r < k ? d1[r] : mk(0, 0);
+        coef[ns * (k + 1) + r] = mk(-y[r].x, -y[r].y);
+    }
+    for (int i = 1; i < ns; ++i) {
+        const double2 si = sig[i], bi = beta[i];
+        __syncthreads();
+        for (int c = 0; c <= k; ++c)
+            for (int r = lane; r < k; r += 64) {
+                double2 v;
+                if (c < k) {
+                    v = a.Hk[c * ldk + r];
+                    if (r == c) v = csub(v, si);
+                } else {
+                    v = cmul(bi, y[r]);
+                }
+                AT(A, r, c) = v;
+            }
+        __syncthreads();
+        hh_qr(A, k, k, k + 1, hv);
+        for (int r = lane; r < k; r += 64) di[r] = AT(A, r, k);
+        __syncthreads();
+        if (!back_sub(A, k, di)) bad = true;
+        // gamma_i += h_{k+1,:} (beta_i d1 - d_i)
+        double2 g = mk(0, 0);
+        for (int c = lane; c < k; c += 64)
+            g = cadd(g, cmul(a.Hk[c * ldk + k], csub(cmul(bi, d1[c]), di[c])));
+        g = mk(wred(g.x), wred(g.y));
+        for (int r = lane; r <= k; r += 64) coef[i * (k + 1) + r] = r < k ? di[r] : mk(0, 0);
+        if (lane == 0) gam[i] = cadd(gam[i], g);
+    }
+    if (lane == 0 && bad) a.flags[b] |= 1;
+}
+
+void proj_small(const ProjArgs& a, int nmem, hipStream_t st) {
+    hipLaunchKernelGGL(k_proj_small, dim3(nmem), dim3(64), 0, st, a);
+}
+
+}  // namespace gdr

@@ -1,0 +1,285 @@
+"""Thin ctypes binding of libgdr.so (include/gdr.h): same names, argument
+marshalling only. Device vectors are torch tensors (complex128, on the GPU)
+passed by data pointer; torch supplies device memory and the stream.
+
+Every numerical step runs in the HIP library; if the library is missing the
+import fails loudly.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgdr.so")
+
+GDR_OK = 0
+GDR_NOT_CONVERGED = 1
+GDR_ERR_ARG = -1
+GDR_ERR_HIP = -2
+GDR_ERR_OOM = -3
+GDR_ERR_BREAKDOWN = -4
+GDR_ERR_STATE = -5
+GDR_PREC_F64 = 0
+GDR_PREC_MIXED = 1
+GDR_PREC_F32 = 1
+GDR_LINKS_F64 = 0
+GDR_LINKS_F32 = 1
+GDR_LINKS_F16 = 2
+
+SYMBOLS = [
+    "gdr_ctx_create", "gdr_ctx_destroy", "gdr_last_error", "gdr_wilson_create",
+    "gdr_op_destroy", "gdr_op_size", "gdr_op_apply", "gdr_op_tables", "gdr_params_default",
+    "gdr_solve_dr_sh", "gdr_solve_proj_sh", "gdr_solve", "gdr_defl_k", "gdr_defl_export",
+    "gdr_defl_import", "gdr_defl_destroy",
+]
+
+
+class gdr_c64(ctypes.Structure):
+    _fields_ = [("re", ctypes.c_double), ("im", ctypes.c_double)]
+
+
+class gdr_params(ctypes.Structure):
+    _fields_ = [("m_dr", ctypes.c_int), ("k", ctypes.c_int), ("m_proj", ctypes.c_int),
+                ("tol", ctypes.c_double), ("tol_extra", ctypes.c_double),
+                ("max_cycles", ctypes.c_int), ("precision", ctypes.c_int),
+                ("batch", ctypes.c_int), ("related_rhs", ctypes.c_int),
+                ("max_refine", ctypes.c_int)]
+
+
+class gdr_stats(ctypes.Structure):
+    _fields_ = [("cycles_dr", ctypes.c_int), ("cycles_extra", ctypes.c_int),
+                ("cycles_proj", ctypes.c_int), ("cycles_cleanup", ctypes.c_int),
+                ("mvp_dr", ctypes.c_int64), ("mvp_extra", ctypes.c_int64),
+                ("mvp_proj", ctypes.c_int64), ("mvp_fp64", ctypes.c_int64),
+                ("mvp_cleanup", ctypes.c_int64), ("t_total", ctypes.c_double),
+                ("t_phase", ctypes.c_double * 8), ("resid", ctypes.POINTER(ctypes.c_double)),
+                ("hist", ctypes.POINTER(ctypes.c_double)), ("hist_cap", ctypes.c_int),
+                ("hist_len", ctypes.c_int), ("theta", ctypes.POINTER(gdr_c64)),
+                ("theta_cap", ctypes.c_int), ("theta_len", ctypes.c_int)]
+
+
+class GdrError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("gdr error %d: %s" % (code, msg))
+        self.code = code
+
+
+def load(path=LIB_PATH):
+    if not os.path.exists(path):
+        raise ImportError("libgdr.so not built: run paper_0707_0502_amd.build (%s)" % path)
+    lib = ctypes.CDLL(path)
+    vp, ip, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
+    lib.gdr_ctx_create.argtypes = [ip, vp, ctypes.POINTER(vp)]
+    lib.gdr_ctx_destroy.argtypes = [vp]
+    lib.gdr_ctx_destroy.restype = None
+    lib.gdr_last_error.argtypes = [vp]
+    lib.gdr_last_error.restype = ctypes.c_char_p
+    lib.gdr_wilson_create.argtypes = [vp, ctypes.POINTER(ip), ctypes.POINTER(ip), ctypes.c_double,
+                                      vp, ip, ip, ctypes.POINTER(vp)]
+    lib.gdr_op_destroy.argtypes = [vp]
+    lib.gdr_op_destroy.restype = None
+    lib.gdr_op_size.argtypes = [vp]
+    lib.gdr_op_size.restype = i64
+    lib.gdr_op_apply.argtypes = [vp, gdr_c64, vp, vp, ip, ip]
+    lib.gdr_op_tables.argtypes = [vp, vp, vp, vp]
+    lib.gdr_params_default.argtypes = [ctypes.POINTER(gdr_params)]
+    lib.gdr_params_default.restype = None
+    lib.gdr_solve_dr_sh.argtypes = [vp, ip, ctypes.POINTER(gdr_c64), vp, vp,
+                                    ctypes.POINTER(gdr_params), ctypes.POINTER(gdr_stats),
+                                    ctypes.POINTER(vp)]
+    lib.gdr_solve_proj_sh.argtypes = [vp, vp, ip, ctypes.POINTER(gdr_c64), ip, vp, vp,
+                                      ctypes.POINTER(gdr_params), ctypes.POINTER(gdr_stats)]
+    lib.gdr_solve.argtypes = [vp, ip, ctypes.POINTER(gdr_c64), ip, vp, vp,
+                              ctypes.POINTER(gdr_params), ctypes.POINTER(gdr_stats)]
+    lib.gdr_defl_k.argtypes = [vp]
+    lib.gdr_defl_export.argtypes = [vp, vp, vp]
+    lib.gdr_defl_import.argtypes = [vp, ip, vp, vp, ip, ctypes.POINTER(vp)]
+    lib.gdr_defl_destroy.argtypes = [vp]
+    lib.gdr_defl_destroy.restype = None
+    return lib
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = load()
+    return _lib
+
+
+def _ptr(t):
+    """Device or host address of a torch tensor / numpy array (contiguous)."""
+    if hasattr(t, "data_ptr"):
+        if not t.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return ctypes.c_void_p(t.data_ptr())
+    if isinstance(t, np.ndarray):
+        if not t.flags["C_CONTIGUOUS"]:
+            raise ValueError("array must be C-contiguous")
+        return ctypes.c_void_p(t.ctypes.data)
+    raise TypeError(type(t))
+
+
+def _sig(sigmas):
+    arr = (gdr_c64 * len(sigmas))()
+    for i, s in enumerate(sigmas):
+        s = complex(s)
+        arr[i] = gdr_c64(s.real, s.imag)
+    return arr
+
+
+class Ctx:
+    def __init__(self, handle):
+        self.h = handle
+
+    def error(self):
+        return lib().gdr_last_error(self.h).decode()
+
+    def check(self, rc):
+        if rc < 0:
+            raise GdrError(rc, self.error())
+        return rc
+
+
+class Op:
+    def __init__(self, ctx, handle, dims):
+        self.ctx, self.h, self.dims = ctx, handle, tuple(dims)
+        self.n = 12 * int(np.prod(dims))
+
+
+class Defl:
+    def __init__(self, op, handle):
+        self.op, self.h = op, handle
+
+
+class Stats:
+    """Caller-owned buffers for gdr_stats (resid, per-cycle history, theta)."""
+
+    def __init__(self, nrhs=1, ns=1, hist_cap=20000, theta_cap=20000):
+        self.resid = np.zeros((nrhs, ns))
+        self.hist_buf = np.zeros((hist_cap, 5))
+        self.theta_buf = np.zeros(theta_cap, dtype=np.complex128)
+        self.s = gdr_stats()
+        self.s.resid = self.resid.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        self.s.hist = self.hist_buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        self.s.hist_cap = hist_cap
+        self.s.theta = ctypes.cast(self.theta_buf.ctypes.data, ctypes.POINTER(gdr_c64))
+        self.s.theta_cap = theta_cap
+
+    @property
+    def hist(self):
+        return self.hist_buf[:self.s.hist_len]
+
+    @property
+    def theta(self):
+        return self.theta_buf[:self.s.theta_len]
+
+    def as_dict(self):
+        s = self.s
+        return dict(cycles_dr=s.cycles_dr, cycles_extra=s.cycles_extra,
+                    cycles_proj=s.cycles_proj, cycles_cleanup=s.cycles_cleanup,
+                    mvp_dr=s.mvp_dr, mvp_extra=s.mvp_extra, mvp_proj=s.mvp_proj,
+                    mvp_fp64=s.mvp_fp64, mvp_cleanup=s.mvp_cleanup, t_total=s.t_total,
+                    t_phase=list(s.t_phase))
+
+
+def gdr_params_default(**kw):
+    p = gdr_params()
+    lib().gdr_params_default(ctypes.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def gdr_ctx_create(device=0, stream=None):
+    h = ctypes.c_void_p()
+    rc = lib().gdr_ctx_create(device, ctypes.c_void_p(stream or 0), ctypes.byref(h))
+    if rc != GDR_OK:
+        raise GdrError(rc, "gdr_ctx_create failed")
+    return Ctx(h)
+
+
+def gdr_ctx_destroy(ctx):
+    lib().gdr_ctx_destroy(ctx.h)
+
+
+def gdr_last_error(ctx):
+    return ctx.error()
+
+
+def gdr_wilson_create(ctx, dims, bc, kappa, links, link_storage=GDR_LINKS_F32):
+    """links: numpy (host) or torch (device) complex128 [4][Lt][Lz][Ly][Lx][3][3]."""
+    d = (ctypes.c_int * 4)(*dims)
+    b = (ctypes.c_int * 4)(*bc)
+    on_dev = int(hasattr(links, "is_cuda") and links.is_cuda)
+    h = ctypes.c_void_p()
+    ctx.check(lib().gdr_wilson_create(ctx.h, d, b, float(kappa), _ptr(links), on_dev,
+                                      link_storage, ctypes.byref(h)))
+    return Op(ctx, h, dims)
+
+
+def gdr_op_destroy(op):
+    lib().gdr_op_destroy(op.h)
+
+
+def gdr_op_size(op):
+    return lib().gdr_op_size(op.h)
+
+
+def gdr_op_apply(op, sigma, x, y, nvec=1, precision=GDR_PREC_F64):
+    s = complex(sigma)
+    return op.ctx.check(lib().gdr_op_apply(op.h, gdr_c64(s.real, s.imag), _ptr(x), _ptr(y),
+                                           nvec, precision))
+
+
+def gdr_op_tables(op):
+    vol = op.n // 12
+    eo = np.zeros(vol, np.int32)
+    nbr = np.zeros((vol, 8), np.int32)
+    sign = np.zeros((vol, 8), np.int8)
+    op.ctx.check(lib().gdr_op_tables(op.h, _ptr(eo), _ptr(nbr), _ptr(sign)))
+    return eo, nbr, sign
+
+
+def gdr_solve_dr_sh(op, sigmas, b, x, params, stats=None, want_defl=True):
+    h = ctypes.c_void_p()
+    rc = op.ctx.check(lib().gdr_solve_dr_sh(
+        op.h, len(sigmas), _sig(sigmas), _ptr(b), _ptr(x), ctypes.byref(params),
+        ctypes.byref(stats.s) if stats else None, ctypes.byref(h) if want_defl else None))
+    return rc, (Defl(op, h) if want_defl and h.value else None)
+
+
+def gdr_solve_proj_sh(op, defl, sigmas, B, X, params, stats=None):
+    nrhs = B.numel() // op.n if hasattr(B, "numel") else B.size // op.n
+    return op.ctx.check(lib().gdr_solve_proj_sh(
+        op.h, defl.h, len(sigmas), _sig(sigmas), nrhs, _ptr(B), _ptr(X), ctypes.byref(params),
+        ctypes.byref(stats.s) if stats else None))
+
+
+def gdr_solve(op, sigmas, B, X, params, stats=None):
+    nrhs = B.numel() // op.n if hasattr(B, "numel") else B.size // op.n
+    return op.ctx.check(lib().gdr_solve(
+        op.h, len(sigmas), _sig(sigmas), nrhs, _ptr(B), _ptr(X), ctypes.byref(params),
+        ctypes.byref(stats.s) if stats else None))
+
+
+def gdr_defl_k(defl):
+    return lib().gdr_defl_k(defl.h)
+
+
+def gdr_defl_export(defl, V=None, Hbar=None):
+    return defl.op.ctx.check(lib().gdr_defl_export(
+        defl.h, _ptr(V) if V is not None else None, _ptr(Hbar) if Hbar is not None else None))
+
+
+def gdr_defl_import(op, k, V, Hbar, precision=GDR_PREC_F64):
+    h = ctypes.c_void_p()
+    op.ctx.check(lib().gdr_defl_import(op.h, k, _ptr(V), _ptr(Hbar), precision, ctypes.byref(h)))
+    return Defl(op, h)
+
+
+def gdr_defl_destroy(defl):
+    lib().gdr_defl_destroy(defl.h)

@@ -1,0 +1,98 @@
+"""GPU parity of the lattice tables and the Wilson-Dirac operator (through
+the C-ABI) against the oracle."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import lattice, wilson
+from tests.gpu_common import ctx, dev, empty, host, make_op, rel, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("dims", [(2, 2, 2, 2), (4, 4, 4, 4), (2, 4, 6, 8), (8, 2, 2, 4)])
+def test_tables_bit_exact(dims):
+    from paper_0707_0502_amd import gdr
+    say("tables", dims)
+    op = make_op(synth.unit_links(dims), 0.1)
+    eo, nbr, sign = gdr.gdr_op_tables(op)
+    e2, n2, s2 = lattice.tables(dims)
+    assert np.array_equal(eo, e2)
+    assert np.array_equal(nbr, n2)
+    assert np.array_equal(sign, s2)
+    gdr.gdr_op_destroy(op)
+
+
+@pytest.mark.parametrize("dims,bc", [((4, 4, 4, 4), (1, 1, 1, -1)), ((2, 4, 6, 8), (1, 1, 1, -1)),
+                                     ((6, 4, 2, 4), (1, -1, 1, 1))])
+def test_apply_matches_oracle(dims, bc):
+    from paper_0707_0502_amd import gdr
+    say("apply", dims, bc)
+    links = synth.gauge_links(dims, 0.5, 3)
+    kappa = 0.137
+    sig = -0.13 + 0.05j
+    X = np.stack([synth.rhs_gaussian(dims, 10 + v).ravel() for v in range(3)])
+    ref = np.stack([wilson.apply_A(links, kappa, x.reshape(dims[::-1] + (4, 3)), sig, bc).ravel()
+                    for x in X])
+    for storage, prec, tol in [(gdr.GDR_LINKS_F32, gdr.GDR_PREC_F64, 1e-14),
+                               (gdr.GDR_LINKS_F32, gdr.GDR_PREC_F32, 1e-6),
+                               (gdr.GDR_LINKS_F16, gdr.GDR_PREC_F32, 2e-3)]:
+        op = make_op(links, kappa, bc, storage)
+        x = dev(X.ravel())
+        y = empty(X.size)
+        gdr.gdr_op_apply(op, sig, x, y, 3, prec)
+        got = host(y).reshape(X.shape)
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        say("  storage", storage, "prec", prec, "max rel err", err)
+        assert err <= tol
+        gdr.gdr_op_destroy(op)
+
+
+def test_apply_many_vectors_and_empty():
+    from paper_0707_0502_amd import gdr
+    dims = (2, 2, 2, 4)
+    links = synth.gauge_links(dims, 0.3, 1)
+    op = make_op(links, 0.12)
+    nv = 19   # more than one launch chunk
+    X = np.stack([synth.rhs_z4(dims, v).ravel() for v in range(nv)])
+    y = empty(X.size)
+    gdr.gdr_op_apply(op, 0.25, dev(X.ravel()), y, nv, gdr.GDR_PREC_F64)
+    got = host(y).reshape(X.shape)
+    for v in range(nv):
+        ref = wilson.apply_A(links, 0.12, X[v].reshape(dims[::-1] + (4, 3)), 0.25).ravel()
+        assert rel(got[v], ref) <= 1e-14
+    assert gdr.gdr_op_apply(op, 0.0, dev(X[0]), empty(X[0].size), 0) == gdr.GDR_OK
+    gdr.gdr_op_destroy(op)
+
+
+def test_gamma5_hermiticity_through_abi():
+    from paper_0707_0502_amd import gdr
+    dims = (4, 4, 4, 4)
+    links = synth.gauge_links(dims, 0.5, 2)
+    op = make_op(links, 0.13)
+    shape = dims[::-1] + (4, 3)
+    x = synth.rhs_gaussian(dims, 1).ravel()
+    yv = synth.rhs_gaussian(dims, 2).ravel()
+    g5 = lambda v: wilson.gamma5_flat(v, shape)
+    a = empty(x.size)
+    gdr.gdr_op_apply(op, 0.0, dev(g5(x)), a)
+    b = empty(x.size)
+    gdr.gdr_op_apply(op, 0.0, dev(yv), b)
+    lhs = np.vdot(yv, g5(host(a)))
+    rhs = np.vdot(host(b), x)
+    assert abs(lhs - rhs) <= 1e-13 * abs(rhs)
+    gdr.gdr_op_destroy(op)
+
+
+def test_bad_operator_arguments():
+    from paper_0707_0502_amd import gdr
+    links = synth.unit_links((2, 2, 2, 2))
+    with pytest.raises(gdr.GdrError) as e:
+        gdr.gdr_wilson_create(ctx(), (3, 2, 2, 2), (1, 1, 1, -1), 0.1, links)
+    assert e.value.code == gdr.GDR_ERR_ARG
+    with pytest.raises(gdr.GdrError) as e:
+        gdr.gdr_wilson_create(ctx(), (2, 2, 2, 2), (1, 1, 1, 0), 0.1, links)
+    assert e.value.code == gdr.GDR_ERR_ARG
+    with pytest.raises(gdr.GdrError) as e:
+        gdr.gdr_wilson_create(ctx(), (2, 2, 2, 2), (1, 1, 1, -1), 0.1, links, 7)
+    assert e.value.code == gdr.GDR_ERR_ARG
