@@ -1,0 +1,229 @@
+#!/usr/bin/env python3
+"""Benchmark of the deflated multi-shift, multi-RHS GMRES hot path on one GPU.
+
+One step = one complete gdr_solve of the workload: GMRES-DR(60,20)-Sh on the
+first right-hand side, the extra right-hand side v_{k+1}, the remaining
+right-hand sides by batched GMRES(40)-Proj(20)-Sh with the correction, and
+the FP64-refined cleanup, all shifts, to a true relative residual of 1e-8.
+Inputs (links, right-hand sides) are synthetic and already resident in HBM
+when the timed region starts.
+
+value = seconds per all-shift solve (one right-hand side, every shift) in
+mixed precision (FP32 matvec / Gram-Schmidt / basis, FP64 small problems,
+accumulation and refinement). The same solve in plain FP64 is timed once for
+the comparison, the dominant kernel class is timed with HIP events on the
+library's stream for the roofline, and the CPU oracle is timed on a bounded
+sample for the cpu_baseline.
+
+usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload C4]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Dslash HBM GB/s; sec per all-shift solve at 1e-8, mixed+batched vs FP64"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def describe(name, cfg):
+    lx, ly, lz, lt = cfg["dims"]
+    kinds = sorted(set(k for k, _ in cfg["rhs"]))
+    return ("%dx%dx%dx%d Wilson-Dirac (n=%d), %d %s RHS x %d shifts, GMRES-DR(%d,%d)-Sh + "
+            "GMRES(%d)-Proj(%d)-Sh batched, tol %g" % (
+                lx, ly, lz, lt, 12 * lx * ly * lz * lt, len(cfg["rhs"]), "/".join(kinds),
+                len(cfg["sigmas"]), cfg["m_dr"], cfg["k"], cfg["m_proj"], cfg["k"], cfg["tol"]))
+
+
+def cpu_baseline(cfg, links, kappa, b, sec_budget, gpu_steps):
+    """Time the oracle's own GMRES-DR-Sh Arnoldi steps on this workload's
+    first right-hand side (a bounded sample), fit t(j) = t_mv + (j+1) t_col
+    and scale to the solve's observed Arnoldi steps per right-hand side."""
+    import numpy as np
+    from oracle import gmres, wilson
+    op = wilson.WilsonOperator(links, kappa)
+    m = cfg["m_dr"]
+    n = op.n
+    V = np.zeros((n, m + 1), dtype=np.complex128)
+    H = np.zeros((m + 1, m), dtype=np.complex128)
+    V[:, 0] = b / np.linalg.norm(b)
+    times = []
+    t_start = time.perf_counter()
+    j = 0
+    while j < m and (time.perf_counter() - t_start) < sec_budget:
+        t0 = time.perf_counter()
+        gmres.arnoldi_step(op, V, H, j)
+        times.append(time.perf_counter() - t0)
+        j += 1
+    js = np.arange(len(times)) + 1.0
+    if len(times) >= 2:
+        t_col, t_mv = np.polyfit(js, np.array(times), 1)
+        t_col = max(t_col, 0.0)
+    else:
+        t_mv, t_col = times[0], 0.0
+    # observed step counts: (number of basis columns at each step) summed
+    cost = sum(t_mv + (jj + 1) * t_col for jj in gpu_steps)
+    threads = os.environ.get("OMP_NUM_THREADS") or str(len(os.sched_getaffinity(0)))
+    return dict(cost=cost, t_mv=t_mv, t_col=t_col, steps=len(times),
+                seconds=time.perf_counter() - t_start, threads=int(threads))
+
+
+def arnoldi_columns(st, cfg, nrhs):
+    """Arnoldi steps of one solve as a list of basis widths j+1 (for the CPU
+    extrapolation), from the library's counters."""
+    m, k, mp = cfg["m_dr"], cfg["k"], cfg["m_proj"]
+    steps = []
+    c = st.s.cycles_dr
+    if c > 0:
+        steps += list(range(0, m))
+        steps += list(range(k, m)) * (c - 1)
+    nproj = st.s.cycles_extra + st.s.cycles_proj + st.s.cycles_cleanup
+    steps += list(range(0, mp)) * nproj
+    return steps
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="C4")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(requested --gpus %d)" % a.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_0707_0502_amd import gdr
+
+    cfg = synth.CONFIGS[a.workload]
+    dims = cfg["dims"]
+    log("bench: workload", a.workload, describe(a.workload, cfg))
+    links = synth.gauge_links(dims, cfg["eps"], cfg["seed"])
+    kappa = synth.kappa(a.workload)
+    B = np.stack([synth.make_rhs(cfg, kd, s).ravel() for kd, s in cfg["rhs"]])
+    sig = list(cfg["sigmas"])
+    nrhs, ns = B.shape[0], len(sig)
+    torch.cuda.init()
+    ctx = gdr.gdr_ctx_create(0, torch.cuda.current_stream().cuda_stream)
+    op = gdr.gdr_wilson_create(ctx, dims, (1, 1, 1, -1), kappa, links, gdr.GDR_LINKS_F32)
+    n = op.n
+    Bd = torch.from_numpy(B.ravel()).cuda()
+    X = torch.zeros(nrhs * ns * n, dtype=torch.complex128, device="cuda")
+    del B
+
+    def params(prec, profile):
+        return gdr.gdr_params_default(m_dr=cfg["m_dr"], k=cfg["k"], m_proj=cfg["m_proj"],
+                                      tol=cfg["tol"], tol_extra=cfg["tol_extra"],
+                                      precision=prec, batch=1, profile=profile)
+
+    pm = params(gdr.GDR_PREC_MIXED, 0xFF)
+    for w in range(a.warmup):
+        st = gdr.Stats(nrhs, ns)
+        rc = gdr.gdr_solve(op, sig, Bd, X, pm, st)
+        log("bench: warmup", w, "rc", rc, "t", round(st.s.t_total, 3), st.as_dict())
+    torch.cuda.synchronize()
+    kern = {}
+    t0 = time.perf_counter()
+    for s in range(a.steps):
+        st = gdr.Stats(nrhs, ns)
+        rc = gdr.gdr_solve(op, sig, Bd, X, pm, st)
+        for name, d in st.kernels().items():
+            e = kern.setdefault(name, dict(ms=0.0, bytes=0.0, flops=0.0, launches=0))
+            for key in e:
+                e[key] += d[key]
+        log("bench: step", s, "rc", rc, "t", round(st.s.t_total, 3))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / a.steps
+    value = ms_per_step / 1e3 / nrhs
+    resid_max = float(st.resid.max())
+    counters = st.as_dict()
+    log("bench: mixed", counters, "max true resid %.3e" % resid_max)
+
+    # dominant kernel class by time, and the Wilson operator's own rate
+    dom = max((k for k in kern if kern[k]["bytes"] > 0), key=lambda k: kern[k]["ms"])
+    kd = kern[dom]
+    achieved = kd["bytes"] / (kd["ms"] * 1e-3) / 1e9
+    ds = kern["dslash"]
+    dslash_gbs = ds["bytes"] / (ds["ms"] * 1e-3) / 1e9 if ds["ms"] > 0 else None
+    total_ms = sum(v["ms"] for v in kern.values())
+
+    fp64 = None
+    if not a.no_fp64:
+        st64 = gdr.Stats(nrhs, ns)
+        X64 = torch.zeros_like(X)
+        torch.cuda.synchronize()
+        tf0 = time.perf_counter()
+        rc64 = gdr.gdr_solve(op, sig, Bd, X64, params(gdr.GDR_PREC_F64, 0), st64)
+        torch.cuda.synchronize()
+        tf = time.perf_counter() - tf0
+        diff = float(torch.linalg.norm(X64 - X) / torch.linalg.norm(X64))
+        fp64 = dict(sec_per_all_shift_solve=tf / nrhs, rc=rc64,
+                    speedup_mixed_vs_fp64=(tf / nrhs) / value,
+                    max_true_resid=float(st64.resid.max()), rel_diff_mixed_vs_fp64=diff,
+                    counters=st64.as_dict())
+        log("bench: fp64", fp64)
+        del X64
+
+    cpu = None
+    if not a.no_cpu:
+        b0 = Bd[:n].cpu().numpy()
+        steps = arnoldi_columns(st, cfg, nrhs)
+        c = cpu_baseline(cfg, links, kappa, b0, a.cpu_seconds, steps)
+        cpu = dict(value=c["cost"] / nrhs, unit="s", cores=c["threads"], kind="oracle",
+                   sample="%d oracle GMRES-DR-Sh Arnoldi steps (matvec + CGS2) on RHS 1 of the "
+                          "same workload in %.1f s; fit t = %.3f s + (j+1) * %.4f s, scaled to the "
+                          "%d Arnoldi steps the GPU solve took, per RHS (extrapolated)"
+                          % (c["steps"], c["seconds"], c["t_mv"], c["t_col"], len(steps)))
+        log("bench: cpu", cpu)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": describe(a.workload, cfg), "name": a.workload,
+                   "precision": "mixed: FP32 matvec/Gram-Schmidt/basis, FP64 small problems, "
+                                "accumulation and refinement",
+                   "nrhs": nrhs, "shifts": ns, "global_batch": nrhs, "parallelism": "1 GPU"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel_share_of_timed_kernel_ms": kd["ms"] / total_ms if total_ms else None},
+        "dslash": {"gbs": dslash_gbs, "frac": (dslash_gbs / HBM_PEAK_GBS) if dslash_gbs else None,
+                   "launches": ds["launches"]},
+        "fp64": fp64,
+        "cpu_baseline": cpu,
+        "max_true_resid": resid_max,
+        "counters": counters,
+        "kernels": kern,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -122,10 +122,22 @@ typedef struct {
     int batch;         /* 1: later RHS run as one batch (one matvec launch per step) */
     int related_rhs;   /* 1: project over earlier solutions first (Sec. 5, eq. (5.2)) */
     int max_refine;    /* mixed precision: cap on refinement rounds of the cleanup */
+    int profile;       /* bitmask of GDR_K_* kernel classes to time with HIP events on the
+                          context stream (0: none); results in gdr_stats.k_* */
 } gdr_params;
 
+/* kernel classes of the profiler (gdr_params.profile bit i = class i) */
+#define GDR_K_DSLASH 0      /* Wilson operator launches (solver and residuals) */
+#define GDR_K_CGS_DOT 1     /* Gram-Schmidt pass 1: h = V^H w */
+#define GDR_K_CGS_UPDOT 2   /* pass 2: w -= V h, h2 = V^H w */
+#define GDR_K_CGS_UPNORM 3  /* pass 3: w -= V h2, ||w|| */
+#define GDR_K_SMALL 4       /* device small dense problems */
+#define GDR_K_COMBINE 5     /* x_i += V d_i, r = V s */
+#define GDR_K_RECOMBINE 6   /* V_{k+1} = V_{m+1} P */
+#define GDR_K_OTHER 7       /* reductions, scaling, conversions */
+
 /* Fill defaults: m_dr 40, k 15, m_proj 40, tol 1e-8, tol_extra sqrt(tol),
- * max_cycles 1000, FP64, batch 1, related 0, max_refine 8. */
+ * max_cycles 1000, FP64, batch 1, related 0, max_refine 8, profile 0. */
 void gdr_params_default(gdr_params* p);
 
 typedef struct {
@@ -145,6 +157,10 @@ typedef struct {
     gdr_c64* theta;      /* caller host array [theta_cap] or NULL: the k harmonic Ritz values
                             kept at every GMRES-DR restart, in selection order */
     int theta_cap, theta_len;
+    double k_ms[8];      /* per kernel class (GDR_K_*) timed with params.profile: total ms */
+    double k_bytes[8];   /* ... algorithmic HBM bytes of those launches (each operand once) */
+    double k_flops[8];   /* ... algorithmic flops */
+    int64_t k_launches[8];
 } gdr_stats;
 
 /* ---------------------------------------------------------------- solvers */

@@ -20,7 +20,7 @@ def rightmost_dense(links, bc=(1, 1, 1, -1)):
     return ev
 
 
-def rightmost_arpack(links, bc=(1, 1, 1, -1), nev=6, ncv=64, tol=1e-8, seed=7):
+def rightmost_arpack(links, bc=(1, 1, 1, -1), nev=6, ncv=64, tol=1e-8, seed=7, maxiter=None):
     lt, lz, ly, lx = links.shape[1:5]
     n = 12 * lx * ly * lz * lt
     shape = (lt, lz, ly, lx, 4, 3)
@@ -31,7 +31,7 @@ def rightmost_arpack(links, bc=(1, 1, 1, -1), nev=6, ncv=64, tol=1e-8, seed=7):
 
     op = sla.LinearOperator((n, n), matvec=mv, dtype=np.complex128)
     v0 = np.random.default_rng(seed).standard_normal(n) + 0j
-    ev = sla.eigs(op, k=nev, which="LR", ncv=ncv, tol=tol, v0=v0,
+    ev = sla.eigs(op, k=nev, which="LR", ncv=ncv, tol=tol, v0=v0, maxiter=maxiter,
                   return_eigenvectors=False)
     return ev
 

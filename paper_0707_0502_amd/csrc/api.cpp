@@ -58,6 +58,10 @@ void stats_reset(gdr_stats* st) {
     for (double& t : st->t_phase) t = 0;
     st->hist_len = 0;
     st->theta_len = 0;
+    for (int i = 0; i < 8; ++i) {
+        st->k_ms[i] = st->k_bytes[i] = st->k_flops[i] = 0;
+        st->k_launches[i] = 0;
+    }
 }
 
 }  // namespace
@@ -105,6 +109,7 @@ void gdr_params_default(gdr_params* p) {
     p->batch = 1;
     p->related_rhs = 0;
     p->max_refine = 8;
+    p->profile = 0;
 }
 
 int gdr_wilson_create(gdr_ctx c, const int dims[4], const int bc[4], double kappa,
@@ -265,7 +270,7 @@ int gdr_solve_dr_sh(gdr_op op, int ns, const gdr_c64* sigma, const gdr_c64* b, g
     double2* beo = mem.get<double2>(n);
     double2* Xeo = mem.get<double2>((size_t)ns * n);
     pack_spinor<double>((const double2*)b, beo, n, op->g, 1, c->st);
-    Stats S{st};
+    Stats S(st, (unsigned)p->profile, c->st);
     gdr_defl_s* d = nullptr;
     bool conv = false;
     Timer tdr;
@@ -276,6 +281,7 @@ int gdr_solve_dr_sh(gdr_op op, int ns, const gdr_c64* sigma, const gdr_c64* b, g
         rc = cleanup(op, d, ns, (const double2*)sigma, 1, beo, Xeo, *p, S);
         if (st) st->t_phase[4] += tc.sec();
     }
+    S.flush();
     finish_stats(op, st, ns, (const double2*)sigma, 1, beo, Xeo, t, 0);
     unpack_spinor<double>(Xeo, n, (double2*)x, op->g, ns, c->st);
     HIPCHK(hipStreamSynchronize(c->st));
@@ -302,13 +308,14 @@ int gdr_solve_proj_sh(gdr_op op, gdr_defl defl, int ns, const gdr_c64* sigma, in
     double2* Beo = mem.get<double2>((size_t)nrhs * n);
     double2* Xeo = mem.get<double2>((size_t)nrhs * ns * n);
     pack_spinor<double>((const double2*)B, Beo, n, op->g, nrhs, c->st);
-    Stats S{st};
+    Stats S(st, (unsigned)p->profile, c->st);
     int rc = solve_proj_batch(op, defl, ns, (const double2*)sigma, nrhs, Beo, Xeo, *p, S);
     if (p->precision == GDR_PREC_MIXED) {
         Timer tc;
         rc = cleanup(op, defl, ns, (const double2*)sigma, nrhs, Beo, Xeo, *p, S);
         if (st) st->t_phase[4] += tc.sec();
     }
+    S.flush();
     finish_stats(op, st, ns, (const double2*)sigma, nrhs, Beo, Xeo, t, 0);
     unpack_spinor<double>(Xeo, n, (double2*)X, op->g, nrhs * ns, c->st);
     HIPCHK(hipStreamSynchronize(c->st));
@@ -332,7 +339,7 @@ int gdr_solve(gdr_op op, int ns, const gdr_c64* sigma, int nrhs, const gdr_c64* 
     double2* Beo = mem.get<double2>((size_t)nrhs * n);
     double2* Xeo = mem.get<double2>((size_t)nrhs * ns * n);
     pack_spinor<double>((const double2*)B, Beo, n, op->g, nrhs, c->st);
-    Stats S{st};
+    Stats S(st, (unsigned)p->profile, c->st);
     gdr_defl_s* d = nullptr;
     bool conv = false;
     Timer tdr;
@@ -354,6 +361,7 @@ int gdr_solve(gdr_op op, int ns, const gdr_c64* sigma, int nrhs, const gdr_c64* 
         rc = cleanup(op, d, ns, (const double2*)sigma, nrhs, Beo, Xeo, *p, S);
         if (st) st->t_phase[4] += tc.sec();
     }
+    S.flush();
     finish_stats(op, st, ns, (const double2*)sigma, nrhs, Beo, Xeo, t, 0);
     unpack_spinor<double>(Xeo, n, (double2*)X, op->g, nrhs * ns, c->st);
     HIPCHK(hipStreamSynchronize(c->st));

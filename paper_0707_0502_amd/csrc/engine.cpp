@@ -33,6 +33,17 @@ static int lst_for(gdr_op_s* op) {
     return std::is_same<T, double>::value ? GDR_LINKS_F64 : op->lst;
 }
 
+// algorithmic bytes of one Wilson launch over nvec vectors: every link and
+// every spinor component once (links shared by the vectors of one launch)
+template <typename T>
+static double dslash_bytes(gdr_op_s* op, int nvec, bool add) {
+    const double vol = op->g.vol;
+    double link = std::is_same<T, double>::value ? 16 : (op->lst == GDR_LINKS_F16 ? 4 : 8);
+    double cs = std::is_same<T, double>::value ? 16 : 8;
+    return vol * (36 * link + nvec * (12 * cs * 2 + (add ? 12 * cs : 0)));
+}
+static double dslash_flops(gdr_op_s* op, int nvec) { return (double)op->g.vol * nvec * 1368.0; }
+
 double vec_norm(gdr_op_s* op, const double2* x) {
     DMem mem;
     hipStream_t st = op->ctx->st;
@@ -70,6 +81,7 @@ struct Arnoldi {
     double2* partial = nullptr;
     int nblk = 0;
     DiagList dl{};
+    Prof* prof = nullptr;
 
     void init(DMem& mem, gdr_op_s* op_, int m_, int nmem_, C* Vbuf, int64_t vms_) {
         op = op_;
@@ -94,22 +106,34 @@ struct Arnoldi {
         }
     }
 
-    void step(int j, const int* act) {
+    void step(int j, const int* act, int nact) {
+        const double cs = sizeof(C);
+        const double dn = (double)n * nact;
         for (int b0 = 0; b0 < nmem; b0 += DSLASH_MAXV) {
             const int nb = std::min(DSLASH_MAXV, nmem - b0);
+            prof->begin(GDR_K_DSLASH);
             dslash<T>(V + b0 * vms + (int64_t)j * n, vms, w + b0 * n, n, nullptr, 0,
                       links_for<T>(op), lst_for<T>(op), op->g, op->kappa, dl, nb, st,
                       act ? act + b0 : nullptr);
+            const int na = std::min(nb, nact - std::min(nact, b0));
+            prof->end(GDR_K_DSLASH, dslash_bytes<T>(op, na, false), dslash_flops(op, na));
         }
         double2* Hj = H + (int64_t)j * (m + 1);
+        const double nc = j + 1;
+        prof->begin(GDR_K_CGS_DOT);
         cgs_pass<T, T>(CGS_DOT, V, n, vms, j + 1, w, n, nullptr, 0, nullptr, 0, partial, nblk, n,
                        nmem, st, act);
+        prof->end(GDR_K_CGS_DOT, dn * (nc * cs + cs), dn * 8 * (nc + 1));
         reduce_cols(partial, nblk, j + 2, Hj, hms, nullptr, 0, nmem, st, act);
+        prof->begin(GDR_K_CGS_UPDOT);
         cgs_pass<T, T>(CGS_UPDATE_DOT, V, n, vms, j + 1, w, n, wd, n, Hj, hms, partial, nblk, n,
                        nmem, st, act);
+        prof->end(GDR_K_CGS_UPDOT, dn * (nc * cs + cs + 16), dn * 16 * nc);
         reduce_cols(partial, nblk, j + 1, h2, 80, Hj, hms, nmem, st, act);
+        prof->begin(GDR_K_CGS_UPNORM);
         cgs_pass<T, T>(CGS_UPDATE_NORM, V, n, vms, j + 1, (const C*)nullptr, 0, wd, n, h2, 80,
                        partial, nblk, n, nmem, st, act);
+        prof->end(GDR_K_CGS_UPNORM, dn * (nc * cs + 32), dn * (8 * nc + 4));
         norm_finish(partial, nblk, H, m + 1, hms, j, Hj + j + 1, hms, inv, brk, 1e-14, nmem, st,
                     act);
         scale_store<T>(wd, n, inv, V + (int64_t)(j + 1) * n, vms, n, nmem, st, act);
@@ -154,6 +178,7 @@ static int dr_run(gdr_op_s* op, int ns, const double2* sig_h, const double2* b_e
     C* Vb = mem.get<C>((size_t)(m + 1) * n);
     Arnoldi<T> A;
     A.init(mem, op, m, 1, Va, 0);
+    A.prof = &S.prof;
     double2* Hn = mem.get<double2>((size_t)(m + 1) * m);
     double2* c0 = mem.get<double2>(m + 1);
     double2* c1 = mem.get<double2>(m + 1);
@@ -207,7 +232,7 @@ static int dr_run(gdr_op_s* op, int ns, const double2* sig_h, const double2* b_e
         A.V = Vc;
         A.H = Hc;
         fill_int(A.brk, -1, 1, st);
-        for (int j = j0; j < m; ++j) A.step(j, nullptr);
+        for (int j = j0; j < m; ++j) A.step(j, nullptr, 1);
         mvps += m - j0;
         HIPCHK(hipMemsetAsync(&outs[cur].flags, 0, sizeof(int), st));
         CycleArgs a{};
@@ -225,15 +250,21 @@ static int dr_run(gdr_op_s* op, int ns, const double2* sig_h, const double2* b_e
         a.cnew = cx;
         a.m = m;
         a.ns = ns;
+        S.prof.begin(GDR_K_SMALL);
         cycle_small(a, 1, st);
+        S.prof.end(GDR_K_SMALL, 0, 0);
+        S.prof.begin(GDR_K_COMBINE);
         vcombine<T>(Vc, n, 0, m, coef, m + 1, 0, ns, X, n, 0, allx, n, 1, st);
+        S.prof.end(GDR_K_COMBINE, (double)n * (m * sizeof(C) + 32.0 * ns), (double)n * m * ns * 8);
         double rtn = 0;
         if (mixed) {
             DiagList dl{};
             dl.d[0] = z(1.0 - sig_h[0].x, -sig_h[0].y);
             dl.alpha[0] = -1;
+            S.prof.begin(GDR_K_DSLASH);
             dslash<double>(X, 0, rtrue, 0, b_eo, 0, op->u64, GDR_LINKS_F64, op->g, op->kappa, dl, 1,
                            st);
+            S.prof.end(GDR_K_DSLASH, dslash_bytes<double>(op, 1, true), dslash_flops(op, 1));
             if (S.st) S.st->mvp_fp64 += 1;
         }
         CycleOut o;
@@ -264,7 +295,10 @@ static int dr_run(gdr_op_s* op, int ns, const double2* sig_h, const double2* b_e
         }
         if (brk >= 0) break;   // lucky breakdown: solved exactly, no deflation space
         S.theta(o.theta, k);
+        S.prof.begin(GDR_K_RECOMBINE);
         vrecombine<T>(Vc, n, m + 1, P, m + 1, k + 1, Vn, n, n, st);
+        S.prof.end(GDR_K_RECOMBINE, (double)n * (m + k + 2) * sizeof(C),
+                   (double)n * (m + 1) * (k + 1) * 8);
         orth_column<T>(op, Vn, k, A.wd, A.partial, A.nblk, tH, tinv, tbrk);
         if (mixed) {
             // residual replacement: coordinates of the FP64 true residual in V_{k+1}
@@ -353,6 +387,7 @@ static void proj_run(gdr_op_s* op, gdr_defl_s* defl, int nmem, int ns,
     C* Vb = mem.get<C>((size_t)vms * nmem);
     Arnoldi<T> A;
     A.init(mem, op, m, nmem, Vb, vms);
+    A.prof = &S.prof;
     double2* sig = mem.get<double2>((size_t)nmem * ns);
     double2* Cb = mem.get<double2>((size_t)80 * nmem);
     double2* cvec = mem.get<double2>((size_t)(m + 1) * nmem);
@@ -394,7 +429,11 @@ static void proj_run(gdr_op_s* op, gdr_defl_s* defl, int nmem, int ns,
     int cur = 1, prv = 0;
     std::vector<CycleOut> oh(nmem);
     std::vector<double2> rnh(nmem);
+    const double cs = sizeof(C);
     for (int cyc = 0; cyc < max_cycles; ++cyc) {
+        int nact0 = 0;
+        for (int b = 0; b < nmem; ++b) nact0 += acth[b];
+        const double dn = (double)n * nact0;
         // ---- minres projection over V_k with v_{k+1} tracking
         if (k > 0) {
             cgs_pass<T, double>(CGS_DOT, Vd, n, 0, k + 1, W + (int64_t)ns * n, wms, nullptr, 0,
@@ -416,9 +455,14 @@ static void proj_run(gdr_op_s* op, gdr_defl_s* defl, int nmem, int ns,
             pa.flags = pflags;
             pa.ns = ns;
             pa.act = act;
+            S.prof.begin(GDR_K_SMALL);
             proj_small(pa, nmem, st);
+            S.prof.end(GDR_K_SMALL, 0, 0);
+            S.prof.begin(GDR_K_COMBINE);
             vcombine<T>(Vd, n, 0, k + 1, coefP, k + 1, cpms, ns + 1, W, n, wms, keep_all, n, nmem,
                         st, act);
+            S.prof.end(GDR_K_COMBINE, dn * ((k + 1) * cs + 32.0 * (ns + 1)),
+                       dn * (k + 1) * (ns + 1) * 8);
         }
         // ---- one GMRES(m)-Sh cycle from r
         cgs_pass<double, double>(CGS_DOT, nullptr, 0, 0, 0, W + (int64_t)ns * n, wms, nullptr, 0,
@@ -427,7 +471,7 @@ static void proj_run(gdr_op_s* op, gdr_defl_s* defl, int nmem, int ns,
         start_cycle(rn2, 1, cvec, m + 1, m, A.inv, nmem, st, act);
         convert_scale<T>(W + (int64_t)ns * n, wms, A.inv, 1, Vb, vms, n, nmem, st, act);
         fill_int(A.brk, -1, nmem, st);
-        for (int j = 0; j < m; ++j) A.step(j, act);
+        for (int j = 0; j < m; ++j) A.step(j, act, nact0);
         HIPCHK(hipMemcpyAsync(outs + cur * nmem, init.data(), nmem * sizeof(CycleOut),
                               hipMemcpyHostToDevice, st));
         CycleArgs a{};
@@ -448,10 +492,15 @@ static void proj_run(gdr_op_s* op, gdr_defl_s* defl, int nmem, int ns,
         a.m = m;
         a.ns = ns;
         a.act = act;
+        S.prof.begin(GDR_K_SMALL);
         cycle_small(a, nmem, st);
+        S.prof.end(GDR_K_SMALL, 0, 0);
         // x_i += V_m d_i ; r = V_{m+1} s
+        S.prof.begin(GDR_K_COMBINE);
         vcombine<T>(Vb, n, vms, m + 1, coefC, m + 1, ccms, ns + 1, W, n, wms, keep_x, n, nmem, st,
                     act);
+        S.prof.end(GDR_K_COMBINE, dn * ((m + 1) * cs + 32.0 * ns + 16),
+                   dn * (m + 1) * (ns + 1) * 8);
         if (mixed) {
             // base residual replaced by the FP64 true residual of shift 1
             for (int b0 = 0; b0 < nmem; b0 += DSLASH_MAXV) {
@@ -462,9 +511,13 @@ static void proj_run(gdr_op_s* op, gdr_defl_s* defl, int nmem, int ns,
                     dl.d[v] = z(1.0 - s1.x, -s1.y);
                     dl.alpha[v] = -1;
                 }
+                const int na = std::min(nb, nact0 - std::min(nact0, b0));
+                S.prof.begin(GDR_K_DSLASH);
                 dslash<double>(W + b0 * wms, wms, W + b0 * wms + (int64_t)ns * n, wms,
                                Bm + b0 * n, n, op->u64, GDR_LINKS_F64, op->g, op->kappa, dl, nb,
                                st, act + b0);
+                S.prof.end(GDR_K_DSLASH, dslash_bytes<double>(op, na, true), dslash_flops(op, na));
+                if (S.st) S.st->mvp_fp64 += na;
             }
             cgs_pass<double, double>(CGS_DOT, nullptr, 0, 0, 0, W + (int64_t)ns * n, wms, nullptr,
                                      0, nullptr, 0, A.partial, A.nblk, n, nmem, st, act);

@@ -71,8 +71,87 @@ struct DMem {
     }
 };
 
+// Optional HIP-event timing of kernel classes (bitmask), on the context
+// stream, with the algorithmic bytes and flops of every timed launch.
+struct Prof {
+    unsigned mask = 0;
+    hipStream_t st = nullptr;
+    struct Rec {
+        int cls;
+        double bytes, flops;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> pend;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t cur = nullptr;
+    double ms[8] = {}, bytes[8] = {}, flops[8] = {};
+    int64_t cnt[8] = {};
+    bool on(int cls) const { return (mask >> cls) & 1u; }
+    hipEvent_t get() {
+        hipEvent_t e;
+        if (!pool.empty()) {
+            e = pool.back();
+            pool.pop_back();
+        } else {
+            HIPCHK(hipEventCreate(&e));
+        }
+        return e;
+    }
+    void begin(int cls) {
+        if (!on(cls)) return;
+        cur = get();
+        HIPCHK(hipEventRecord(cur, st));
+    }
+    void end(int cls, double b, double f) {
+        if (!on(cls)) return;
+        hipEvent_t e = get();
+        HIPCHK(hipEventRecord(e, st));
+        pend.push_back({cls, b, f, cur, e});
+        if (pend.size() > 2048) harvest();
+    }
+    void harvest() {
+        if (pend.empty()) return;
+        HIPCHK(hipEventSynchronize(pend.back().b));
+        for (auto& r : pend) {
+            float t = 0;
+            HIPCHK(hipEventElapsedTime(&t, r.a, r.b));
+            ms[r.cls] += t;
+            bytes[r.cls] += r.bytes;
+            flops[r.cls] += r.flops;
+            cnt[r.cls] += 1;
+            pool.push_back(r.a);
+            pool.push_back(r.b);
+        }
+        pend.clear();
+    }
+    ~Prof() {
+        for (auto& r : pend) {
+            pool.push_back(r.a);
+            pool.push_back(r.b);
+        }
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    }
+};
+
 struct Stats {
     gdr_stats* st = nullptr;
+    Prof prof;
+    Stats(gdr_stats* s, unsigned mask, hipStream_t stream) : st(s) {
+        prof.mask = mask;
+        prof.st = stream;
+    }
+    void flush() {
+        prof.harvest();
+        if (!st) return;
+        for (int c = 0; c < 8; ++c) {
+            st->k_ms[c] += prof.ms[c];
+            st->k_bytes[c] += prof.bytes[c];
+            st->k_flops[c] += prof.flops[c];
+            st->k_launches[c] += prof.cnt[c];
+            prof.ms[c] = prof.bytes[c] = prof.flops[c] = 0;
+            prof.cnt[c] = 0;
+        }
+    }
     void hist(int phase, int cycle, int64_t mvps, double r1, double rmax) {
         if (!st || !st->hist || st->hist_len >= st->hist_cap) return;
         double* h = st->hist + 5 * st->hist_len++;

@@ -26,6 +26,8 @@ GDR_PREC_F32 = 1
 GDR_LINKS_F64 = 0
 GDR_LINKS_F32 = 1
 GDR_LINKS_F16 = 2
+K_CLASSES = ["dslash", "cgs_dot", "cgs_update_dot", "cgs_update_norm", "small", "combine",
+             "recombine", "other"]
 
 SYMBOLS = [
     "gdr_ctx_create", "gdr_ctx_destroy", "gdr_last_error", "gdr_wilson_create",
@@ -44,7 +46,7 @@ class gdr_params(ctypes.Structure):
                 ("tol", ctypes.c_double), ("tol_extra", ctypes.c_double),
                 ("max_cycles", ctypes.c_int), ("precision", ctypes.c_int),
                 ("batch", ctypes.c_int), ("related_rhs", ctypes.c_int),
-                ("max_refine", ctypes.c_int)]
+                ("max_refine", ctypes.c_int), ("profile", ctypes.c_int)]
 
 
 class gdr_stats(ctypes.Structure):
@@ -56,7 +58,9 @@ class gdr_stats(ctypes.Structure):
                 ("t_phase", ctypes.c_double * 8), ("resid", ctypes.POINTER(ctypes.c_double)),
                 ("hist", ctypes.POINTER(ctypes.c_double)), ("hist_cap", ctypes.c_int),
                 ("hist_len", ctypes.c_int), ("theta", ctypes.POINTER(gdr_c64)),
-                ("theta_cap", ctypes.c_int), ("theta_len", ctypes.c_int)]
+                ("theta_cap", ctypes.c_int), ("theta_len", ctypes.c_int),
+                ("k_ms", ctypes.c_double * 8), ("k_bytes", ctypes.c_double * 8),
+                ("k_flops", ctypes.c_double * 8), ("k_launches", ctypes.c_int64 * 8)]
 
 
 class GdrError(RuntimeError):
@@ -184,6 +188,11 @@ class Stats:
                     mvp_dr=s.mvp_dr, mvp_extra=s.mvp_extra, mvp_proj=s.mvp_proj,
                     mvp_fp64=s.mvp_fp64, mvp_cleanup=s.mvp_cleanup, t_total=s.t_total,
                     t_phase=list(s.t_phase))
+
+    def kernels(self):
+        s = self.s
+        return {K_CLASSES[i]: dict(ms=s.k_ms[i], bytes=s.k_bytes[i], flops=s.k_flops[i],
+                                   launches=s.k_launches[i]) for i in range(8)}
 
 
 def gdr_params_default(**kw):

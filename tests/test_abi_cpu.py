@@ -41,10 +41,11 @@ def test_struct_layouts_match_header(tmp_path):
 #include <stddef.h>
 #include "gdr.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(gdr_params), sizeof(gdr_stats),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(gdr_params), sizeof(gdr_stats),
          offsetof(gdr_params, tol), offsetof(gdr_params, max_refine),
          offsetof(gdr_stats, mvp_dr), offsetof(gdr_stats, t_phase),
-         offsetof(gdr_stats, resid), offsetof(gdr_stats, theta_len));
+         offsetof(gdr_stats, resid), offsetof(gdr_stats, theta_len),
+         offsetof(gdr_stats, k_ms), offsetof(gdr_stats, k_launches));
   return 0;
 }
 """)
@@ -53,14 +54,15 @@ int main(void) {
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     P, S = gdr.gdr_params, gdr.gdr_stats
     want = [ctypes.sizeof(P), ctypes.sizeof(S), P.tol.offset, P.max_refine.offset,
-            S.mvp_dr.offset, S.t_phase.offset, S.resid.offset, S.theta_len.offset]
+            S.mvp_dr.offset, S.t_phase.offset, S.resid.offset, S.theta_len.offset,
+            S.k_ms.offset, S.k_launches.offset]
     assert got == want
 
 
 def test_params_default_host_only():
     from paper_0707_0502_amd import gdr
     p = gdr.gdr_params_default()
-    assert (p.m_dr, p.k, p.m_proj, p.precision, p.batch) == (40, 15, 40, gdr.GDR_PREC_F64, 1)
+    assert (p.m_dr, p.k, p.m_proj, p.precision, p.batch, p.profile) == (40, 15, 40, gdr.GDR_PREC_F64, 1, 0)
     assert p.tol == 1e-8 and p.tol_extra == 0
 
 
