@@ -124,6 +124,7 @@ typedef struct {
     int max_refine;    /* mixed precision: cap on refinement rounds of the cleanup */
     int profile;       /* bitmask of GDR_K_* kernel classes to time with HIP events on the
                           context stream (0: none); results in gdr_stats.k_* */
+    int m_clean;       /* cycle length of the mixed-precision cleanup solves (0: automatic) */
 } gdr_params;
 
 /* kernel classes of the profiler (gdr_params.profile bit i = class i) */
@@ -137,7 +138,7 @@ typedef struct {
 #define GDR_K_OTHER 7       /* reductions, scaling, conversions */
 
 /* Fill defaults: m_dr 40, k 15, m_proj 40, tol 1e-8, tol_extra sqrt(tol),
- * max_cycles 1000, FP64, batch 1, related 0, max_refine 8, profile 0. */
+ * max_cycles 1000, FP64, batch 1, related 0, max_refine 8, profile 0, m_clean 0. */
 void gdr_params_default(gdr_params* p);
 
 typedef struct {
@@ -161,6 +162,7 @@ typedef struct {
     double k_bytes[8];   /* ... algorithmic HBM bytes of those launches (each operand once) */
     double k_flops[8];   /* ... algorithmic flops */
     int64_t k_launches[8];
+    double resid_main;   /* mixed precision: largest true relative residual before the cleanup */
 } gdr_stats;
 
 /* ---------------------------------------------------------------- solvers */

@@ -39,6 +39,10 @@ bool check_params(gdr_ctx_s* c, const gdr_params* p, int ns, bool need_dr) {
         c->err = "need 1 <= m_proj <= 64";
         return false;
     }
+    if (p->m_clean < 0 || p->m_clean > MAXM) {
+        c->err = "need 0 <= m_clean <= 64";
+        return false;
+    }
     if (!(p->tol > 0) || p->max_cycles < 1 || p->max_refine < 0) {
         c->err = "need tol > 0, max_cycles >= 1, max_refine >= 0";
         return false;
@@ -62,6 +66,7 @@ void stats_reset(gdr_stats* st) {
         st->k_ms[i] = st->k_bytes[i] = st->k_flops[i] = 0;
         st->k_launches[i] = 0;
     }
+    st->resid_main = 0;
 }
 
 }  // namespace
@@ -110,6 +115,7 @@ void gdr_params_default(gdr_params* p) {
     p->related_rhs = 0;
     p->max_refine = 8;
     p->profile = 0;
+    p->m_clean = 0;
 }
 
 int gdr_wilson_create(gdr_ctx c, const int dims[4], const int bc[4], double kappa,

@@ -826,7 +826,10 @@ int cleanup(gdr_op_s* op, gdr_defl_s* defl, int ns, const double2* sig, int nrhs
     std::vector<double> bn(nrhs);
     for (int j = 0; j < nrhs; ++j) bn[j] = vec_norm(op, B_eo + (int64_t)j * n);
     bool done = false;
-    for (int round = 0; round < p.max_refine && !done; ++round) {
+    // the residuals left by the FP32 phases are already small and the
+    // deflation space is reused: short cycles reach the needed reduction
+    const int mc = p.m_clean > 0 ? p.m_clean : std::min(p.m_proj, 16);
+    for (int round = 0; round <= p.max_refine && !done; ++round) {
         // pairs above tolerance
         struct Pair { int j, i; double res; };
         std::vector<Pair> todo;
@@ -836,11 +839,12 @@ int cleanup(gdr_op_s* op, gdr_defl_s* defl, int ns, const double2* sig, int nrhs
             if (S.st) S.st->mvp_fp64 += ns;
             for (int i = 0; i < ns; ++i) {
                 const double rel = bn[j] > 0 ? rn[i] / bn[j] : 0;
+                if (round == 0 && S.st) S.st->resid_main = std::max(S.st->resid_main, rel);
                 if (rel > p.tol) todo.push_back({j, i, rel});
             }
         }
-        if (todo.empty()) {
-            done = true;
+        if (todo.empty() || round == p.max_refine) {
+            done = todo.empty();
             break;
         }
         for (size_t pos = 0; pos < todo.size(); pos += 16) {
@@ -861,9 +865,9 @@ int cleanup(gdr_op_s* op, gdr_defl_s* defl, int ns, const double2* sig, int nrhs
             }
             ProjResult Rr;
             if (defl && defl->prec == GDR_PREC_F64)
-                proj_run<double>(op, defl, nmem, 1, sgm, Bm, W, tol, bnorm, p.m_proj, p.max_cycles, S, phase, Rr);
+                proj_run<double>(op, defl, nmem, 1, sgm, Bm, W, tol, bnorm, mc, p.max_cycles, S, phase, Rr);
             else
-                proj_run<float>(op, defl, nmem, 1, sgm, Bm, W, tol, bnorm, p.m_proj, p.max_cycles, S, phase, Rr);
+                proj_run<float>(op, defl, nmem, 1, sgm, Bm, W, tol, bnorm, mc, p.max_cycles, S, phase, Rr);
             for (int b = 0; b < nmem; ++b) {
                 const Pair& q = todo[pos + b];
                 axpy_dev(X_eo + ((int64_t)q.j * ns + q.i) * n, 0, W + (int64_t)b * 2 * n, 0,

@@ -46,7 +46,8 @@ class gdr_params(ctypes.Structure):
                 ("tol", ctypes.c_double), ("tol_extra", ctypes.c_double),
                 ("max_cycles", ctypes.c_int), ("precision", ctypes.c_int),
                 ("batch", ctypes.c_int), ("related_rhs", ctypes.c_int),
-                ("max_refine", ctypes.c_int), ("profile", ctypes.c_int)]
+                ("max_refine", ctypes.c_int), ("profile", ctypes.c_int),
+                ("m_clean", ctypes.c_int)]
 
 
 class gdr_stats(ctypes.Structure):
@@ -60,7 +61,8 @@ class gdr_stats(ctypes.Structure):
                 ("hist_len", ctypes.c_int), ("theta", ctypes.POINTER(gdr_c64)),
                 ("theta_cap", ctypes.c_int), ("theta_len", ctypes.c_int),
                 ("k_ms", ctypes.c_double * 8), ("k_bytes", ctypes.c_double * 8),
-                ("k_flops", ctypes.c_double * 8), ("k_launches", ctypes.c_int64 * 8)]
+                ("k_flops", ctypes.c_double * 8), ("k_launches", ctypes.c_int64 * 8),
+                ("resid_main", ctypes.c_double)]
 
 
 class GdrError(RuntimeError):
@@ -187,7 +189,7 @@ class Stats:
                     cycles_proj=s.cycles_proj, cycles_cleanup=s.cycles_cleanup,
                     mvp_dr=s.mvp_dr, mvp_extra=s.mvp_extra, mvp_proj=s.mvp_proj,
                     mvp_fp64=s.mvp_fp64, mvp_cleanup=s.mvp_cleanup, t_total=s.t_total,
-                    t_phase=list(s.t_phase))
+                    t_phase=list(s.t_phase), resid_main=s.resid_main)
 
     def kernels(self):
         s = self.s
