@@ -414,10 +414,14 @@ int gdr_defl_import(gdr_op op, int k, const gdr_c64* V, const gdr_c64* Hbar, int
     d->prec = precision;
     const int64_t n = op->n;
     if (precision == GDR_PREC_MIXED) {
-        HIPCHK(hipMalloc(&d->V, (size_t)(k + 1) * n * sizeof(float2)));
+        const size_t bytes = (size_t)(k + 1 + BASIS_PAD) * n * sizeof(float2);
+        HIPCHK(hipMalloc(&d->V, bytes));
+        HIPCHK(hipMemsetAsync(d->V, 0, bytes, c->st));
         pack_spinor<float>((const double2*)V, (float2*)d->V, n, op->g, k + 1, c->st);
     } else {
-        HIPCHK(hipMalloc(&d->V, (size_t)(k + 1) * n * sizeof(double2)));
+        const size_t bytes = (size_t)(k + 1 + BASIS_PAD) * n * sizeof(double2);
+        HIPCHK(hipMalloc(&d->V, bytes));
+        HIPCHK(hipMemsetAsync(d->V, 0, bytes, c->st));
         pack_spinor<double>((const double2*)V, (double2*)d->V, n, op->g, k + 1, c->st);
     }
     if (k > 0) {

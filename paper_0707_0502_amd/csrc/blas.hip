@@ -179,23 +179,194 @@ __global__ __launch_bounds__(256) void k_cgs(const typename CT<T>::t* __restrict
     }
 }
 
+// Orders this wavefront's LDS writes before its own later LDS reads (the
+// lanes of one wavefront exchange data through LDS without a block barrier).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// FP32 basis, passes that need V^H w (DOT and UPDATE_DOT). Each wavefront
+// owns 64-row tiles: with lanes = rows it loads the tile's basis entries
+// (one coalesced 512 B segment per column, all columns issued before use,
+// the next tile's loads issued before the current tile's dot products),
+// applies the update w -= V h, and stages the tile in LDS; then with
+// lanes = columns each lane accumulates its column's dot product over the
+// tile's 64 rows, so no cross-lane reduction is needed until the end.
+constexpr int TPAD = MAXM + 1;   // LDS tile row stride (odd: conflict-free both ways)
+constexpr int TW_WAVES = 4;
+
+template <typename TW, int MODE>
+__global__ __launch_bounds__(64 * TW_WAVES) void k_cgs_tile(
+    const float2* __restrict__ V, int64_t ldv, int64_t v_ms, int ncols,
+    const typename CT<TW>::t* __restrict__ win, int64_t win_ms, double2* __restrict__ wd,
+    int64_t wd_ms, const double2* __restrict__ h, int64_t h_ms, double2* __restrict__ partial,
+    int nblk, int64_t n, const int* __restrict__ act) {
+    const int mem = blockIdx.y;
+    if (act && !act[mem]) return;
+    V += mem * v_ms;
+    win += mem * win_ms;
+    if (wd) wd += mem * wd_ms;
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    __shared__ double2 hs[MAXM];
+    __shared__ float2 tile[TW_WAVES][64 * TPAD];
+    __shared__ double2 wp[TW_WAVES][64];
+    __shared__ double2 red[TW_WAVES][MAXM + 1];
+    if (MODE == CGS_UPDATE_DOT)
+        for (int t = threadIdx.x; t < MAXM; t += blockDim.x)
+            hs[t] = t < ncols ? h[mem * h_ms + t] : mk(0, 0);
+    __syncthreads();
+    float2* tl = tile[wv];
+    double2 acc = mk(0, 0);
+    double nacc = 0;
+    const int64_t ntiles = (n + 63) / 64;
+    const int64_t stride = (int64_t)gridDim.x * TW_WAVES;
+    int64_t t = (int64_t)blockIdx.x * TW_WAVES + wv;
+    // Basis allocations carry 8 spare columns, so the loads run in uniform
+    // chunks of 8 columns; rows past n are clamped to a valid row and enter
+    // with weight zero.
+    float2 vr[MAXM];
+    typename CT<TW>::t wn;
+    auto load_tile = [&](int64_t tt) {
+        int64_t i = tt * 64 + lane;
+        if (i >= n) i = n - 1;
+        wn = win[i];
+        const float2* p = V + i;
+#pragma unroll
+        for (int c8 = 0; c8 < MAXM; c8 += 8) {
+            if (c8 < ncols) {
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    vr[c8 + c] = *p;
+                    p += ldv;
+                }
+            }
+        }
+    };
+    if (t < ntiles) load_tile(t);
+    for (; t < ntiles; t += stride) {
+        const int64_t i = t * 64 + lane;
+        const bool ok = i < n;
+        double2 w = ok ? to_d(wn) : mk(0, 0);
+        if (MODE == CGS_DOT) nacc += cabs2(w);
+#pragma unroll
+        for (int c8 = 0; c8 < MAXM; c8 += 8) {
+            if (c8 < ncols) {
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    if (MODE == CGS_UPDATE_DOT) w = csub(w, cmul(to_d(vr[c8 + c]), hs[c8 + c]));
+                    tl[lane * TPAD + c8 + c] = vr[c8 + c];
+                }
+            }
+        }
+        if (MODE == CGS_UPDATE_DOT && ok) wd[i] = w;
+        wp[wv][lane] = ok ? w : mk(0, 0);
+        // prefetch the next tile while this one's dot products run
+        if (t + stride < ntiles) load_tile(t + stride);
+        wave_sync();
+        if (lane < ncols) {
+#pragma unroll 8
+            for (int r = 0; r < 64; ++r) acc = cadd(acc, cjmul(to_d(tl[r * TPAD + lane]), wp[wv][r]));
+        }
+        wave_sync();
+    }
+    if (lane < ncols) red[wv][lane] = acc;
+    if (MODE == CGS_DOT) {
+        nacc = wsum(nacc);
+        if (lane == 0) red[wv][ncols] = mk(nacc, 0);
+    }
+    __syncthreads();
+    const int nval = MODE == CGS_DOT ? ncols + 1 : ncols;
+    for (int c = threadIdx.x; c < nval; c += blockDim.x) {
+        double2 sum = red[0][c];
+        for (int ww = 1; ww < TW_WAVES; ++ww) sum = cadd(sum, red[ww][c]);
+        partial[((int64_t)mem * nval + c) * nblk + blockIdx.x] = sum;
+    }
+}
+
+// Streaming passes without dot products (UPDATE, UPDATE_NORM) for both
+// precisions: lanes = rows, all of a row's basis entries loaded before use.
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void k_cgs_stream(
+    const typename CT<T>::t* __restrict__ V, int64_t ldv, int64_t v_ms, int ncols,
+    const typename CT<T>::t* __restrict__ win, int64_t win_ms, double2* __restrict__ wd,
+    int64_t wd_ms, const double2* __restrict__ h, int64_t h_ms, double2* __restrict__ partial,
+    int nblk, int64_t n, const int* __restrict__ act) {
+    using C = typename CT<T>::t;
+    constexpr int CH = std::is_same<T, float>::value ? 32 : 16;
+    const int mem = blockIdx.y;
+    if (act && !act[mem]) return;
+    V += mem * v_ms;
+    if (win) win += mem * win_ms;
+    wd += mem * wd_ms;
+    __shared__ double2 hs[MAXM];
+    __shared__ double red[4];
+    for (int t = threadIdx.x; t < ncols; t += blockDim.x) hs[t] = h[mem * h_ms + t];
+    __syncthreads();
+    double nacc = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double2 w = win ? to_d(win[i]) : wd[i];
+        for (int c0 = 0; c0 < ncols; c0 += CH) {
+            C vr[CH];
+#pragma unroll
+            for (int c = 0; c < CH; ++c)
+                if (c0 + c < ncols) vr[c] = V[(c0 + c) * ldv + i];
+#pragma unroll
+            for (int c = 0; c < CH; ++c)
+                if (c0 + c < ncols) w = csub(w, cmul(to_d(vr[c]), hs[c0 + c]));
+        }
+        wd[i] = w;
+        if (MODE == CGS_UPDATE_NORM) nacc += cabs2(w);
+    }
+    if (MODE != CGS_UPDATE_NORM) return;
+    nacc = wsum(nacc);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) red[wv] = nacc;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        partial[(int64_t)mem * nblk + blockIdx.x] = mk(red[0] + red[1] + red[2] + red[3], 0);
+}
+
 template <typename T, typename TW>
 void cgs_pass(int mode, const typename CT<T>::t* V, int64_t ldv, int64_t v_mstride, int ncols,
               const typename CT<TW>::t* win, int64_t win_mstride, double2* wd, int64_t wd_mstride,
               const double2* h, int64_t h_mstride, double2* partial, int nblk, int64_t n, int nmem,
               hipStream_t st, const int* act) {
     dim3 grid(nblk, nmem), blk(CGS_BLOCK);
-    constexpr bool cache = std::is_same<T, float>::value;
-#define GDR_CGS(M, CA)                                                                           \
-    hipLaunchKernelGGL((k_cgs<T, TW, M, CA>), grid, blk, 0, st, V, ldv, v_mstride, ncols, win,   \
-                       win_mstride, wd, wd_mstride, h, h_mstride, partial, nblk, n, act)
-    switch (mode) {
-        case CGS_DOT: GDR_CGS(CGS_DOT, false); break;
-        case CGS_UPDATE_DOT: GDR_CGS(CGS_UPDATE_DOT, cache); break;
-        case CGS_UPDATE_NORM: GDR_CGS(CGS_UPDATE_NORM, false); break;
-        default: GDR_CGS(CGS_UPDATE, false); break;
+    if (mode == CGS_UPDATE_NORM || mode == CGS_UPDATE) {
+        // streaming passes read win only as type T (never the FP64 residual)
+        const typename CT<T>::t* wt = (const typename CT<T>::t*)win;
+        if (mode == CGS_UPDATE_NORM)
+            hipLaunchKernelGGL((k_cgs_stream<T, CGS_UPDATE_NORM>), grid, blk, 0, st, V, ldv,
+                               v_mstride, ncols, wt, win_mstride, wd, wd_mstride, h, h_mstride,
+                               partial, nblk, n, act);
+        else
+            hipLaunchKernelGGL((k_cgs_stream<T, CGS_UPDATE>), grid, blk, 0, st, V, ldv, v_mstride,
+                               ncols, wt, win_mstride, wd, wd_mstride, h, h_mstride, partial, nblk,
+                               n, act);
+        return;
     }
+    if constexpr (std::is_same<T, float>::value) {
+        dim3 bt(64 * TW_WAVES);
+        if (mode == CGS_DOT)
+            hipLaunchKernelGGL((k_cgs_tile<TW, CGS_DOT>), grid, bt, 0, st, V, ldv, v_mstride,
+                               ncols, win, win_mstride, wd, wd_mstride, h, h_mstride, partial,
+                               nblk, n, act);
+        else
+            hipLaunchKernelGGL((k_cgs_tile<TW, CGS_UPDATE_DOT>), grid, bt, 0, st, V, ldv,
+                               v_mstride, ncols, win, win_mstride, wd, wd_mstride, h, h_mstride,
+                               partial, nblk, n, act);
+    } else {
+#define GDR_CGS(M)                                                                               \
+    hipLaunchKernelGGL((k_cgs<T, TW, M, false>), grid, blk, 0, st, V, ldv, v_mstride, ncols, win, \
+                       win_mstride, wd, wd_mstride, h, h_mstride, partial, nblk, n, act)
+        if (mode == CGS_DOT) GDR_CGS(CGS_DOT);
+        else GDR_CGS(CGS_UPDATE_DOT);
 #undef GDR_CGS
+    }
 }
 template void cgs_pass<double, double>(int, const double2*, int64_t, int64_t, int, const double2*,
                                        int64_t, double2*, int64_t, const double2*, int64_t,

@@ -63,5 +63,6 @@ constexpr int MAXK = 63;
 constexpr int CGS_GROUP = 16;             // columns reduced together
 constexpr int CGS_MAXG = 5;               // up to 80 reduced columns
 constexpr int CGS_BLOCK = 256;
+constexpr int BASIS_PAD = 8;              // spare zeroed columns after every basis
 
 }  // namespace gdr

@@ -44,6 +44,17 @@ static double dslash_bytes(gdr_op_s* op, int nvec, bool add) {
 }
 static double dslash_flops(gdr_op_s* op, int nvec) { return (double)op->g.vol * nvec * 1368.0; }
 
+// Krylov bases carry BASIS_PAD zeroed spare columns: the Gram-Schmidt
+// kernels load columns in chunks of 8 without per-column guards.
+template <typename T>
+static typename CT<T>::t* alloc_basis(DMem& mem, int cols, int64_t n, hipStream_t st) {
+    using C = typename CT<T>::t;
+    const size_t cnt = (size_t)(cols + BASIS_PAD) * n;
+    C* p = mem.get<C>(cnt);
+    HIPCHK(hipMemsetAsync(p, 0, cnt * sizeof(C), st));
+    return p;
+}
+
 double vec_norm(gdr_op_s* op, const double2* x) {
     DMem mem;
     hipStream_t st = op->ctx->st;
@@ -174,8 +185,8 @@ static int dr_run(gdr_op_s* op, int ns, const double2* sig_h, const double2* b_e
     const int64_t n = op->n;
     const int m = p.m_dr, k = p.k;
     DMem mem;
-    C* Va = mem.get<C>((size_t)(m + 1) * n);
-    C* Vb = mem.get<C>((size_t)(m + 1) * n);
+    C* Va = alloc_basis<T>(mem, m + 1, n, st);
+    C* Vb = alloc_basis<T>(mem, m + 1, n, st);
     Arnoldi<T> A;
     A.init(mem, op, m, 1, Va, 0);
     A.prof = &S.prof;
@@ -326,7 +337,8 @@ static int dr_run(gdr_op_s* op, int ns, const double2* sig_h, const double2* b_e
             d->k = k;
             d->prec = mixed ? GDR_PREC_MIXED : GDR_PREC_F64;
             try {
-                HIPCHK(hipMalloc(&d->V, (size_t)(k + 1) * n * sizeof(C)));
+                HIPCHK(hipMalloc(&d->V, (size_t)(k + 1 + BASIS_PAD) * n * sizeof(C)));
+                HIPCHK(hipMemsetAsync(d->V, 0, (size_t)(k + 1 + BASIS_PAD) * n * sizeof(C), st));
                 HIPCHK(hipMemcpyAsync(d->V, Vn, (size_t)(k + 1) * n * sizeof(C),
                                       hipMemcpyDeviceToDevice, st));
                 if (k > 0) {
@@ -382,9 +394,9 @@ static void proj_run(gdr_op_s* op, gdr_defl_s* defl, int nmem, int ns,
     const int k = defl ? defl->k : 0;
     const C* Vd = defl ? (const C*)defl->V : nullptr;
     DMem mem;
-    const int64_t vms = (int64_t)(m + 1) * n;
+    const int64_t vms = (int64_t)(m + 1 + BASIS_PAD) * n;
     const int64_t wms = (int64_t)(ns + 1) * n;
-    C* Vb = mem.get<C>((size_t)vms * nmem);
+    C* Vb = alloc_basis<T>(mem, (m + 1 + BASIS_PAD) * nmem - BASIS_PAD, n, st);
     Arnoldi<T> A;
     A.init(mem, op, m, nmem, Vb, vms);
     A.prof = &S.prof;
