@@ -42,6 +42,13 @@ __device__ __forceinline__ Z<R> ld(const __half2* p) {
     return {(R)v.x, (R)v.y};
 }
 
+// element at byte offset `off` (32-bit) from a uniform base: lets the
+// compiler use scalar-base + 32-bit vector-offset addressing
+template <typename X>
+__device__ __forceinline__ const X* at(const X* base, unsigned off) {
+    return (const X*)((const char*)base + off);
+}
+
 template <typename TS, typename TL, typename R>
 struct DslashK {
     using C = typename CT<TS>::t;
@@ -55,10 +62,11 @@ struct DslashK {
         const int nb = gridDim.x;
         const int b = blockIdx.x;
         const int lb = (nb % 8 == 0) ? ((b % 8) * (nb / 8) + b / 8) : b;
-        const int tid = lb * blockDim.x + threadIdx.x;
-        if (tid >= g.vol) return;
-        const int p = tid >= g.vh;
-        const int s = tid - p * g.vh;
+        // each block covers one parity, so every base pointer is uniform
+        const int bpp = (g.vh + 255) / 256;
+        const int p = lb >= bpp;
+        const int s = (lb - p * bpp) * 256 + threadIdx.x;
+        if (s >= g.vh) return;
         const int q = 1 - p;
         int c[4];
         {
@@ -80,50 +88,58 @@ struct DslashK {
 #pragma unroll
             for (int a = 0; a < 3; ++a) acc[sp][a] = {0, 0};
 
-#pragma unroll
+        // Spin projection of hop mu with sign sg (-1: forward with 1 - g_mu,
+        // +1: backward with 1 + g_mu) in the chiral basis:
+        //   h0 = psi0 + c0 psi_{p0},  h1 = psi1 + c1 psi_{p1},
+        //   out rows 0,1 += U h0, U h1;  row p0 += conj(c0) U h0;  row p1 += conj(c1) U h1
+        // with (p0, p1) = (3, 2) for mu = x, y and (2, 3) for mu = z, t, and
+        //   mu=x: c0 = c1 = i sg;   mu=y: c0 = -sg, c1 = sg;
+        //   mu=z: c0 = i sg, c1 = -i sg;   mu=t: c0 = c1 = sg.
+#pragma unroll 1
         for (int mu = 0; mu < 4; ++mu) {
+            const int L = g.L[mu];
+            const int cm = mu == 0 ? c[0] : mu == 1 ? c[1] : mu == 2 ? c[2] : c[3];
+            const int up = cm + 1 == L ? 0 : cm + 1;
+            const int dn = cm == 0 ? L - 1 : cm - 1;
+            const bool low = mu < 2;   // (p0, p1) = (3, 2)
 #pragma unroll
             for (int dir = 0; dir < 2; ++dir) {
-                // dir 0: forward hop with (1 - g_mu) U_mu(x); dir 1: backward with (1 + g_mu) U^H
-                int cc[4] = {c[0], c[1], c[2], c[3]};
-                if (dir == 0) {
-                    cc[mu] = (c[mu] + 1 == g.L[mu]) ? 0 : c[mu] + 1;
-                } else {
-                    cc[mu] = (c[mu] == 0) ? g.L[mu] - 1 : c[mu] - 1;
-                }
-                const int sn = (cc[0] >> 1) + g.hx * (cc[1] + g.L[1] * (cc[2] + g.L[2] * cc[3]));
+                const int cn = dir == 0 ? up : dn;
+                const int x = mu == 0 ? cn : c[0];
+                const int y = mu == 1 ? cn : c[1];
+                const int zz = mu == 2 ? cn : c[2];
+                const int tt = mu == 3 ? cn : c[3];
+                const int sn = (x >> 1) + g.hx * (y + g.L[1] * (zz + g.L[2] * tt));
+                const R sg = dir == 0 ? R(-1) : R(1);
+                // c0, c1 as (re, im)
+                R c0r, c0i, c1r, c1i;
+                if (mu == 0) { c0r = 0; c0i = sg; c1r = 0; c1i = sg; }
+                else if (mu == 1) { c0r = -sg; c0i = 0; c1r = sg; c1i = 0; }
+                else if (mu == 2) { c0r = 0; c0i = sg; c1r = 0; c1i = -sg; }
+                else { c0r = sg; c0i = 0; c1r = sg; c1i = 0; }
                 Z<R> ps[4][3];
 #pragma unroll
                 for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-                    for (int a = 0; a < 3; ++a) ps[sp][a] = ld<R>(inq + (sp * 3 + a) * vh + sn);
-                const R sg = dir == 0 ? R(-1) : R(1);
-                Z<R> h0[3], h1[3];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    if (mu == 0) {
-                        h0[a] = zaddi(ps[0][a], ps[3][a], sg);
-                        h1[a] = zaddi(ps[1][a], ps[2][a], sg);
-                    } else if (mu == 1) {
-                        h0[a] = zaxs(ps[0][a], ps[3][a], -sg);
-                        h1[a] = zaxs(ps[1][a], ps[2][a], sg);
-                    } else if (mu == 2) {
-                        h0[a] = zaddi(ps[0][a], ps[2][a], sg);
-                        h1[a] = zaddi(ps[1][a], ps[3][a], -sg);
-                    } else {
-                        h0[a] = zaxs(ps[0][a], ps[2][a], sg);
-                        h1[a] = zaxs(ps[1][a], ps[3][a], sg);
-                    }
-                }
-                // link: forward U_mu(x) from parity p at s; backward U_mu(x-mu) from parity q at sn
+                    for (int a = 0; a < 3; ++a)
+                        ps[sp][a] = ld<R>(at(inq + (sp * 3 + a) * vh, (unsigned)sn * (unsigned)sizeof(C)));
                 const int lp = dir == 0 ? p : q;
                 const int ls = dir == 0 ? s : sn;
-                const TL* lk = links + ((int64_t)(lp * 4 + mu) * 9) * vh + ls;
+                const TL* lk = links + ((int64_t)(lp * 4 + mu) * 9) * vh;
                 Z<R> u[3][3];
 #pragma unroll
                 for (int a = 0; a < 3; ++a)
 #pragma unroll
-                    for (int bb = 0; bb < 3; ++bb) u[a][bb] = ld<R>(lk + (a * 3 + bb) * vh);
+                    for (int bb = 0; bb < 3; ++bb)
+                        u[a][bb] = ld<R>(at(lk + (a * 3 + bb) * vh, (unsigned)ls * (unsigned)sizeof(TL)));
+                Z<R> h0[3], h1[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const Z<R> q0 = low ? ps[3][a] : ps[2][a];
+                    const Z<R> q1 = low ? ps[2][a] : ps[3][a];
+                    h0[a] = {ps[0][a].x + c0r * q0.x - c0i * q0.y, ps[0][a].y + c0r * q0.y + c0i * q0.x};
+                    h1[a] = {ps[1][a].x + c1r * q1.x - c1i * q1.y, ps[1][a].y + c1r * q1.y + c1i * q1.x};
+                }
                 Z<R> g0[3], g1[3];
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
@@ -131,7 +147,7 @@ struct DslashK {
 #pragma unroll
                     for (int bb = 0; bb < 3; ++bb) {
                         // forward: U[a][bb]; backward: conj(U[bb][a])
-                        Z<R> m = dir == 0 ? u[a][bb] : Z<R>{u[bb][a].x, -u[bb][a].y};
+                        const Z<R> m = dir == 0 ? u[a][bb] : Z<R>{u[bb][a].x, -u[bb][a].y};
                         s0.x += m.x * h0[bb].x - m.y * h0[bb].y;
                         s0.y += m.x * h0[bb].y + m.y * h0[bb].x;
                         s1.x += m.x * h1[bb].x - m.y * h1[bb].y;
@@ -144,22 +160,11 @@ struct DslashK {
                 for (int a = 0; a < 3; ++a) {
                     acc[0][a] = zadd(acc[0][a], g0[a]);
                     acc[1][a] = zadd(acc[1][a], g1[a]);
-                    Z<R> r2, r3;
-                    if (mu == 0) {
-                        r2 = zi(g1[a], -sg);
-                        r3 = zi(g0[a], -sg);
-                    } else if (mu == 1) {
-                        r2 = zs(g1[a], sg);
-                        r3 = zs(g0[a], -sg);
-                    } else if (mu == 2) {
-                        r2 = zi(g0[a], -sg);
-                        r3 = zi(g1[a], sg);
-                    } else {
-                        r2 = zs(g0[a], sg);
-                        r3 = zs(g1[a], sg);
-                    }
-                    acc[2][a] = zadd(acc[2][a], r2);
-                    acc[3][a] = zadd(acc[3][a], r3);
+                    // conj(c0) g0 and conj(c1) g1
+                    const Z<R> e0 = {c0r * g0[a].x + c0i * g0[a].y, c0r * g0[a].y - c0i * g0[a].x};
+                    const Z<R> e1 = {c1r * g1[a].x + c1i * g1[a].y, c1r * g1[a].y - c1i * g1[a].x};
+                    acc[2][a] = zadd(acc[2][a], low ? e1 : e0);
+                    acc[3][a] = zadd(acc[3][a], low ? e0 : e1);
                 }
             }
         }
@@ -190,8 +195,11 @@ struct DslashK {
     }
 };
 
+template <typename TS> struct DslashOcc { static constexpr int waves = 4; };
+template <> struct DslashOcc<double> { static constexpr int waves = 2; };
+
 template <typename TS, typename TL, typename R>
-__global__ __launch_bounds__(256) void k_dslash(const typename CT<TS>::t* __restrict__ in,
+__global__ __launch_bounds__(256, DslashOcc<TS>::waves) void k_dslash(const typename CT<TS>::t* __restrict__ in,
                                                 int64_t in_stride, typename CT<TS>::t* __restrict__ out,
                                                 int64_t out_stride,
                                                 const typename CT<TS>::t* __restrict__ add,
@@ -207,7 +215,7 @@ void dslash(const typename CT<TS>::t* in, int64_t in_stride, typename CT<TS>::t*
             int64_t out_stride, const typename CT<TS>::t* add, int64_t add_stride,
             const void* links, int link_storage, const Geom& g, double kappa, const DiagList& dl,
             int nvec, hipStream_t st, const int* act) {
-    dim3 grid((g.vol + 255) / 256, nvec);
+    dim3 grid(2 * ((g.vh + 255) / 256), nvec);
     if constexpr (std::is_same<TS, double>::value) {
         hipLaunchKernelGGL((k_dslash<double, double2, double>), grid, dim3(256), 0, st, in,
                            in_stride, out, out_stride, add, add_stride, (const double2*)links, g,
