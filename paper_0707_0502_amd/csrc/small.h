@@ -13,6 +13,7 @@ struct CycleOut {
     int pad;
     double2 beta[MAXNS];        // beta_i^new
     double2 theta[MAXM];        // kept harmonic Ritz values (restart only)
+    long long tclk[8];          // restart phase timestamps (wall_clock64 ticks)
 };
 
 struct CycleArgs {

@@ -175,9 +175,48 @@ __device__ void hessenberg(double2* T, double2* Z, int nn, double2* hv) {
     }
 }
 
+// Givens parameters with plain sqrt/division (the small matrices are well
+// scaled): [[c, s], [-conj(s), c]] [x; y] = [r; 0], c real >= 0.
+__device__ __forceinline__ void givens_fast(double2 x, double2 y, double& c, double2& s) {
+    const double ax2 = cabs2(x), ay2 = cabs2(y);
+    if (ay2 == 0.0) {
+        c = 1.0;
+        s = mk(0, 0);
+    } else if (ax2 == 0.0) {
+        c = 0.0;
+        s = cscale(cconj(y), 1.0 / sqrt(ay2));
+    } else {
+        const double ax = sqrt(ax2);
+        const double ir = 1.0 / sqrt(ax2 + ay2);
+        c = ax * ir;
+        s = cscale(cmul(x, cconj(y)), ir / ax);
+    }
+}
+
+// Apply the rotations kk = k0..k1-1 (parameters rc/rs[kk]) to columns
+// kk, kk+1 of row r of M, in order, carrying the running entry.
+__device__ __forceinline__ void rot_row_seq(double2* M, int r, int k0, int k1, const double* rc,
+                                            const double2* rs) {
+    if (k0 >= k1) return;
+    double2 a = AT(M, r, k0);
+    for (int kk = k0; kk < k1; ++kk) {
+        const double2 b = AT(M, r, kk + 1);
+        const double c = rc[kk];
+        const double2 sv = rs[kk];
+        AT(M, r, kk) = cadd(cscale(a, c), cjmul(sv, b));
+        a = csub(cscale(b, c), cmul(sv, a));
+    }
+    AT(M, r, k1) = a;
+}
+
 // Complex Schur form of the upper Hessenberg T by single-shift QR with
-// Wilkinson shifts; Z accumulates. Returns 0 on success.
-__device__ int schur(double2* T, double2* Z, int nn) {
+// Wilkinson shifts; Z accumulates. During a bulge-chase sweep only the row
+// updates and the column updates of the 4-row window around the bulge are
+// applied at once; the column updates of the rows above the window and the
+// updates of Z are applied after the sweep, row by row in rotation order
+// (left and right rotations commute, so the result is the same similarity).
+// Returns 0 on success.
+__device__ int schur(double2* T, double2* Z, int nn, double* rc, double2* rs) {
     const int lane = threadIdx.x;
     const double eps = 2.220446049250313e-16;
     double fro = 0;
@@ -188,11 +227,12 @@ __device__ int schur(double2* T, double2* Z, int nn) {
     int hi = nn - 1, iter = 0, total = 0;
     while (hi > 0) {
         if (total > 60 * nn) return 1;
+        // deflation test on squared magnitudes: |t_{l,l-1}|^2 <= eps^2 (|t_{l-1,l-1}|^2 + |t_{l,l}|^2)
         int l = hi;
         for (; l > 0; --l) {
-            double tst = cabs(AT(T, l - 1, l - 1)) + cabs(AT(T, l, l));
-            if (tst == 0.0) tst = fro;
-            if (cabs(AT(T, l, l - 1)) <= eps * tst) break;
+            double tst = cabs2(AT(T, l - 1, l - 1)) + cabs2(AT(T, l, l));
+            if (tst == 0.0) tst = fro * fro;
+            if (cabs2(AT(T, l, l - 1)) <= eps * eps * tst) break;
         }
         __syncthreads();
         if (l > 0 && lane == 0) AT(T, l, l - 1) = mk(0, 0);
@@ -225,34 +265,58 @@ __device__ int schur(double2* T, double2* Z, int nn) {
                 y = AT(T, kk + 1, kk - 1);
             }
             double c;
-            double2 s;
-            givens(x, y, c, s);
+            double2 sv;
+            givens_fast(x, y, c, sv);
+            if (lane == 0) {
+                rc[kk] = c;
+                rs[kk] = sv;
+            }
+            // full row update (lanes = columns); the annihilated bulge entry
+            // is stored as an exact zero
+            const int c0 = kk > lo ? kk - 1 : lo;
+            for (int col = c0 + lane; col < nn; col += 64) {
+                const double2 a = AT(T, kk, col), b = AT(T, kk + 1, col);
+                AT(T, kk, col) = cadd(cscale(a, c), cmul(sv, b));
+                AT(T, kk + 1, col) = (kk > lo && col == kk - 1) ? mk(0, 0) : csub(cscale(b, c), cjmul(sv, a));
+            }
             __syncthreads();
-            rot_rows(T, kk, kk > lo ? kk - 1 : lo, nn, c, s);
-            __syncthreads();
-            rot_cols(T, kk, 0, min(kk + 3, hi + 1), c, s);
-            rot_cols(Z, kk, 0, nn, c, s);
-            __syncthreads();
-            if (kk > lo && lane == 0) AT(T, kk + 1, kk - 1) = mk(0, 0);
+            // column update of the window rows max(lo, kk-1) .. min(kk+2, hi)
+            const int r0 = kk - 1 > lo ? kk - 1 : lo;
+            const int r1 = min(kk + 3, hi + 1);
+            if (lane < r1 - r0) {
+                const int r = r0 + lane;
+                const double2 a = AT(T, r, kk), b = AT(T, r, kk + 1);
+                AT(T, r, kk) = cadd(cscale(a, c), cjmul(sv, b));
+                AT(T, r, kk + 1) = csub(cscale(b, c), cmul(sv, a));
+            }
             __syncthreads();
         }
+        // deferred column updates: row r < lo takes every rotation of the
+        // sweep, row r in [lo, hi] the rotations kk >= r + 2
+        for (int r = lane; r <= hi; r += 64) rot_row_seq(T, r, r < lo ? lo : r + 2, hi, rc, rs);
+        for (int r = lane; r < nn; r += 64) rot_row_seq(Z, r, lo, hi, rc, rs);
+        __syncthreads();
         ++iter;
         ++total;
     }
     return 0;
 }
 
-// swap the adjacent diagonal entries p, p+1 of the triangular T (and Z)
-__device__ void schur_swap(double2* T, double2* Z, int nn, int p) {
+// swap the adjacent diagonal entries p, p+1 of the triangular T; the
+// rotation is recorded in (rc, rs)[slot] for a later batched update of Z
+__device__ void schur_swap(double2* T, int nn, int p, double* rc, double2* rs, int slot) {
     const double2 t11 = AT(T, p, p), t22 = AT(T, p + 1, p + 1), t12 = AT(T, p, p + 1);
     double c;
     double2 s;
-    givens(t12, csub(t22, t11), c, s);
+    givens_fast(t12, csub(t22, t11), c, s);
+    if (threadIdx.x == 0) {
+        rc[slot] = c;
+        rs[slot] = s;
+    }
     __syncthreads();
     rot_rows(T, p, p, nn, c, s);
     __syncthreads();
     rot_cols(T, p, 0, p + 2, c, s);
-    rot_cols(Z, p, 0, nn, c, s);
     __syncthreads();
     if (threadIdx.x == 0) {
         AT(T, p, p) = t22;
@@ -283,7 +347,10 @@ __global__ __launch_bounds__(64) void k_cycle_small(CycleArgs a) {
     __shared__ double2 A[(MAXM + 2) * LD];
     __shared__ double2 Zs[MAXM * LD];
     __shared__ double2 hv[LD + 1], sv[LD + 1], dv[LD + 1], fv[LD + 1];
+    __shared__ double rotc[MAXM];
+    __shared__ double2 rots[MAXM];
 
+    long long t_start = wall_clock64();
     // ---- base least squares: [Hs | c], Hs = H - sigma_1 I_bar, (p+1) x p
     const double2 s1 = sig[0];
     for (int c = 0; c <= p; ++c)
@@ -330,6 +397,10 @@ __global__ __launch_bounds__(64) void k_cycle_small(CycleArgs a) {
         if (!a.restart || exact || p < m) return;
         // ---------------- GMRES-DR restart (harmonic Ritz, base shift)
         const int k = a.k;
+        if (lane == 0) {
+            out->tclk[0] = t_start;
+            out->tclk[1] = wall_clock64();
+        }
         __syncthreads();
         if (k > 0) {
         // f = Hm^{-H} e_m :  A = [Hm^H | e_m]
@@ -350,6 +421,7 @@ __global__ __launch_bounds__(64) void k_cycle_small(CycleArgs a) {
         for (int r = lane; r < m; r += 64) fv[r] = AT(A, r, m);
         __syncthreads();
         back_sub(A, m, fv);
+        if (lane == 0) out->tclk[2] = wall_clock64();
         const double h2 = cabs2(H[(m - 1) * ldh + m]);
         // G = Hm + h2 f e_m^H  into A (m x m); Z = I
         for (int c = 0; c < m; ++c)
@@ -362,7 +434,9 @@ __global__ __launch_bounds__(64) void k_cycle_small(CycleArgs a) {
             }
         __syncthreads();
         hessenberg(A, Zs, m, hv);
-        int fail = schur(A, Zs, m);
+        if (lane == 0) out->tclk[3] = wall_clock64();
+        int fail = schur(A, Zs, m, rotc, rots);
+        if (lane == 0) out->tclk[4] = wall_clock64();
         if (fail) {
             if (lane == 0) out->flags |= 2;
             return;
@@ -373,11 +447,22 @@ __global__ __launch_bounds__(64) void k_cycle_small(CycleArgs a) {
             for (int j = pos + 1; j < m; ++j)
                 if (key_less(AT(A, j, j), AT(A, best, best))) best = j;
             __syncthreads();
-            for (int q = best - 1; q >= pos; --q) schur_swap(A, Zs, m, q);
+            // swaps q = best-1 .. pos; Z takes them in the same order afterwards
+            for (int q = best - 1; q >= pos; --q) schur_swap(A, m, q, rotc, rots, q);
+            for (int r = lane; r < m; r += 64) {
+                for (int q = best - 1; q >= pos; --q) {
+                    const double2 a = AT(Zs, r, q), b = AT(Zs, r, q + 1);
+                    const double c = rotc[q];
+                    const double2 sq = rots[q];
+                    AT(Zs, r, q) = cadd(cscale(a, c), cjmul(sq, b));
+                    AT(Zs, r, q + 1) = csub(cscale(b, c), cmul(sq, a));
+                }
+            }
             if (lane == 0) out->theta[pos] = AT(A, pos, pos);
             __syncthreads();
         }
         }  // k > 0
+        if (lane == 0) out->tclk[5] = wall_clock64();
         // p_{k+1}: s orthogonalised twice against [Z_k; 0], normalised
         for (int rep = 0; rep < 2; ++rep) {
             for (int j = lane; j < k; j += 64) {
@@ -434,6 +519,7 @@ __global__ __launch_bounds__(64) void k_cycle_small(CycleArgs a) {
             }
             a.cnew[i] = acc;
         }
+        if (lane == 0) out->tclk[6] = wall_clock64();
         return;
     }
 

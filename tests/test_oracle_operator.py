@@ -118,3 +118,13 @@ def test_kappa_c_arpack_matches_dense():
     kd = kappa.kappa_c_from_eigs(kappa.rightmost_dense(u))
     ka = kappa.kappa_c_from_eigs(kappa.rightmost_arpack(u, ncv=40))
     assert abs(kd - ka) < 1e-9 * kd
+
+
+def test_kappa_c_restarted_arnoldi_matches_dense():
+    """The large-lattice estimate (restarted Arnoldi on D) agrees with the
+    dense spectrum's rightmost eigenvalue."""
+    u = synth.gauge_links((2, 4, 2, 4), 0.5, 1)
+    kd = kappa.kappa_c_from_eigs(kappa.rightmost_dense(u))
+    ev, res = kappa.rightmost_restarted_arnoldi(u, m=40, restarts=6)
+    ka = kappa.kappa_c_from_eigs(ev)
+    assert abs(ka - kd) <= 2e-3 * kd
