@@ -175,8 +175,17 @@ __device__ void hessenberg(double2* T, double2* Z, int nn, double2* hv) {
     }
 }
 
-// Givens parameters with plain sqrt/division (the small matrices are well
-// scaled): [[c, s], [-conj(s), c]] [x; y] = [r; 0], c real >= 0.
+// 1/sqrt(a) for normal a > 0: the hardware estimate refined by two Newton
+// steps y <- y (3 - a y^2) / 2 (quadratic convergence to full precision).
+__device__ __forceinline__ double rsqrt_nr(double a) {
+    double y = __builtin_amdgcn_rsq(a);
+    y = y * (1.5 - 0.5 * a * y * y);
+    y = y * (1.5 - 0.5 * a * y * y);
+    return y;
+}
+
+// Givens parameters (the small matrices are well scaled):
+// [[c, s], [-conj(s), c]] [x; y] = [r; 0], c real >= 0.
 __device__ __forceinline__ void givens_fast(double2 x, double2 y, double& c, double2& s) {
     const double ax2 = cabs2(x), ay2 = cabs2(y);
     if (ay2 == 0.0) {
@@ -184,13 +193,21 @@ __device__ __forceinline__ void givens_fast(double2 x, double2 y, double& c, dou
         s = mk(0, 0);
     } else if (ax2 == 0.0) {
         c = 0.0;
-        s = cscale(cconj(y), 1.0 / sqrt(ay2));
+        s = cscale(cconj(y), rsqrt_nr(ay2));
     } else {
-        const double ax = sqrt(ax2);
-        const double ir = 1.0 / sqrt(ax2 + ay2);
-        c = ax * ir;
-        s = cscale(cmul(x, cconj(y)), ir / ax);
+        const double iax = rsqrt_nr(ax2);
+        const double ir = rsqrt_nr(ax2 + ay2);
+        c = ax2 * iax * ir;
+        s = cscale(cmul(x, cconj(y)), ir * iax);
     }
+}
+
+// The small kernels run one wavefront per workgroup: a wave-local fence is
+// enough to order LDS writes before other lanes' reads.
+__device__ __forceinline__ void wsync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Apply the rotations kk = k0..k1-1 (parameters rc/rs[kk]) to columns
@@ -216,14 +233,14 @@ __device__ __forceinline__ void rot_row_seq(double2* M, int r, int k0, int k1, c
 // updates of Z are applied after the sweep, row by row in rotation order
 // (left and right rotations commute, so the result is the same similarity).
 // Returns 0 on success.
-__device__ int schur(double2* T, double2* Z, int nn, double* rc, double2* rs) {
+__device__ int schur(double2* T, double2* Z, int nn, double* rc, double2* rs, long long* nrot) {
     const int lane = threadIdx.x;
     const double eps = 2.220446049250313e-16;
     double fro = 0;
     for (int c = 0; c < nn; ++c)
         for (int r = lane; r < nn; r += 64) fro += cabs2(AT(T, r, c));
     fro = sqrt(wred(fro));
-    __syncthreads();
+    wsync();
     int hi = nn - 1, iter = 0, total = 0;
     while (hi > 0) {
         if (total > 60 * nn) return 1;
@@ -234,9 +251,9 @@ __device__ int schur(double2* T, double2* Z, int nn, double* rc, double2* rs) {
             if (tst == 0.0) tst = fro * fro;
             if (cabs2(AT(T, l, l - 1)) <= eps * eps * tst) break;
         }
-        __syncthreads();
+        wsync();
         if (l > 0 && lane == 0) AT(T, l, l - 1) = mk(0, 0);
-        __syncthreads();
+        wsync();
         if (l == hi) {
             --hi;
             iter = 0;
@@ -279,7 +296,7 @@ __device__ int schur(double2* T, double2* Z, int nn, double* rc, double2* rs) {
                 AT(T, kk, col) = cadd(cscale(a, c), cmul(sv, b));
                 AT(T, kk + 1, col) = (kk > lo && col == kk - 1) ? mk(0, 0) : csub(cscale(b, c), cjmul(sv, a));
             }
-            __syncthreads();
+            wsync();
             // column update of the window rows max(lo, kk-1) .. min(kk+2, hi)
             const int r0 = kk - 1 > lo ? kk - 1 : lo;
             const int r1 = min(kk + 3, hi + 1);
@@ -289,13 +306,14 @@ __device__ int schur(double2* T, double2* Z, int nn, double* rc, double2* rs) {
                 AT(T, r, kk) = cadd(cscale(a, c), cjmul(sv, b));
                 AT(T, r, kk + 1) = csub(cscale(b, c), cmul(sv, a));
             }
-            __syncthreads();
+            wsync();
         }
         // deferred column updates: row r < lo takes every rotation of the
         // sweep, row r in [lo, hi] the rotations kk >= r + 2
+        if (nrot && lane == 0) *nrot += hi - lo;
         for (int r = lane; r <= hi; r += 64) rot_row_seq(T, r, r < lo ? lo : r + 2, hi, rc, rs);
         for (int r = lane; r < nn; r += 64) rot_row_seq(Z, r, lo, hi, rc, rs);
-        __syncthreads();
+        wsync();
         ++iter;
         ++total;
     }
@@ -313,17 +331,17 @@ __device__ void schur_swap(double2* T, int nn, int p, double* rc, double2* rs, i
         rc[slot] = c;
         rs[slot] = s;
     }
-    __syncthreads();
+    wsync();
     rot_rows(T, p, p, nn, c, s);
-    __syncthreads();
+    wsync();
     rot_cols(T, p, 0, p + 2, c, s);
-    __syncthreads();
+    wsync();
     if (threadIdx.x == 0) {
         AT(T, p, p) = t22;
         AT(T, p + 1, p + 1) = t11;
         AT(T, p + 1, p) = mk(0, 0);
     }
-    __syncthreads();
+    wsync();
 }
 
 // ---------------------------------------------------------------------------
@@ -435,7 +453,9 @@ __global__ __launch_bounds__(64) void k_cycle_small(CycleArgs a) {
         __syncthreads();
         hessenberg(A, Zs, m, hv);
         if (lane == 0) out->tclk[3] = wall_clock64();
-        int fail = schur(A, Zs, m, rotc, rots);
+        long long nrot = 0;
+        int fail = schur(A, Zs, m, rotc, rots, &nrot);
+        if (lane == 0) out->tclk[7] = nrot;
         if (lane == 0) out->tclk[4] = wall_clock64();
         if (fail) {
             if (lane == 0) out->flags |= 2;
