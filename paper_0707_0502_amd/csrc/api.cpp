@@ -136,13 +136,8 @@ int gdr_wilson_create(gdr_ctx c, const int dims[4], const int bc[4], double kapp
     API_TRY(c)
     HIPCHK(hipSetDevice(c->device));
     op->ctx = c;
-    for (int mu = 0; mu < 4; ++mu) {
-        op->g.L[mu] = dims[mu];
-        op->bc[mu] = bc[mu];
-    }
-    op->g.vol = (int)vol;
-    op->g.vh = (int)(vol / 2);
-    op->g.hx = dims[0] / 2;
+    for (int mu = 0; mu < 4; ++mu) op->bc[mu] = bc[mu];
+    op->g = make_geom(dims);
     op->kappa = kappa;
     op->n = 12 * vol;
     op->lst = link_storage == GDR_LINKS_F64 ? GDR_LINKS_F32 : link_storage;

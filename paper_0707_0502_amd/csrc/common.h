@@ -8,16 +8,54 @@
 
 namespace gdr {
 
-// Lattice geometry. Internal vectors are even-odd SoA: component c (spin*3 +
-// colour, 0..11) of the site with checkerboard index s on parity p lives at
-// [(p*12 + c)*vh + s]; links at [((p*4 + mu)*9 + a*3 + b)*vh + s] with the
-// boundary factor bc[mu] folded into U_mu(x) on the last slice x_mu = L-1.
+// Lattice geometry. Internal vectors are tile-blocked SoA: the lattice is cut
+// into tiles of b_0 x b_1 x b_2 x b_3 sites (b_mu = 4 where L_mu is a multiple
+// of 4, else 2), tiles are numbered lexicographically (x fastest) and the
+// sites of a tile are stored contiguously, also lexicographically. Component c
+// (spin*3 + colour, 0..11) of site s lives at [c*vol + s]; links at
+// [(mu*9 + a*3 + b)*vol + s] with the boundary factor bc[mu] folded into
+// U_mu(x) on the last slice x_mu = L_mu - 1. The even-odd numbering is kept
+// for the lattice tables only.
 struct Geom {
-    int L[4];   // Lx, Ly, Lz, Lt (all even)
-    int vol;    // sites
-    int vh;     // sites per parity
-    int hx;     // Lx / 2
+    int L[4];    // Lx, Ly, Lz, Lt (all even)
+    int vol;     // sites
+    int vh;      // sites per parity
+    int hx;      // Lx / 2
+    int lb[4];   // log2 of the tile extent per direction (1 or 2)
+    int off[4];  // bit offset of direction mu inside the in-tile index
+    int nt[4];   // tiles per direction
+    int ltv;     // log2 of the tile volume
 };
+
+inline Geom make_geom(const int dims[4]) {
+    Geom g;
+    long long vol = 1;
+    int o = 0;
+    for (int mu = 0; mu < 4; ++mu) {
+        g.L[mu] = dims[mu];
+        vol *= dims[mu];
+        g.lb[mu] = dims[mu] % 4 == 0 ? 2 : 1;
+        g.off[mu] = o;
+        o += g.lb[mu];
+        g.nt[mu] = dims[mu] >> g.lb[mu];
+    }
+    g.ltv = o;
+    g.vol = (int)vol;
+    g.vh = (int)(vol / 2);
+    g.hx = dims[0] / 2;
+    return g;
+}
+
+// storage index of the site with coordinates c[0..3]
+__host__ __device__ __forceinline__ int site_of(const Geom& g, const int c[4]) {
+    int tile = 0, w = 0;
+#pragma unroll
+    for (int mu = 3; mu >= 0; --mu) {
+        tile = tile * g.nt[mu] + (c[mu] >> g.lb[mu]);
+        w |= (c[mu] & ((1 << g.lb[mu]) - 1)) << g.off[mu];
+    }
+    return (tile << g.ltv) | w;
+}
 
 template <typename T> struct CT;
 template <> struct CT<double> { using t = double2; };

@@ -1,14 +1,16 @@
 // Wilson-Dirac matrix-vector product (Sec. 4, Example 7's operator):
 //   out = alpha * ((1 - sigma) in - kappa D in) [+ add]
 //   D psi(x) = sum_mu (1 - g_mu) U_mu(x) psi(x+mu) + (1 + g_mu) U_mu(x-mu)^H psi(x-mu)
-// One thread per lattice site (both parities in one launch), even-odd SoA
-// vectors so every component load is coalesced across a wavefront. Each
-// hop is spin-projected to a 2-spinor, multiplied by the 3x3 link and
-// reconstructed (the rank-2 projectors 1 -/+ g_mu of the chiral basis).
-// The time-boundary factor is folded into the links at pack time. Blocks
-// are remapped so that each XCD (blocks are dealt round-robin over the 8
-// XCDs) works on one contiguous range of sites, keeping neighbour reuse in
-// its own L2.
+// One thread per lattice site on the tile-blocked SoA layout (every
+// component load is a contiguous run across a wavefront). A block covers
+// 256 consecutive sites, i.e. whole tiles; it first stages its own input
+// tile in LDS, so the hops that stay inside a tile read LDS and only the
+// hops across a tile face read global memory. Each hop is spin-projected to
+// a 2-spinor, multiplied by the 3x3 link and reconstructed (the rank-2
+// projectors 1 -/+ g_mu of the chiral basis). The time-boundary factor is
+// folded into the links at pack time. Blocks are remapped so that each XCD
+// (blocks are dealt round-robin over the 8 XCDs) works on one contiguous
+// range of tiles, keeping the cross-face reuse in its own L2.
 #include "kernels.h"
 
 namespace gdr {
@@ -57,36 +59,48 @@ struct DslashK {
                                int64_t out_stride, const C* __restrict__ add, int64_t add_stride,
                                const TL* __restrict__ links, const Geom& g, R kappa,
                                const DiagList& dl, const int* __restrict__ act) {
+        __shared__ C sp[12 * 256];
         const int v = blockIdx.y;
-        if (act && !act[v]) return;
+        if (act && !act[v]) return;   // uniform over the block
         const int nb = gridDim.x;
         const int b = blockIdx.x;
         const int lb = (nb % 8 == 0) ? ((b % 8) * (nb / 8) + b / 8) : b;
-        // each block covers one parity, so every base pointer is uniform
-        const int bpp = (g.vh + 255) / 256;
-        const int p = lb >= bpp;
-        const int s = (lb - p * bpp) * 256 + threadIdx.x;
-        if (s >= g.vh) return;
-        const int q = 1 - p;
-        int c[4];
-        {
-            int r = s / g.hx;
-            int xh = s - r * g.hx;
-            c[1] = r % g.L[1];
-            r /= g.L[1];
-            c[2] = r % g.L[2];
-            c[3] = r / g.L[2];
-            c[0] = 2 * xh + ((p + c[1] + c[2] + c[3]) & 1);
-        }
-        const int64_t vh = g.vh;
+        const int local = threadIdx.x;
+        const int site = lb * 256 + local;
+        const int vol = g.vol;
+        const bool valid = site < vol;   // blocks hold whole tiles: a tile is all valid or all not
+        const int64_t V = vol;
         const C* inv = in + v * in_stride;
-        const C* inq = inv + (int64_t)q * 12 * vh;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            C z;
+            z.x = 0;
+            z.y = 0;
+            sp[c * 256 + local] = valid ? inv[c * V + site] : z;
+        }
+        __syncthreads();
+        if (!valid) return;
+        const int ltv = g.ltv;
+        const int T = site >> ltv;
+        const int w = site & ((1 << ltv) - 1);
+        const int slot = local & ~((1 << ltv) - 1);   // first LDS slot of this tile
+        int tc[4];
+        {
+            int r = T;
+            tc[0] = r % g.nt[0];
+            r /= g.nt[0];
+            tc[1] = r % g.nt[1];
+            r /= g.nt[1];
+            tc[2] = r % g.nt[2];
+            tc[3] = r / g.nt[2];
+        }
+        const int tst[4] = {1, g.nt[0], g.nt[0] * g.nt[1], g.nt[0] * g.nt[1] * g.nt[2]};
 
         Z<R> acc[4][3];
 #pragma unroll
-        for (int sp = 0; sp < 4; ++sp)
+        for (int sp_ = 0; sp_ < 4; ++sp_)
 #pragma unroll
-            for (int a = 0; a < 3; ++a) acc[sp][a] = {0, 0};
+            for (int a = 0; a < 3; ++a) acc[sp_][a] = {0, 0};
 
         // Spin projection of hop mu with sign sg (-1: forward with 1 - g_mu,
         // +1: backward with 1 + g_mu) in the chiral basis:
@@ -97,41 +111,53 @@ struct DslashK {
         //   mu=z: c0 = i sg, c1 = -i sg;   mu=t: c0 = c1 = sg.
 #pragma unroll 1
         for (int mu = 0; mu < 4; ++mu) {
-            const int L = g.L[mu];
-            const int cm = mu == 0 ? c[0] : mu == 1 ? c[1] : mu == 2 ? c[2] : c[3];
-            const int up = cm + 1 == L ? 0 : cm + 1;
-            const int dn = cm == 0 ? L - 1 : cm - 1;
+            const int offm = g.off[mu];
+            const int bm = 1 << g.lb[mu];
+            const int cm = (w >> offm) & (bm - 1);
+            const int ntm = g.nt[mu];
+            const int tcm = mu == 0 ? tc[0] : mu == 1 ? tc[1] : mu == 2 ? tc[2] : tc[3];
+            const int stm = mu == 0 ? tst[0] : mu == 1 ? tst[1] : mu == 2 ? tst[2] : tst[3];
             const bool low = mu < 2;   // (p0, p1) = (3, 2)
+            const TL* lk = links + (int64_t)mu * 9 * V;
 #pragma unroll
             for (int dir = 0; dir < 2; ++dir) {
-                const int cn = dir == 0 ? up : dn;
-                const int x = mu == 0 ? cn : c[0];
-                const int y = mu == 1 ? cn : c[1];
-                const int zz = mu == 2 ? cn : c[2];
-                const int tt = mu == 3 ? cn : c[3];
-                const int sn = (x >> 1) + g.hx * (y + g.L[1] * (zz + g.L[2] * tt));
+                const bool inside = dir == 0 ? cm < bm - 1 : cm > 0;
+                int wn, Tn;
+                if (dir == 0) {
+                    wn = inside ? w + (1 << offm) : w - ((bm - 1) << offm);
+                    Tn = inside ? T : (tcm == ntm - 1 ? T - (ntm - 1) * stm : T + stm);
+                } else {
+                    wn = inside ? w - (1 << offm) : w + ((bm - 1) << offm);
+                    Tn = inside ? T : (tcm == 0 ? T + (ntm - 1) * stm : T - stm);
+                }
+                const int sn = (Tn << ltv) | wn;
                 const R sg = dir == 0 ? R(-1) : R(1);
-                // c0, c1 as (re, im)
                 R c0r, c0i, c1r, c1i;
                 if (mu == 0) { c0r = 0; c0i = sg; c1r = 0; c1i = sg; }
                 else if (mu == 1) { c0r = -sg; c0i = 0; c1r = sg; c1i = 0; }
                 else if (mu == 2) { c0r = 0; c0i = sg; c1r = 0; c1i = -sg; }
                 else { c0r = sg; c0i = 0; c1r = sg; c1i = 0; }
                 Z<R> ps[4][3];
+                if (inside) {
+                    const int li = slot + wn;
 #pragma unroll
-                for (int sp = 0; sp < 4; ++sp)
+                    for (int s_ = 0; s_ < 4; ++s_)
 #pragma unroll
-                    for (int a = 0; a < 3; ++a)
-                        ps[sp][a] = ld<R>(at(inq + (sp * 3 + a) * vh, (unsigned)sn * (unsigned)sizeof(C)));
-                const int lp = dir == 0 ? p : q;
-                const int ls = dir == 0 ? s : sn;
-                const TL* lk = links + ((int64_t)(lp * 4 + mu) * 9) * vh;
+                        for (int a = 0; a < 3; ++a) ps[s_][a] = ld<R>(&sp[(s_ * 3 + a) * 256 + li]);
+                } else {
+#pragma unroll
+                    for (int s_ = 0; s_ < 4; ++s_)
+#pragma unroll
+                        for (int a = 0; a < 3; ++a)
+                            ps[s_][a] = ld<R>(at(inv + (s_ * 3 + a) * V, (unsigned)sn * (unsigned)sizeof(C)));
+                }
+                const int ls = dir == 0 ? site : sn;
                 Z<R> u[3][3];
 #pragma unroll
                 for (int a = 0; a < 3; ++a)
 #pragma unroll
                     for (int bb = 0; bb < 3; ++bb)
-                        u[a][bb] = ld<R>(at(lk + (a * 3 + bb) * vh, (unsigned)ls * (unsigned)sizeof(TL)));
+                        u[a][bb] = ld<R>(at(lk + (a * 3 + bb) * V, (unsigned)ls * (unsigned)sizeof(TL)));
                 Z<R> h0[3], h1[3];
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
@@ -168,29 +194,28 @@ struct DslashK {
                 }
             }
         }
-        const C* inp = inv + (int64_t)p * 12 * vh + s;
-        C* o = out + v * out_stride + (int64_t)p * 12 * vh + s;
-        const C* ad = add ? add + v * add_stride + (int64_t)p * 12 * vh + s : nullptr;
+        C* o = out + v * out_stride + site;
+        const C* ad = add ? add + v * add_stride + site : nullptr;
         const R dre = (R)dl.d[v].x, dim = (R)dl.d[v].y, al = (R)dl.alpha[v];
 #pragma unroll
-        for (int sp = 0; sp < 4; ++sp)
+        for (int s_ = 0; s_ < 4; ++s_)
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                const int comp = sp * 3 + a;
-                Z<R> xi = ld<R>(inp + comp * vh);
-                R re = dre * xi.x - dim * xi.y - kappa * acc[sp][a].x;
-                R im = dre * xi.y + dim * xi.x - kappa * acc[sp][a].y;
+                const int comp = s_ * 3 + a;
+                Z<R> xi = ld<R>(&sp[comp * 256 + local]);
+                R re = dre * xi.x - dim * xi.y - kappa * acc[s_][a].x;
+                R im = dre * xi.y + dim * xi.x - kappa * acc[s_][a].y;
                 re *= al;
                 im *= al;
                 if (ad) {
-                    Z<R> av = ld<R>(ad + comp * vh);
+                    Z<R> av = ld<R>(ad + comp * V);
                     re += av.x;
                     im += av.y;
                 }
-                C w;
-                w.x = re;
-                w.y = im;
-                o[comp * vh] = w;
+                C wv;
+                wv.x = re;
+                wv.y = im;
+                o[comp * V] = wv;
             }
     }
 };
@@ -215,7 +240,7 @@ void dslash(const typename CT<TS>::t* in, int64_t in_stride, typename CT<TS>::t*
             int64_t out_stride, const typename CT<TS>::t* add, int64_t add_stride,
             const void* links, int link_storage, const Geom& g, double kappa, const DiagList& dl,
             int nvec, hipStream_t st, const int* act) {
-    dim3 grid(2 * ((g.vh + 255) / 256), nvec);
+    dim3 grid((g.vol + 255) / 256, nvec);
     if constexpr (std::is_same<TS, double>::value) {
         hipLaunchKernelGGL((k_dslash<double, double2, double>), grid, dim3(256), 0, st, in,
                            in_stride, out, out_stride, add, add_stride, (const double2*)links, g,

@@ -6,13 +6,13 @@
 namespace gdr {
 
 // ------------------------------------------------------------ layout (layout.hip)
-// canonical complex128 [v][t][z][y][x][4][3]  <->  internal even-odd SoA of type T,
-// vector v at eo + v*eo_stride (elements)
+// canonical complex128 [v][t][z][y][x][4][3]  <->  internal tile-blocked SoA of
+// type T, vector v at dst + v*stride (elements)
 template <typename T>
-void pack_spinor(const double2* canon, typename CT<T>::t* eo, int64_t eo_stride, const Geom& g,
+void pack_spinor(const double2* canon, typename CT<T>::t* dst, int64_t stride, const Geom& g,
                  int nvec, hipStream_t st);
 template <typename T>
-void unpack_spinor(const typename CT<T>::t* eo, int64_t eo_stride, double2* canon, const Geom& g,
+void unpack_spinor(const typename CT<T>::t* src, int64_t stride, double2* canon, const Geom& g,
                    int nvec, hipStream_t st);
 // storage: 0 FP64 (double2), 1 FP32 (float2), 2 FP16 (__half2 per complex)
 void pack_links(const double2* canon, void* out, int storage, const Geom& g, const int bc[4],

@@ -1,5 +1,5 @@
-// Canonical <-> even-odd SoA layout conversion, link packing and the
-// lattice tables (checked bit for bit against the oracle's tables).
+// Canonical <-> tile-blocked SoA layout conversion, link packing and the
+// even-odd lattice tables (checked bit for bit against the oracle's tables).
 #include "kernels.h"
 
 namespace gdr {
@@ -23,48 +23,44 @@ __device__ __forceinline__ int eo_of(const Geom& g, int lex, int x, int y, int z
 }
 
 template <typename T>
-__global__ void k_pack_spinor(const double2* __restrict__ canon, typename CT<T>::t* __restrict__ eo,
-                              int64_t eo_stride, Geom g) {
+__global__ void k_pack_spinor(const double2* __restrict__ canon, typename CT<T>::t* __restrict__ dst,
+                              int64_t stride, Geom g) {
     int lex = blockIdx.x * blockDim.x + threadIdx.x;
     int v = blockIdx.y;
     if (lex >= g.vol) return;
-    int x, y, z, t;
-    lex_coords(g, lex, x, y, z, t);
-    int p = (x + y + z + t) & 1;
-    int s = lex >> 1;
+    int c[4];
+    lex_coords(g, lex, c[0], c[1], c[2], c[3]);
     const double2* src = canon + ((int64_t)v * g.vol + lex) * 12;
-    typename CT<T>::t* dst = eo + v * eo_stride + (int64_t)p * 12 * g.vh + s;
+    typename CT<T>::t* d = dst + v * stride + site_of(g, c);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) dst[(int64_t)c * g.vh] = from_d<T>(src[c]);
+    for (int k = 0; k < 12; ++k) d[(int64_t)k * g.vol] = from_d<T>(src[k]);
 }
 
 template <typename T>
-__global__ void k_unpack_spinor(const typename CT<T>::t* __restrict__ eo, int64_t eo_stride,
+__global__ void k_unpack_spinor(const typename CT<T>::t* __restrict__ src, int64_t stride,
                                 double2* __restrict__ canon, Geom g) {
     int lex = blockIdx.x * blockDim.x + threadIdx.x;
     int v = blockIdx.y;
     if (lex >= g.vol) return;
-    int x, y, z, t;
-    lex_coords(g, lex, x, y, z, t);
-    int p = (x + y + z + t) & 1;
-    int s = lex >> 1;
-    const typename CT<T>::t* src = eo + v * eo_stride + (int64_t)p * 12 * g.vh + s;
-    double2* dst = canon + ((int64_t)v * g.vol + lex) * 12;
+    int c[4];
+    lex_coords(g, lex, c[0], c[1], c[2], c[3]);
+    const typename CT<T>::t* s = src + v * stride + site_of(g, c);
+    double2* d = canon + ((int64_t)v * g.vol + lex) * 12;
 #pragma unroll
-    for (int c = 0; c < 12; ++c) dst[c] = to_d(src[(int64_t)c * g.vh]);
+    for (int k = 0; k < 12; ++k) d[k] = to_d(s[(int64_t)k * g.vol]);
 }
 
 template <typename T>
-void pack_spinor(const double2* canon, typename CT<T>::t* eo, int64_t eo_stride, const Geom& g,
+void pack_spinor(const double2* canon, typename CT<T>::t* dst, int64_t stride, const Geom& g,
                  int nvec, hipStream_t st) {
     dim3 grid((g.vol + 255) / 256, nvec);
-    hipLaunchKernelGGL(k_pack_spinor<T>, grid, dim3(256), 0, st, canon, eo, eo_stride, g);
+    hipLaunchKernelGGL(k_pack_spinor<T>, grid, dim3(256), 0, st, canon, dst, stride, g);
 }
 template <typename T>
-void unpack_spinor(const typename CT<T>::t* eo, int64_t eo_stride, double2* canon, const Geom& g,
+void unpack_spinor(const typename CT<T>::t* src, int64_t stride, double2* canon, const Geom& g,
                    int nvec, hipStream_t st) {
     dim3 grid((g.vol + 255) / 256, nvec);
-    hipLaunchKernelGGL(k_unpack_spinor<T>, grid, dim3(256), 0, st, eo, eo_stride, canon, g);
+    hipLaunchKernelGGL(k_unpack_spinor<T>, grid, dim3(256), 0, st, src, stride, canon, g);
 }
 template void pack_spinor<double>(const double2*, double2*, int64_t, const Geom&, int, hipStream_t);
 template void pack_spinor<float>(const double2*, float2*, int64_t, const Geom&, int, hipStream_t);
@@ -75,22 +71,22 @@ struct BC4 {
     int v[4];
 };
 
-// links internal: [p][mu][e = a*3+b][vh], bc[mu] folded into U_mu(x) at x_mu = L_mu - 1
+// links internal: [mu][e = a*3+b][vol] in tile order, bc[mu] folded into
+// U_mu(x) at x_mu = L_mu - 1
 __global__ void k_pack_links(const double2* __restrict__ canon, void* __restrict__ out, int storage,
                              Geom g, BC4 bc) {
     int lex = blockIdx.x * blockDim.x + threadIdx.x;
     if (lex >= g.vol) return;
     int c[4];
     lex_coords(g, lex, c[0], c[1], c[2], c[3]);
-    int p = (c[0] + c[1] + c[2] + c[3]) & 1;
-    int s = lex >> 1;
+    const int s = site_of(g, c);
     for (int mu = 0; mu < 4; ++mu) {
         double f = (c[mu] == g.L[mu] - 1) ? (double)bc.v[mu] : 1.0;
         const double2* src = canon + ((int64_t)mu * g.vol + lex) * 9;
-        int64_t base = ((int64_t)(p * 4 + mu) * 9) * g.vh + s;
+        int64_t base = ((int64_t)mu * 9) * g.vol + s;
         for (int e = 0; e < 9; ++e) {
             double2 u = cscale(src[e], f);
-            int64_t o = base + (int64_t)e * g.vh;
+            int64_t o = base + (int64_t)e * g.vol;
             if (storage == 0) {
                 ((double2*)out)[o] = u;
             } else if (storage == 1) {
