@@ -379,6 +379,262 @@ template void cgs_pass<float, double>(int, const float2*, int64_t, int64_t, int,
                                       int, int64_t, int, hipStream_t, const int*);
 
 // ---------------------------------------------------------------------------
+// Delayed classical Gram-Schmidt (DCGS2) passes of the Arnoldi step.
+//
+// k_gs_dot: one sweep over V forms V_{0..nc-1}^H x_a for NX right-hand
+// vectors x_a, plus ||x_{NX-1}||^2. A block owns a contiguous row range; its
+// four waves split the columns, each wave accumulates up to 8 columns x NX
+// vectors per lane in FP64 over the rows, then a butterfly reduce-scatter
+// over the wavefront leaves one sum per four lanes. Partial sums go to
+// partial[((mem*nval) + a*nc + c)*nblk + blk], nval = NX*nc + 1.
+template <typename T, typename TX, int NX>
+__global__ __launch_bounds__(256) void k_gs_dot(
+    const typename CT<T>::t* __restrict__ V, int64_t ldv, int64_t v_ms, int nc,
+    const typename CT<TX>::t* __restrict__ x0, int64_t x0_ms,
+    const typename CT<TX>::t* __restrict__ x1, int64_t x1_ms, double2* __restrict__ partial,
+    int nblk, int64_t n, const int* __restrict__ act) {
+    const int mem = blockIdx.y;
+    if (act && !act[mem]) return;
+    V += mem * v_ms;
+    x0 += mem * x0_ms;
+    if (NX > 1) x1 += mem * x1_ms;
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int64_t per = ((n + nblk - 1) / nblk + 63) & ~(int64_t)63;
+    const int64_t r0 = (int64_t)blockIdx.x * per;
+    const int64_t r1 = r0 + per < n ? r0 + per : n;
+    const int nval = NX * nc + 1;
+    double2* pout = partial + (int64_t)mem * nval * nblk + blockIdx.x;
+    const int g = (nc + 3) >> 2;
+    const int c0 = wv * g;
+    const int c1 = c0 + g < nc ? c0 + g : nc;
+    for (int cs = c0; cs < c1; cs += 8) {
+        const int cnt = c1 - cs < 8 ? c1 - cs : 8;
+        double2 acc[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc[q] = mk(0, 0);
+        const typename CT<T>::t* vp = V + (int64_t)cs * ldv;
+        for (int64_t i = r0 + lane; i < r1; i += 64) {
+            const double2 xa = to_d(x0[i]);
+            const double2 xb = NX > 1 ? to_d(x1[i]) : mk(0, 0);
+            typename CT<T>::t vr[8];
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                if (c < cnt) vr[c] = vp[(int64_t)c * ldv + i];
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                if (c < cnt) {
+                    const double2 v = to_d(vr[c]);
+                    acc[c] = cadd(acc[c], cjmul(v, xa));
+                    if (NX > 1) acc[8 + c] = cadd(acc[8 + c], cjmul(v, xb));
+                }
+        }
+        const double2 sum = rs16(acc, lane);
+        if ((lane & 3) == 0) {
+            const int q = (lane >> 2) & 15;
+            const int a = q >> 3, c = q & 7;
+            if (c < cnt && a < NX) pout[(int64_t)(a * nc + cs + c) * nblk] = sum;
+        }
+    }
+    if (wv == 3) {
+        const typename CT<TX>::t* xl = NX > 1 ? x1 : x0;
+        double s2 = 0;
+        for (int64_t i = r0 + lane; i < r1; i += 64) s2 += cabs2(to_d(xl[i]));
+        s2 = wsum(s2);
+        if (lane == 0) pout[(int64_t)(NX * nc) * nblk] = mk(s2, 0);
+    }
+}
+
+// k_gs_update: one sweep forms NO outputs
+//   y_o = sum_a beta[o][a] x_a - sum_{c<nc} V_c coef[o][c]
+// with coefficients coef[mem*coef_ms + o*(MAXM+1) + c] and
+// beta[mem*coef_ms + 2*(MAXM+1) + 2*o + a]. y_0 may alias x_0 (each row is
+// read before it is written by the same thread).
+template <typename T, int NX, int NO>
+__global__ __launch_bounds__(256) void k_gs_update(
+    const typename CT<T>::t* __restrict__ V, int64_t ldv, int64_t v_ms, int nc,
+    const typename CT<T>::t* x0, int64_t x0_ms, const typename CT<T>::t* __restrict__ x1,
+    int64_t x1_ms, typename CT<T>::t* y0, int64_t y0_ms, typename CT<T>::t* __restrict__ y1,
+    int64_t y1_ms, const double2* __restrict__ coef, int64_t coef_ms, int64_t n,
+    const int* __restrict__ act) {
+    using C = typename CT<T>::t;
+    constexpr int CH = std::is_same<T, float>::value ? 16 : 8;
+    const int mem = blockIdx.y;
+    if (act && !act[mem]) return;
+    V += mem * v_ms;
+    x0 += mem * x0_ms;
+    y0 += mem * y0_ms;
+    if (NX > 1) x1 += mem * x1_ms;
+    if (NO > 1) y1 += mem * y1_ms;
+    coef += mem * coef_ms;
+    __shared__ double2 cf[NO][MAXM + 1];
+    __shared__ double2 bt[NO][2];
+    for (int t = threadIdx.x; t < nc; t += blockDim.x) {
+        cf[0][t] = coef[t];
+        if (NO > 1) cf[NO - 1][t] = coef[(MAXM + 1) + t];
+    }
+    if (threadIdx.x < 2 * NO) bt[threadIdx.x >> 1][threadIdx.x & 1] = coef[2 * (MAXM + 1) + threadIdx.x];
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double2 xa = to_d(x0[i]);
+        const double2 xb = NX > 1 ? to_d(x1[i]) : mk(0, 0);
+        double2 o0 = cmul(bt[0][0], xa), o1 = mk(0, 0);
+        if (NX > 1) o0 = cadd(o0, cmul(bt[0][1], xb));
+        if (NO > 1) o1 = cadd(cmul(bt[NO - 1][0], xa), cmul(bt[NO - 1][1], xb));
+        for (int cb = 0; cb < nc; cb += CH) {
+            C vr[CH];
+#pragma unroll
+            for (int c = 0; c < CH; ++c)
+                if (cb + c < nc) vr[c] = V[(int64_t)(cb + c) * ldv + i];
+#pragma unroll
+            for (int c = 0; c < CH; ++c)
+                if (cb + c < nc) {
+                    const double2 v = to_d(vr[c]);
+                    o0 = csub(o0, cmul(v, cf[0][cb + c]));
+                    if (NO > 1) o1 = csub(o1, cmul(v, cf[NO - 1][cb + c]));
+                }
+        }
+        y0[i] = from_d<T>(o0);
+        if (NO > 1) y1[i] = from_d<T>(o1);
+    }
+}
+
+template <typename T, typename TX>
+void gs_dot(const typename CT<T>::t* V, int64_t ldv, int64_t v_ms, int nc,
+            const typename CT<TX>::t* x0, int64_t x0_ms, const typename CT<TX>::t* x1,
+            int64_t x1_ms, double2* partial, int nblk, int64_t n, int nmem, hipStream_t st,
+            const int* act) {
+    dim3 grid(nblk, nmem), blk(256);
+    if (x1)
+        hipLaunchKernelGGL((k_gs_dot<T, TX, 2>), grid, blk, 0, st, V, ldv, v_ms, nc, x0, x0_ms, x1,
+                           x1_ms, partial, nblk, n, act);
+    else
+        hipLaunchKernelGGL((k_gs_dot<T, TX, 1>), grid, blk, 0, st, V, ldv, v_ms, nc, x0, x0_ms, x1,
+                           x1_ms, partial, nblk, n, act);
+}
+
+template <typename T>
+void gs_update(const typename CT<T>::t* V, int64_t ldv, int64_t v_ms, int nc,
+               const typename CT<T>::t* x0, int64_t x0_ms, const typename CT<T>::t* x1,
+               int64_t x1_ms, typename CT<T>::t* y0, int64_t y0_ms, typename CT<T>::t* y1,
+               int64_t y1_ms, const double2* coef, int64_t coef_ms, int64_t n, int nmem,
+               hipStream_t st, const int* act) {
+    dim3 grid(cgs_nblk(n), nmem), blk(256);
+    if (x1)
+        hipLaunchKernelGGL((k_gs_update<T, 2, 2>), grid, blk, 0, st, V, ldv, v_ms, nc, x0, x0_ms,
+                           x1, x1_ms, y0, y0_ms, y1, y1_ms, coef, coef_ms, n, act);
+    else
+        hipLaunchKernelGGL((k_gs_update<T, 1, 1>), grid, blk, 0, st, V, ldv, v_ms, nc, x0, x0_ms,
+                           x1, x1_ms, y0, y0_ms, y1, y1_ms, coef, coef_ms, n, act);
+}
+
+template void gs_dot<float, float>(const float2*, int64_t, int64_t, int, const float2*, int64_t,
+                                   const float2*, int64_t, double2*, int, int64_t, int,
+                                   hipStream_t, const int*);
+template void gs_dot<double, double>(const double2*, int64_t, int64_t, int, const double2*,
+                                     int64_t, const double2*, int64_t, double2*, int, int64_t,
+                                     int, hipStream_t, const int*);
+template void gs_dot<float, double>(const float2*, int64_t, int64_t, int, const double2*, int64_t,
+                                    const double2*, int64_t, double2*, int, int64_t, int,
+                                    hipStream_t, const int*);
+template void gs_update<float>(const float2*, int64_t, int64_t, int, const float2*, int64_t,
+                               const float2*, int64_t, float2*, int64_t, float2*, int64_t,
+                               const double2*, int64_t, int64_t, int, hipStream_t, const int*);
+template void gs_update<double>(const double2*, int64_t, int64_t, int, const double2*, int64_t,
+                                const double2*, int64_t, double2*, int64_t, double2*, int64_t,
+                                const double2*, int64_t, int64_t, int, hipStream_t, const int*);
+
+// DCGS2 bookkeeping for step j (one wavefront per member). G holds the reduced
+// sums of k_gs_dot over columns 0..j with x_0 = r (the once-orthogonalised,
+// unnormalised candidate in column j) and, when nx = 2, x_1 = w = A r:
+//   s = V_j^H r, alpha = r^H r, p = V_j^H w, gamma = r^H w, omega = ||w||^2.
+// With nu = (alpha - ||s||^2)^{1/2} the candidate becomes q_j = (r - V_j s)/nu,
+// column j-1 of H gains its second Gram-Schmidt pass (H[0..j-1][j-1] += s,
+// H[j][j-1] = nu) unless `first`, and for nx = 2 the first pass of the next
+// column follows from the same sums: with d = [p; (gamma - s^H p)/nu],
+//   H[0..j][j] = (d - H[0..j][0..j-1] s)/nu,
+//   r_next = (w - V_j p - d_j q_j)/nu.
+// Output coefficients for k_gs_update (q_j and r_next as combinations of r, w
+// and V_j). A subdiagonal nu <= tol * ||A q_{j-1}|| is a breakdown at column j-1:
+// brk is set and every coefficient of this and later steps is zero.
+__global__ __launch_bounds__(64) void k_dcgs_coef(const double2* __restrict__ G, int64_t g_ms,
+                                                  int j, int nx, int first, double2* __restrict__ H,
+                                                  int64_t ldh, int64_t h_ms,
+                                                  double2* __restrict__ coef, int64_t coef_ms,
+                                                  double* __restrict__ ref, int* __restrict__ brk,
+                                                  double tol, const int* __restrict__ act) {
+    const int b = blockIdx.x;
+    if (act && !act[b]) return;
+    const int lane = threadIdx.x;
+    G += b * g_ms;
+    H += b * h_ms;
+    coef += b * coef_ms;
+    const int nc = j + 1;
+    __shared__ double2 ss[MAXM + 1];
+    const double2 s = lane < j ? G[lane] : mk(0, 0);
+    const double2 pk = (nx > 1 && lane < j) ? G[nc + lane] : mk(0, 0);
+    ss[lane] = s;
+    const double alpha = G[j].x;
+    const double nrm_s = wsum(cabs2(s));
+    const double nu2 = alpha - nrm_s;
+    const double refv = first ? 0.0 : ref[b];
+    bool broken = brk[b] >= 0;
+    if (!broken && !(nu2 > tol * tol * refv * refv && nu2 > 0)) {
+        broken = true;
+        if (lane == 0) brk[b] = j - 1;
+        if (!first && lane == 0) H[(int64_t)(j - 1) * ldh + j] = mk(0, 0);
+    }
+    if (broken) {
+        for (int t = lane; t < 2 * (MAXM + 1) + 4; t += 64) coef[t] = mk(0, 0);
+        if (nx > 1)
+            for (int i = lane; i <= j; i += 64) H[(int64_t)j * ldh + i] = mk(0, 0);
+        if (lane == 0) ref[b] = 0;
+        return;
+    }
+    const double nu = sqrt(nu2), inu = 1.0 / nu;
+    if (!first) {
+        if (lane < j) {
+            double2* hc = H + (int64_t)(j - 1) * ldh;
+            hc[lane] = cadd(hc[lane], s);
+        }
+        if (lane == 0) H[(int64_t)(j - 1) * ldh + j] = mk(nu, 0);
+    }
+    if (lane < j) coef[lane] = cscale(s, inu);
+    if (lane == 0) {
+        coef[2 * (MAXM + 1) + 0] = mk(inu, 0);
+        coef[2 * (MAXM + 1) + 1] = mk(0, 0);
+    }
+    if (nx == 1) return;
+    __syncthreads();   // corrected column j-1 visible to every lane
+    const double2 sp = mk(wsum(s.x * pk.x + s.y * pk.y), wsum(s.x * pk.y - s.y * pk.x));
+    const double2 gam = G[nc + j];
+    const double2 dj = cscale(csub(gam, sp), inu);
+    // H[0..j][j] = (d - H s)/nu, lane i = row i
+    for (int i = lane; i <= j; i += 64) {
+        double2 hs = mk(0, 0);
+        // full sum: after a GMRES-DR restart the leading (k+1) x k block is dense
+        for (int kk = 0; kk < j; ++kk) hs = cadd(hs, cmul(H[(int64_t)kk * ldh + i], ss[kk]));
+        const double2 di = i < j ? G[nc + i] : dj;
+        H[(int64_t)j * ldh + i] = cscale(csub(di, hs), inu);
+    }
+    const double2 djn = cscale(dj, inu);
+    if (lane < j) coef[(MAXM + 1) + lane] = cscale(csub(pk, cmul(djn, s)), inu);
+    if (lane == 0) {
+        coef[2 * (MAXM + 1) + 2] = cscale(djn, -inu);
+        coef[2 * (MAXM + 1) + 3] = mk(inu, 0);
+        ref[b] = sqrt(G[2 * nc].x) * inu;
+    }
+}
+
+void dcgs_coef(const double2* G, int64_t g_ms, int j, int nx, int first, double2* H, int64_t ldh,
+               int64_t h_ms, double2* coef, int64_t coef_ms, double* ref, int* brk, double tol,
+               int nmem, hipStream_t st, const int* act) {
+    hipLaunchKernelGGL(k_dcgs_coef, dim3(nmem), dim3(64), 0, st, G, g_ms, j, nx, first, H, ldh,
+                       h_ms, coef, coef_ms, ref, brk, tol, act);
+}
+
+// ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_reduce_cols(const double2* __restrict__ partial, int nblk,
                                                      int ncols, double2* __restrict__ out,
                                                      int64_t out_ms, double2* __restrict__ add_to,

@@ -75,6 +75,14 @@ double vec_norm(gdr_op_s* op, const double2* x) {
 // ---------------------------------------------------------------------------
 // Batched Arnoldi step (eq. (2.2)) with CGS2: one operator launch and three
 // sweeps over each member's basis per step.
+// Arnoldi recurrence (eq. (2.2)) with delayed classical Gram-Schmidt
+// (DCGS2): the operator is applied to the once-orthogonalised candidate r_j in
+// column j, and one projection sweep V_{0..j}^H [r_j, A r_j] plus one update
+// sweep both finish column j (its second Gram-Schmidt pass, folded into the
+// correction of H column j-1) and produce the next candidate r_{j+1} in
+// column j+1. In exact arithmetic this is the same basis and Hessenberg
+// matrix as CGS2 (orthogonalise twice); the last candidate is finished by
+// close(). Two sweeps over the basis per step instead of three.
 template <typename T>
 struct Arnoldi {
     using C = typename CT<T>::t;
@@ -93,6 +101,10 @@ struct Arnoldi {
     int* brk = nullptr;
     double2* partial = nullptr;
     int nblk = 0;
+    double2* G = nullptr;       // reduced projection sums, GMS per member
+    double2* coef = nullptr;    // update coefficients, GS_COEF_MS per member
+    double* ref = nullptr;      // ||A q_{j-1}|| estimate per member (breakdown test)
+    static constexpr int GMS = 2 * (MAXM + 1) + 2;
     DiagList dl{};
     Prof* prof = nullptr;
 
@@ -112,44 +124,57 @@ struct Arnoldi {
         inv = mem.get<double>(nmem);
         brk = mem.get<int>(nmem);
         nblk = cgs_nblk(n);
-        partial = mem.get<double2>((size_t)80 * nblk * nmem);
+        partial = mem.get<double2>((size_t)std::max(80, 2 * m + 4) * nblk * nmem);
+        G = mem.get<double2>((size_t)GMS * nmem);
+        coef = mem.get<double2>((size_t)GS_COEF_MS * nmem);
+        ref = mem.get<double>(nmem);
         for (int v = 0; v < DSLASH_MAXV; ++v) {
             dl.d[v] = z(1);
             dl.alpha[v] = 1;
         }
     }
 
-    void step(int j, const int* act, int nact) {
+    // Step j: column j holds the candidate r_j (columns 0..j-1 final); j0 is
+    // the first step of the cycle (column j0 already orthonormal, H columns
+    // before it final).
+    void step(int j, int j0, const int* act, int nact) {
         const double cs = sizeof(C);
         const double dn = (double)n * nact;
+        C* col = V + (int64_t)j * n;
         for (int b0 = 0; b0 < nmem; b0 += DSLASH_MAXV) {
             const int nb = std::min(DSLASH_MAXV, nmem - b0);
             prof->begin(GDR_K_DSLASH);
-            dslash<T>(V + b0 * vms + (int64_t)j * n, vms, w + b0 * n, n, nullptr, 0,
-                      links_for<T>(op), lst_for<T>(op), op->g, op->kappa, dl, nb, st,
-                      act ? act + b0 : nullptr);
+            dslash<T>(col + b0 * vms, vms, w + b0 * n, n, nullptr, 0, links_for<T>(op),
+                      lst_for<T>(op), op->g, op->kappa, dl, nb, st, act ? act + b0 : nullptr);
             const int na = std::min(nb, nact - std::min(nact, b0));
             prof->end(GDR_K_DSLASH, dslash_bytes<T>(op, na, false), dslash_flops(op, na));
         }
-        double2* Hj = H + (int64_t)j * (m + 1);
         const double nc = j + 1;
         prof->begin(GDR_K_CGS_DOT);
-        cgs_pass<T, T>(CGS_DOT, V, n, vms, j + 1, w, n, nullptr, 0, nullptr, 0, partial, nblk, n,
-                       nmem, st, act);
-        prof->end(GDR_K_CGS_DOT, dn * (nc * cs + cs), dn * 8 * (nc + 1));
-        reduce_cols(partial, nblk, j + 2, Hj, hms, nullptr, 0, nmem, st, act);
+        gs_dot<T, T>(V, n, vms, j + 1, col, vms, w, n, partial, nblk, n, nmem, st, act);
+        prof->end(GDR_K_CGS_DOT, dn * (nc + 1) * cs, dn * 16 * (nc + 1));
+        reduce_cols(partial, nblk, 2 * (j + 1) + 1, G, GMS, nullptr, 0, nmem, st, act);
+        dcgs_coef(G, GMS, j, 2, j == j0, H, m + 1, hms, coef, GS_COEF_MS, ref, brk, 1e-14, nmem,
+                  st, act);
         prof->begin(GDR_K_CGS_UPDOT);
-        cgs_pass<T, T>(CGS_UPDATE_DOT, V, n, vms, j + 1, w, n, wd, n, Hj, hms, partial, nblk, n,
-                       nmem, st, act);
-        prof->end(GDR_K_CGS_UPDOT, dn * (nc * cs + cs + 16), dn * 16 * nc);
-        reduce_cols(partial, nblk, j + 1, h2, 80, Hj, hms, nmem, st, act);
+        gs_update<T>(V, n, vms, j, col, vms, w, n, col, vms, col + n, vms, coef, GS_COEF_MS, n,
+                     nmem, st, act);
+        prof->end(GDR_K_CGS_UPDOT, dn * (j + 4) * cs, dn * 16 * j);
+    }
+
+    // Finish the last candidate (column m): second pass against columns 0..m-1.
+    void close(const int* act, int nact) {
+        const double cs = sizeof(C);
+        const double dn = (double)n * nact;
+        C* col = V + (int64_t)m * n;
         prof->begin(GDR_K_CGS_UPNORM);
-        cgs_pass<T, T>(CGS_UPDATE_NORM, V, n, vms, j + 1, (const C*)nullptr, 0, wd, n, h2, 80,
-                       partial, nblk, n, nmem, st, act);
-        prof->end(GDR_K_CGS_UPNORM, dn * (nc * cs + 32), dn * (8 * nc + 4));
-        norm_finish(partial, nblk, H, m + 1, hms, j, Hj + j + 1, hms, inv, brk, 1e-14, nmem, st,
-                    act);
-        scale_store<T>(wd, n, inv, V + (int64_t)(j + 1) * n, vms, n, nmem, st, act);
+        gs_dot<T, T>(V, n, vms, m + 1, col, vms, (const C*)nullptr, 0, partial, nblk, n, nmem, st,
+                     act);
+        reduce_cols(partial, nblk, m + 2, G, GMS, nullptr, 0, nmem, st, act);
+        dcgs_coef(G, GMS, m, 1, 0, H, m + 1, hms, coef, GS_COEF_MS, ref, brk, 1e-14, nmem, st, act);
+        gs_update<T>(V, n, vms, m, col, vms, (const C*)nullptr, 0, col, vms, (C*)nullptr, 0, coef,
+                     GS_COEF_MS, n, nmem, st, act);
+        prof->end(GDR_K_CGS_UPNORM, dn * (2.0 * (m + 1) + 1) * cs, dn * 16.0 * m);
     }
 };
 
@@ -245,7 +270,8 @@ static int dr_run(gdr_op_s* op, int ns, const double2* sig_h, const double2* b_e
         A.V = Vc;
         A.H = Hc;
         fill_int(A.brk, -1, 1, st);
-        for (int j = j0; j < m; ++j) A.step(j, nullptr, 1);
+        for (int j = j0; j < m; ++j) A.step(j, j0, nullptr, 1);
+        A.close(nullptr, 1);
         mvps += m - j0;
         HIPCHK(hipMemsetAsync(&outs[cur].flags, 0, sizeof(int), st));
         CycleArgs a{};
@@ -485,7 +511,8 @@ static void proj_run(gdr_op_s* op, gdr_defl_s* defl, int nmem, int ns,
         start_cycle(rn2, 1, cvec, m + 1, m, A.inv, nmem, st, act);
         convert_scale<T>(W + (int64_t)ns * n, wms, A.inv, 1, Vb, vms, n, nmem, st, act);
         fill_int(A.brk, -1, nmem, st);
-        for (int j = 0; j < m; ++j) A.step(j, act, nact0);
+        for (int j = 0; j < m; ++j) A.step(j, 0, act, nact0);
+        A.close(act, nact0);
         HIPCHK(hipMemcpyAsync(outs + cur * nmem, init.data(), nmem * sizeof(CycleOut),
                               hipMemcpyHostToDevice, st));
         CycleArgs a{};

@@ -34,6 +34,30 @@ void dslash(const typename CT<TS>::t* in, int64_t in_stride, typename CT<TS>::t*
             const void* links, int link_storage, const Geom& g, double kappa, const DiagList& dl,
             int nvec, hipStream_t st, const int* act = nullptr);
 
+// ------------------------------------------------------------ DCGS2 (blas.hip)
+// Column-block sums of V_{0..nc-1}^H x_a (a < 1 or 2; x1 == nullptr for one
+// vector) and ||x_last||^2 into partial[((mem*nval) + a*nc + c)*nblk + blk],
+// nval = (#x)*nc + 1; reduce with reduce_cols(partial, nblk, nval, ...).
+template <typename T, typename TX>
+void gs_dot(const typename CT<T>::t* V, int64_t ldv, int64_t v_ms, int nc,
+            const typename CT<TX>::t* x0, int64_t x0_ms, const typename CT<TX>::t* x1,
+            int64_t x1_ms, double2* partial, int nblk, int64_t n, int nmem, hipStream_t st,
+            const int* act = nullptr);
+// y_o = sum_a beta[o][a] x_a - V_{0..nc-1} coef[o] (o < 1 or 2 outputs as inputs);
+// layout of coef per member: coef[o*(MAXM+1) + c], beta at 2*(MAXM+1) + 2*o + a.
+constexpr int GS_COEF_MS = 2 * (MAXM + 1) + 4;
+template <typename T>
+void gs_update(const typename CT<T>::t* V, int64_t ldv, int64_t v_ms, int nc,
+               const typename CT<T>::t* x0, int64_t x0_ms, const typename CT<T>::t* x1,
+               int64_t x1_ms, typename CT<T>::t* y0, int64_t y0_ms, typename CT<T>::t* y1,
+               int64_t y1_ms, const double2* coef, int64_t coef_ms, int64_t n, int nmem,
+               hipStream_t st, const int* act = nullptr);
+// DCGS2 bookkeeping of step j (see blas.hip): H corrections, next H column and
+// the update coefficients, breakdown flag.
+void dcgs_coef(const double2* G, int64_t g_ms, int j, int nx, int first, double2* H, int64_t ldh,
+               int64_t h_ms, double2* coef, int64_t coef_ms, double* ref, int* brk, double tol,
+               int nmem, hipStream_t st, const int* act = nullptr);
+
 // ------------------------------------------------------------ BLAS (blas.hip)
 // Block-partial buffers: partial[(member*ncols_tot + col)*nblk + blk] (double2)
 int cgs_nblk(int64_t n);
