@@ -1,12 +1,12 @@
 // Vector kernels of the Arnoldi recurrence (eq. (2.2)): classical Gram-Schmidt
-// applied twice (CGS2) against the Krylov basis, norms, scaling, and the
-// tall-skinny combinations x_i += V d_i, r = V s and V_{k+1} = V_{m+1} P.
+// against the Krylov basis in the delayed two-pass form (DCGS2), norms,
+// scaling, and the tall-skinny combinations x_i += V d_i, r = V s and
+// V_{k+1} = V_{m+1} P.
 //
-// Dot products V^H w: each lane of a wavefront owns one row of a 64-row tile
-// and forms the products of its row with 16 basis columns; a butterfly
+// Dot products V^H x: lanes own rows, each wave accumulates a group of
+// columns over its block's rows in FP64 registers, and a butterfly
 // reduce-scatter over the wavefront (shuffles at distance 32,16,8,4, then an
-// all-reduce over 2,1) leaves column (lane>>2)&15's tile sum on four lanes,
-// which accumulate it over the wave's tiles in one register. Blocks write
+// all-reduce over 2,1) leaves value (lane>>2)&15 on four lanes. Blocks write
 // per-column partial sums; a second kernel adds them in a fixed order, so
 // every result is bitwise reproducible. All accumulation is FP64.
 #include "kernels.h"
@@ -59,324 +59,6 @@ int cgs_nblk(int64_t n) {
     if (nb < 1) nb = 1;
     return (int)nb;
 }
-
-template <typename T, typename TW, int MODE, bool CACHE>
-__global__ __launch_bounds__(256) void k_cgs(const typename CT<T>::t* __restrict__ V, int64_t ldv,
-                                             int64_t v_ms, int ncols,
-                                             const typename CT<TW>::t* __restrict__ win,
-                                             int64_t win_ms, double2* __restrict__ wd,
-                                             int64_t wd_ms, const double2* __restrict__ h,
-                                             int64_t h_ms, double2* __restrict__ partial,
-                                             int nblk, int64_t n, const int* __restrict__ act) {
-    using C = typename CT<T>::t;
-    const int mem = blockIdx.y;
-    if (act && !act[mem]) return;
-    V += mem * v_ms;
-    if (win) win += mem * win_ms;
-    if (wd) wd += mem * wd_ms;
-    const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
-    __shared__ double2 hs[MAXM + 16];
-    __shared__ double2 red[4][CGS_MAXG * 16];
-    if (MODE != CGS_DOT) {
-        for (int t = threadIdx.x; t < ncols; t += blockDim.x) hs[t] = h[mem * h_ms + t];
-        __syncthreads();
-    }
-    const int nval = MODE == CGS_DOT ? ncols + 1 : (MODE == CGS_UPDATE_DOT ? ncols : 1);
-    const int ngrp = (nval + 15) / 16;
-    double2 acc[CGS_MAXG];
-#pragma unroll
-    for (int g = 0; g < CGS_MAXG; ++g) acc[g] = mk(0, 0);
-    double nacc = 0;
-
-    const int64_t ntiles = (n + 63) / 64;
-    for (int64_t tile = (int64_t)blockIdx.x * 4 + wv; tile < ntiles; tile += (int64_t)gridDim.x * 4) {
-        const int64_t i = tile * 64 + lane;
-        const bool ok = i < n;
-        if (MODE == CGS_DOT) {
-            double2 w = ok ? to_d(win[i]) : mk(0, 0);
-            const double ww = cabs2(w);
-#pragma unroll
-            for (int g = 0; g < CGS_MAXG; ++g) {
-                if (g < ngrp) {
-                    double2 a[16];
-#pragma unroll
-                    for (int c = 0; c < 16; ++c) {
-                        const int col = g * 16 + c;
-                        if (col < ncols && ok)
-                            a[c] = cjmul(to_d(V[col * ldv + i]), w);
-                        else
-                            a[c] = mk(col == ncols ? ww : 0.0, 0);
-                    }
-                    acc[g] = cadd(acc[g], rs16(a, lane));
-                }
-            }
-        } else {
-            double2 w;
-            if (MODE == CGS_UPDATE_DOT || (MODE == CGS_UPDATE && win))
-                w = ok ? to_d(win[i]) : mk(0, 0);
-            else
-                w = ok ? wd[i] : mk(0, 0);
-            C vr[CACHE ? MAXM : 1];
-            if (CACHE) {
-#pragma unroll
-                for (int col = 0; col < MAXM; ++col) {
-                    if (col < ncols) {
-                        vr[col] = ok ? V[col * ldv + i] : C{0, 0};
-                        w = csub(w, cmul(to_d(vr[col]), hs[col]));
-                    }
-                }
-            } else {
-                for (int col = 0; col < ncols; ++col) {
-                    double2 vv = ok ? to_d(V[col * ldv + i]) : mk(0, 0);
-                    w = csub(w, cmul(vv, hs[col]));
-                }
-            }
-            if (ok) wd[i] = w;
-            if (MODE == CGS_UPDATE_NORM) nacc += cabs2(w);
-            if (MODE == CGS_UPDATE_DOT) {
-#pragma unroll
-                for (int g = 0; g < CGS_MAXG; ++g) {
-                    if (g < ngrp) {
-                        double2 a[16];
-#pragma unroll
-                        for (int c = 0; c < 16; ++c) {
-                            const int col = g * 16 + c;
-                            if (col < ncols && ok) {
-                                double2 vv;
-                                if (CACHE) vv = to_d(vr[col < MAXM ? col : 0]);
-                                else vv = to_d(V[col * ldv + i]);
-                                a[c] = cjmul(vv, w);
-                            } else {
-                                a[c] = mk(0, 0);
-                            }
-                        }
-                        acc[g] = cadd(acc[g], rs16(a, lane));
-                    }
-                }
-            }
-        }
-    }
-    if (MODE == CGS_UPDATE) return;
-    // block reduction in a fixed order
-    if (MODE == CGS_UPDATE_NORM) {
-        nacc = wsum(nacc);
-        if (lane == 0) red[wv][0] = mk(nacc, 0);
-    } else {
-        if ((lane & 3) == 0) {
-#pragma unroll
-            for (int g = 0; g < CGS_MAXG; ++g)
-                if (g < ngrp) red[wv][g * 16 + (lane >> 2)] = acc[g];
-        }
-    }
-    __syncthreads();
-    for (int t = threadIdx.x; t < nval; t += blockDim.x) {
-        double2 s = red[0][t];
-        s = cadd(s, red[1][t]);
-        s = cadd(s, red[2][t]);
-        s = cadd(s, red[3][t]);
-        partial[((int64_t)mem * nval + t) * nblk + blockIdx.x] = s;
-    }
-}
-
-// Orders this wavefront's LDS writes before its own later LDS reads (the
-// lanes of one wavefront exchange data through LDS without a block barrier).
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// FP32 basis, passes that need V^H w (DOT and UPDATE_DOT). Each wavefront
-// owns 64-row tiles: with lanes = rows it loads the tile's basis entries
-// (one coalesced 512 B segment per column, all columns issued before use,
-// the next tile's loads issued before the current tile's dot products),
-// applies the update w -= V h, and stages the tile in LDS; then with
-// lanes = columns each lane accumulates its column's dot product over the
-// tile's 64 rows, so no cross-lane reduction is needed until the end.
-constexpr int TPAD = MAXM + 1;   // LDS tile row stride (odd: conflict-free both ways)
-constexpr int TW_WAVES = 4;
-
-template <typename TW, int MODE>
-__global__ __launch_bounds__(64 * TW_WAVES) void k_cgs_tile(
-    const float2* __restrict__ V, int64_t ldv, int64_t v_ms, int ncols,
-    const typename CT<TW>::t* __restrict__ win, int64_t win_ms, double2* __restrict__ wd,
-    int64_t wd_ms, const double2* __restrict__ h, int64_t h_ms, double2* __restrict__ partial,
-    int nblk, int64_t n, const int* __restrict__ act) {
-    const int mem = blockIdx.y;
-    if (act && !act[mem]) return;
-    V += mem * v_ms;
-    win += mem * win_ms;
-    if (wd) wd += mem * wd_ms;
-    const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
-    __shared__ double2 hs[MAXM];
-    __shared__ float2 tile[TW_WAVES][64 * TPAD];
-    __shared__ double2 wp[TW_WAVES][64];
-    __shared__ double2 red[TW_WAVES][MAXM + 1];
-    if (MODE == CGS_UPDATE_DOT)
-        for (int t = threadIdx.x; t < MAXM; t += blockDim.x)
-            hs[t] = t < ncols ? h[mem * h_ms + t] : mk(0, 0);
-    __syncthreads();
-    float2* tl = tile[wv];
-    double2 acc = mk(0, 0);
-    double nacc = 0;
-    const int64_t ntiles = (n + 63) / 64;
-    const int64_t stride = (int64_t)gridDim.x * TW_WAVES;
-    int64_t t = (int64_t)blockIdx.x * TW_WAVES + wv;
-    // Basis allocations carry 8 spare columns, so the loads run in uniform
-    // chunks of 8 columns; rows past n are clamped to a valid row and enter
-    // with weight zero.
-    float2 vr[MAXM];
-    typename CT<TW>::t wn;
-    auto load_tile = [&](int64_t tt) {
-        int64_t i = tt * 64 + lane;
-        if (i >= n) i = n - 1;
-        wn = win[i];
-        const float2* p = V + i;
-#pragma unroll
-        for (int c8 = 0; c8 < MAXM; c8 += 8) {
-            if (c8 < ncols) {
-#pragma unroll
-                for (int c = 0; c < 8; ++c) {
-                    vr[c8 + c] = *p;
-                    p += ldv;
-                }
-            }
-        }
-    };
-    if (t < ntiles) load_tile(t);
-    for (; t < ntiles; t += stride) {
-        const int64_t i = t * 64 + lane;
-        const bool ok = i < n;
-        double2 w = ok ? to_d(wn) : mk(0, 0);
-        if (MODE == CGS_DOT) nacc += cabs2(w);
-#pragma unroll
-        for (int c8 = 0; c8 < MAXM; c8 += 8) {
-            if (c8 < ncols) {
-#pragma unroll
-                for (int c = 0; c < 8; ++c) {
-                    if (MODE == CGS_UPDATE_DOT) w = csub(w, cmul(to_d(vr[c8 + c]), hs[c8 + c]));
-                    tl[lane * TPAD + c8 + c] = vr[c8 + c];
-                }
-            }
-        }
-        if (MODE == CGS_UPDATE_DOT && ok) wd[i] = w;
-        wp[wv][lane] = ok ? w : mk(0, 0);
-        // prefetch the next tile while this one's dot products run
-        if (t + stride < ntiles) load_tile(t + stride);
-        wave_sync();
-        if (lane < ncols) {
-#pragma unroll 8
-            for (int r = 0; r < 64; ++r) acc = cadd(acc, cjmul(to_d(tl[r * TPAD + lane]), wp[wv][r]));
-        }
-        wave_sync();
-    }
-    if (lane < ncols) red[wv][lane] = acc;
-    if (MODE == CGS_DOT) {
-        nacc = wsum(nacc);
-        if (lane == 0) red[wv][ncols] = mk(nacc, 0);
-    }
-    __syncthreads();
-    const int nval = MODE == CGS_DOT ? ncols + 1 : ncols;
-    for (int c = threadIdx.x; c < nval; c += blockDim.x) {
-        double2 sum = red[0][c];
-        for (int ww = 1; ww < TW_WAVES; ++ww) sum = cadd(sum, red[ww][c]);
-        partial[((int64_t)mem * nval + c) * nblk + blockIdx.x] = sum;
-    }
-}
-
-// Streaming passes without dot products (UPDATE, UPDATE_NORM) for both
-// precisions: lanes = rows, all of a row's basis entries loaded before use.
-template <typename T, int MODE>
-__global__ __launch_bounds__(256) void k_cgs_stream(
-    const typename CT<T>::t* __restrict__ V, int64_t ldv, int64_t v_ms, int ncols,
-    const typename CT<T>::t* __restrict__ win, int64_t win_ms, double2* __restrict__ wd,
-    int64_t wd_ms, const double2* __restrict__ h, int64_t h_ms, double2* __restrict__ partial,
-    int nblk, int64_t n, const int* __restrict__ act) {
-    using C = typename CT<T>::t;
-    constexpr int CH = std::is_same<T, float>::value ? 32 : 16;
-    const int mem = blockIdx.y;
-    if (act && !act[mem]) return;
-    V += mem * v_ms;
-    if (win) win += mem * win_ms;
-    wd += mem * wd_ms;
-    __shared__ double2 hs[MAXM];
-    __shared__ double red[4];
-    for (int t = threadIdx.x; t < ncols; t += blockDim.x) hs[t] = h[mem * h_ms + t];
-    __syncthreads();
-    double nacc = 0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        double2 w = win ? to_d(win[i]) : wd[i];
-        for (int c0 = 0; c0 < ncols; c0 += CH) {
-            C vr[CH];
-#pragma unroll
-            for (int c = 0; c < CH; ++c)
-                if (c0 + c < ncols) vr[c] = V[(c0 + c) * ldv + i];
-#pragma unroll
-            for (int c = 0; c < CH; ++c)
-                if (c0 + c < ncols) w = csub(w, cmul(to_d(vr[c]), hs[c0 + c]));
-        }
-        wd[i] = w;
-        if (MODE == CGS_UPDATE_NORM) nacc += cabs2(w);
-    }
-    if (MODE != CGS_UPDATE_NORM) return;
-    nacc = wsum(nacc);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (lane == 0) red[wv] = nacc;
-    __syncthreads();
-    if (threadIdx.x == 0)
-        partial[(int64_t)mem * nblk + blockIdx.x] = mk(red[0] + red[1] + red[2] + red[3], 0);
-}
-
-template <typename T, typename TW>
-void cgs_pass(int mode, const typename CT<T>::t* V, int64_t ldv, int64_t v_mstride, int ncols,
-              const typename CT<TW>::t* win, int64_t win_mstride, double2* wd, int64_t wd_mstride,
-              const double2* h, int64_t h_mstride, double2* partial, int nblk, int64_t n, int nmem,
-              hipStream_t st, const int* act) {
-    dim3 grid(nblk, nmem), blk(CGS_BLOCK);
-    if (mode == CGS_UPDATE_NORM || mode == CGS_UPDATE) {
-        // streaming passes read win only as type T (never the FP64 residual)
-        const typename CT<T>::t* wt = (const typename CT<T>::t*)win;
-        if (mode == CGS_UPDATE_NORM)
-            hipLaunchKernelGGL((k_cgs_stream<T, CGS_UPDATE_NORM>), grid, blk, 0, st, V, ldv,
-                               v_mstride, ncols, wt, win_mstride, wd, wd_mstride, h, h_mstride,
-                               partial, nblk, n, act);
-        else
-            hipLaunchKernelGGL((k_cgs_stream<T, CGS_UPDATE>), grid, blk, 0, st, V, ldv, v_mstride,
-                               ncols, wt, win_mstride, wd, wd_mstride, h, h_mstride, partial, nblk,
-                               n, act);
-        return;
-    }
-    if constexpr (std::is_same<T, float>::value) {
-        dim3 bt(64 * TW_WAVES);
-        if (mode == CGS_DOT)
-            hipLaunchKernelGGL((k_cgs_tile<TW, CGS_DOT>), grid, bt, 0, st, V, ldv, v_mstride,
-                               ncols, win, win_mstride, wd, wd_mstride, h, h_mstride, partial,
-                               nblk, n, act);
-        else
-            hipLaunchKernelGGL((k_cgs_tile<TW, CGS_UPDATE_DOT>), grid, bt, 0, st, V, ldv,
-                               v_mstride, ncols, win, win_mstride, wd, wd_mstride, h, h_mstride,
-                               partial, nblk, n, act);
-    } else {
-#define GDR_CGS(M)                                                                               \
-    hipLaunchKernelGGL((k_cgs<T, TW, M, false>), grid, blk, 0, st, V, ldv, v_mstride, ncols, win, \
-                       win_mstride, wd, wd_mstride, h, h_mstride, partial, nblk, n, act)
-        if (mode == CGS_DOT) GDR_CGS(CGS_DOT);
-        else GDR_CGS(CGS_UPDATE_DOT);
-#undef GDR_CGS
-    }
-}
-template void cgs_pass<double, double>(int, const double2*, int64_t, int64_t, int, const double2*,
-                                       int64_t, double2*, int64_t, const double2*, int64_t,
-                                       double2*, int, int64_t, int, hipStream_t, const int*);
-template void cgs_pass<float, float>(int, const float2*, int64_t, int64_t, int, const float2*,
-                                     int64_t, double2*, int64_t, const double2*, int64_t, double2*,
-                                     int, int64_t, int, hipStream_t, const int*);
-template void cgs_pass<float, double>(int, const float2*, int64_t, int64_t, int, const double2*,
-                                      int64_t, double2*, int64_t, const double2*, int64_t, double2*,
-                                      int, int64_t, int, hipStream_t, const int*);
 
 // ---------------------------------------------------------------------------
 // Delayed classical Gram-Schmidt (DCGS2) passes of the Arnoldi step.
@@ -664,77 +346,10 @@ void reduce_cols(const double2* partial, int nblk, int ncols, double2* out, int6
                        out, out_mstride, add_to, add_mstride, act);
 }
 
-__global__ __launch_bounds__(256) void k_norm_finish(const double2* __restrict__ partial, int nblk,
-                                                     double2* __restrict__ H, int64_t ldh,
-                                                     int64_t h_ms, int j,
-                                                     const double2* __restrict__ w0, int64_t w0_ms,
-                                                     double* __restrict__ inv, int* __restrict__ brk,
-                                                     double tol_rel, const int* __restrict__ act) {
-    const int b = blockIdx.x;
-    if (act && !act[b]) return;
-    const double2* p = partial + (int64_t)b * nblk;
-    double s = 0;
-    for (int k = threadIdx.x; k < nblk; k += blockDim.x) s += p[k].x;
-    __shared__ double red[256];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w >= 1; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        double nrm = sqrt(red[0]);
-        double ref = sqrt(w0[b * w0_ms].x);
-        bool broke = brk[b] >= 0 || !(nrm > tol_rel * ref);
-        if (broke) {
-            if (brk[b] < 0) brk[b] = j;
-            H[b * h_ms + (int64_t)j * ldh + j + 1] = mk(0, 0);
-            inv[b] = 0.0;
-        } else {
-            H[b * h_ms + (int64_t)j * ldh + j + 1] = mk(nrm, 0);
-            inv[b] = 1.0 / nrm;
-        }
-    }
-}
-
-void norm_finish(const double2* partial, int nblk, double2* H, int64_t ldh, int64_t h_mstride,
-                 int j, const double2* w0, int64_t w0_mstride, double* inv, int* brk,
-                 double tol_rel, int nmem, hipStream_t st, const int* act) {
-    hipLaunchKernelGGL(k_norm_finish, dim3(nmem), dim3(256), 0, st, partial, nblk, H, ldh,
-                       h_mstride, j, w0, w0_mstride, inv, brk, tol_rel, act);
-}
-
-// ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) void k_scale_store(const double2* __restrict__ wd, int64_t wd_ms,
-                                                     const double* __restrict__ inv,
-                                                     typename CT<T>::t* __restrict__ v,
-                                                     int64_t v_ms, int64_t n,
-                                                     const int* __restrict__ act) {
-    const int b = blockIdx.y;
-    if (act && !act[b]) return;
-    const double s = inv[b];
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        v[b * v_ms + i] = from_d<T>(cscale(wd[b * wd_ms + i], s));
-}
-
 static int vec_grid(int64_t n) {
     int64_t g = (n + 255) / 256;
     return (int)(g > 8192 ? 8192 : g);
 }
-
-template <typename T>
-void scale_store(const double2* wd, int64_t wd_mstride, const double* inv,
-                 typename CT<T>::t* v, int64_t v_mstride, int64_t n, int nmem, hipStream_t st,
-                 const int* act) {
-    hipLaunchKernelGGL(k_scale_store<T>, dim3(vec_grid(n), nmem), dim3(256), 0, st, wd,
-                       wd_mstride, inv, v, v_mstride, n, act);
-}
-template void scale_store<double>(const double2*, int64_t, const double*, double2*, int64_t,
-                                  int64_t, int, hipStream_t, const int*);
-template void scale_store<float>(const double2*, int64_t, const double*, float2*, int64_t, int64_t,
-                                 int, hipStream_t, const int*);
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_convert_scale(const double2* __restrict__ x, int64_t x_ms,

@@ -98,9 +98,6 @@ template <> __device__ __forceinline__ float2 from_d<float>(double2 a) {
 constexpr int MAXM = 64;     // max restart length m
 constexpr int MAXNS = 16;    // max shifts
 constexpr int MAXK = 63;
-constexpr int CGS_GROUP = 16;             // columns reduced together
-constexpr int CGS_MAXG = 5;               // up to 80 reduced columns
-constexpr int CGS_BLOCK = 256;
 constexpr int BASIS_PAD = 8;              // spare zeroed columns after every basis
 
 }  // namespace gdr

@@ -58,13 +58,16 @@ struct DslashK {
     __device__ static void run(const C* __restrict__ in, int64_t in_stride, C* __restrict__ out,
                                int64_t out_stride, const C* __restrict__ add, int64_t add_stride,
                                const TL* __restrict__ links, const Geom& g, R kappa,
-                               const DiagList& dl, const int* __restrict__ act) {
+                               const DiagList& dl, const int* __restrict__ act, int nvec) {
         __shared__ C sp[12 * 256];
-        const int v = blockIdx.y;
-        if (act && !act[v]) return;   // uniform over the block
+        // blocks of one tile range for all nvec vectors are consecutive, so a
+        // batched launch reads each link from HBM once and from L2 after that
         const int nb = gridDim.x;
         const int b = blockIdx.x;
-        const int lb = (nb % 8 == 0) ? ((b % 8) * (nb / 8) + b / 8) : b;
+        const int lbv = (nb % 8 == 0) ? ((b % 8) * (nb / 8) + b / 8) : b;
+        const int v = lbv % nvec;
+        const int lb = lbv / nvec;
+        if (act && !act[v]) return;   // uniform over the block
         const int local = threadIdx.x;
         const int site = lb * 256 + local;
         const int vol = g.vol;
@@ -230,9 +233,9 @@ __global__ __launch_bounds__(256, DslashOcc<TS>::waves) void k_dslash(const type
                                                 const typename CT<TS>::t* __restrict__ add,
                                                 int64_t add_stride, const TL* __restrict__ links,
                                                 Geom g, R kappa, DiagList dl,
-                                                const int* __restrict__ act) {
+                                                const int* __restrict__ act, int nvec) {
     DslashK<TS, TL, R>::run(in, in_stride, out, out_stride, add, add_stride, links, g, kappa, dl,
-                            act);
+                            act, nvec);
 }
 
 template <typename TS>
@@ -240,20 +243,20 @@ void dslash(const typename CT<TS>::t* in, int64_t in_stride, typename CT<TS>::t*
             int64_t out_stride, const typename CT<TS>::t* add, int64_t add_stride,
             const void* links, int link_storage, const Geom& g, double kappa, const DiagList& dl,
             int nvec, hipStream_t st, const int* act) {
-    dim3 grid((g.vol + 255) / 256, nvec);
+    dim3 grid(((g.vol + 255) / 256) * nvec);
     if constexpr (std::is_same<TS, double>::value) {
         hipLaunchKernelGGL((k_dslash<double, double2, double>), grid, dim3(256), 0, st, in,
                            in_stride, out, out_stride, add, add_stride, (const double2*)links, g,
-                           kappa, dl, act);
+                           kappa, dl, act, nvec);
     } else {
         if (link_storage == 2) {
             hipLaunchKernelGGL((k_dslash<float, __half2, float>), grid, dim3(256), 0, st, in,
                                in_stride, out, out_stride, add, add_stride,
-                               (const __half2*)links, g, (float)kappa, dl, act);
+                               (const __half2*)links, g, (float)kappa, dl, act, nvec);
         } else {
             hipLaunchKernelGGL((k_dslash<float, float2, float>), grid, dim3(256), 0, st, in,
                                in_stride, out, out_stride, add, add_stride, (const float2*)links,
-                               g, (float)kappa, dl, act);
+                               g, (float)kappa, dl, act, nvec);
         }
     }
 }

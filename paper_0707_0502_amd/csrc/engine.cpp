@@ -63,8 +63,7 @@ double vec_norm(gdr_op_s* op, const double2* x) {
     const int nblk = cgs_nblk(op->n);
     double2* part = mem.get<double2>(nblk);
     double2* out = mem.get<double2>(1);
-    cgs_pass<double, double>(CGS_DOT, nullptr, 0, 0, 0, x, 0, nullptr, 0, nullptr, 0, part, nblk,
-                             op->n, 1, st);
+    gs_dot<double, double>(nullptr, 0, 0, 0, x, 0, nullptr, 0, part, nblk, op->n, 1, st);
     reduce_cols(part, nblk, 1, out, 1, nullptr, 0, 1, st);
     double2 h;
     HIPCHK(hipMemcpyAsync(&h, out, sizeof(h), hipMemcpyDeviceToHost, st));
@@ -93,10 +92,8 @@ struct Arnoldi {
     C* V = nullptr;
     int64_t vms = 0;
     C* w = nullptr;
-    double2* wd = nullptr;
     double2* H = nullptr;
     int64_t hms = 0;
-    double2* h2 = nullptr;
     double* inv = nullptr;
     int* brk = nullptr;
     double2* partial = nullptr;
@@ -117,10 +114,8 @@ struct Arnoldi {
         V = Vbuf;
         vms = vms_;
         w = mem.get<C>(n * nmem);
-        wd = mem.get<double2>(n * nmem);
         hms = (int64_t)(m + 1) * m;
         H = mem.get<double2>(hms * nmem);
-        h2 = mem.get<double2>(80 * nmem);
         inv = mem.get<double>(nmem);
         brk = mem.get<int>(nmem);
         nblk = cgs_nblk(n);
@@ -178,27 +173,23 @@ struct Arnoldi {
     }
 };
 
-// Orthonormalise column k of Vb against columns 0..k-1 (CGS2) in place.
+// Orthonormalise column k of Vb against columns 0..k-1 in place: classical
+// Gram-Schmidt twice, each pass one projection sweep and one update sweep.
 template <typename T>
-static void orth_column(gdr_op_s* op, typename CT<T>::t* Vb, int k, double2* wd, double2* partial,
-                        int nblk, double2* tH, double* tinv, int* tbrk) {
+static void orth_column(gdr_op_s* op, typename CT<T>::t* Vb, int k, double2* partial, int nblk,
+                        double2* tG, double2* tcoef, double* tref, int* tbrk) {
     using C = typename CT<T>::t;
     hipStream_t st = op->ctx->st;
     const int64_t n = op->n;
     C* col = Vb + (int64_t)k * n;
-    fill_int(tbrk, -1, 1, st);
-    cgs_pass<T, T>(CGS_DOT, Vb, n, 0, k, col, 0, nullptr, 0, nullptr, 0, partial, nblk, n, 1, st);
-    reduce_cols(partial, nblk, k + 1, tH, 0, nullptr, 0, 1, st);   // tH[k] = ||col||^2
-    if (k > 0) {
-        cgs_pass<T, T>(CGS_UPDATE_DOT, Vb, n, 0, k, col, 0, wd, 0, tH, 0, partial, nblk, n, 1, st);
-        reduce_cols(partial, nblk, k, tH + 80, 0, nullptr, 0, 1, st);
-    } else {
-        cgs_pass<T, T>(CGS_UPDATE, Vb, n, 0, 0, col, 0, wd, 0, tH, 0, partial, nblk, n, 1, st);
+    for (int pass = 0; pass < 2; ++pass) {
+        fill_int(tbrk, -1, 1, st);
+        gs_dot<T, T>(Vb, n, 0, k + 1, col, 0, (const C*)nullptr, 0, partial, nblk, n, 1, st);
+        reduce_cols(partial, nblk, k + 2, tG, 0, nullptr, 0, 1, st);
+        dcgs_coef(tG, 0, k, 1, 1, nullptr, 0, 0, tcoef, 0, tref, tbrk, 0.0, 1, st);
+        gs_update<T>(Vb, n, 0, k, col, 0, (const C*)nullptr, 0, col, 0, (C*)nullptr, 0, tcoef, 0, n,
+                     1, st);
     }
-    cgs_pass<T, T>(CGS_UPDATE_NORM, Vb, n, 0, k, (const C*)nullptr, 0, wd, 0, tH + 80, 0, partial,
-                   nblk, n, 1, st);
-    norm_finish(partial, nblk, tH + 160, 0, 0, 0, tH + k, 0, tinv, tbrk, 0.0, 1, st);
-    scale_store<T>(wd, 0, tinv, col, 0, n, 1, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -225,6 +216,7 @@ static int dr_run(gdr_op_s* op, int ns, const double2* sig_h, const double2* b_e
     CycleOut* outs = mem.get<CycleOut>(2);
     double2* sig = mem.get<double2>(ns);
     double2* tH = mem.get<double2>(256);
+    double2* tcoef = mem.get<double2>(GS_COEF_MS);
     double* tinv = mem.get<double>(2);
     int* tbrk = mem.get<int>(2);
     double* dsc = mem.get<double>(2);
@@ -338,11 +330,10 @@ static int dr_run(gdr_op_s* op, int ns, const double2* sig_h, const double2* b_e
         vrecombine<T>(Vc, n, m + 1, P, m + 1, k + 1, Vn, n, n, st);
         S.prof.end(GDR_K_RECOMBINE, (double)n * (m + k + 2) * sizeof(C),
                    (double)n * (m + 1) * (k + 1) * 8);
-        orth_column<T>(op, Vn, k, A.wd, A.partial, A.nblk, tH, tinv, tbrk);
+        orth_column<T>(op, Vn, k, A.partial, A.nblk, tH, tcoef, tinv, tbrk);
         if (mixed) {
             // residual replacement: coordinates of the FP64 true residual in V_{k+1}
-            cgs_pass<T, double>(CGS_DOT, Vn, n, 0, k + 1, rtrue, 0, nullptr, 0, nullptr, 0,
-                                A.partial, A.nblk, n, 1, st);
+            gs_dot<T, double>(Vn, n, 0, k + 1, rtrue, 0, nullptr, 0, A.partial, A.nblk, n, 1, st);
             reduce_cols(A.partial, A.nblk, k + 2, tH, 0, nullptr, 0, 1, st);
             HIPCHK(hipMemcpyAsync(cx, tH, (k + 1) * sizeof(double2), hipMemcpyDeviceToDevice, st));
         }
@@ -476,8 +467,8 @@ static void proj_run(gdr_op_s* op, gdr_defl_s* defl, int nmem, int ns,
         const double dn = (double)n * nact0;
         // ---- minres projection over V_k with v_{k+1} tracking
         if (k > 0) {
-            cgs_pass<T, double>(CGS_DOT, Vd, n, 0, k + 1, W + (int64_t)ns * n, wms, nullptr, 0,
-                                nullptr, 0, A.partial, A.nblk, n, nmem, st, act);
+            gs_dot<T, double>(Vd, n, 0, k + 1, W + (int64_t)ns * n, wms, nullptr, 0, A.partial,
+                              A.nblk, n, nmem, st, act);
             reduce_cols(A.partial, A.nblk, k + 2, Cb, 80, nullptr, 0, nmem, st, act);
             ProjArgs pa{};
             pa.Hk = defl->Hk;
@@ -505,8 +496,8 @@ static void proj_run(gdr_op_s* op, gdr_defl_s* defl, int nmem, int ns,
                        dn * (k + 1) * (ns + 1) * 8);
         }
         // ---- one GMRES(m)-Sh cycle from r
-        cgs_pass<double, double>(CGS_DOT, nullptr, 0, 0, 0, W + (int64_t)ns * n, wms, nullptr, 0,
-                                 nullptr, 0, A.partial, A.nblk, n, nmem, st, act);
+        gs_dot<double, double>(nullptr, 0, 0, 0, W + (int64_t)ns * n, wms, nullptr, 0, A.partial,
+                               A.nblk, n, nmem, st, act);
         reduce_cols(A.partial, A.nblk, 1, rn2, 1, nullptr, 0, nmem, st, act);
         start_cycle(rn2, 1, cvec, m + 1, m, A.inv, nmem, st, act);
         convert_scale<T>(W + (int64_t)ns * n, wms, A.inv, 1, Vb, vms, n, nmem, st, act);
@@ -560,8 +551,8 @@ static void proj_run(gdr_op_s* op, gdr_defl_s* defl, int nmem, int ns,
                 S.prof.end(GDR_K_DSLASH, dslash_bytes<double>(op, na, true), dslash_flops(op, na));
                 if (S.st) S.st->mvp_fp64 += na;
             }
-            cgs_pass<double, double>(CGS_DOT, nullptr, 0, 0, 0, W + (int64_t)ns * n, wms, nullptr,
-                                     0, nullptr, 0, A.partial, A.nblk, n, nmem, st, act);
+            gs_dot<double, double>(nullptr, 0, 0, 0, W + (int64_t)ns * n, wms, nullptr, 0,
+                                   A.partial, A.nblk, n, nmem, st, act);
             reduce_cols(A.partial, A.nblk, 1, rn2, 1, nullptr, 0, nmem, st, act);
             HIPCHK(hipMemcpyAsync(rnh.data(), rn2, nmem * sizeof(double2), hipMemcpyDeviceToHost, st));
         }
@@ -664,8 +655,8 @@ static std::vector<double2> vk1_dot_residuals(gdr_defl_s* d, int ns, const doubl
     }
     dslash<double>(xs + n, n, Rt, n, rhs, 0, op->u64, GDR_LINKS_F64, op->g, op->kappa, dl, ns - 1,
                    st);
-    cgs_pass<T, double>(CGS_DOT, (const C*)d->V + (int64_t)d->k * n, n, 0, 1, Rt, n, nullptr, 0,
-                        nullptr, 0, part, nblk, n, ns - 1, st);
+    gs_dot<T, double>((const C*)d->V + (int64_t)d->k * n, n, 0, 1, Rt, n, nullptr, 0, part, nblk,
+                      n, ns - 1, st);
     reduce_cols(part, nblk, 2, g, 2, nullptr, 0, ns - 1, st);
     std::vector<double2> gh(2 * (ns - 1));
     HIPCHK(hipMemcpyAsync(gh.data(), g, gh.size() * sizeof(double2), hipMemcpyDeviceToHost, st));
@@ -833,8 +824,7 @@ static std::vector<double> norms(gdr_op_s* op, const double2* R, int nv) {
     const int nblk = cgs_nblk(op->n);
     double2* part = mem.get<double2>((size_t)nblk * nv);
     double2* out = mem.get<double2>(nv);
-    cgs_pass<double, double>(CGS_DOT, nullptr, 0, 0, 0, R, op->n, nullptr, 0, nullptr, 0, part,
-                             nblk, op->n, nv, st);
+    gs_dot<double, double>(nullptr, 0, 0, 0, R, op->n, nullptr, 0, part, nblk, op->n, nv, st);
     reduce_cols(part, nblk, 1, out, 1, nullptr, 0, nv, st);
     std::vector<double2> h(nv);
     HIPCHK(hipMemcpyAsync(h.data(), out, nv * sizeof(double2), hipMemcpyDeviceToHost, st));

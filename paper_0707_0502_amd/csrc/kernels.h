@@ -59,42 +59,13 @@ void dcgs_coef(const double2* G, int64_t g_ms, int j, int nx, int first, double2
                int nmem, hipStream_t st, const int* act = nullptr);
 
 // ------------------------------------------------------------ BLAS (blas.hip)
-// Block-partial buffers: partial[(member*ncols_tot + col)*nblk + blk] (double2)
+// Block-partial buffers: partial[(member*ncols_tot + col)*nblk + blk] (double2);
+// blocks per sweep over n rows
 int cgs_nblk(int64_t n);
-
-enum CgsMode { CGS_DOT = 0, CGS_UPDATE_DOT = 1, CGS_UPDATE_NORM = 2, CGS_UPDATE = 3 };
-
-// Batched over members b < nmem (blockIdx.y). Per member:
-//   V  = Vb + b*v_mstride, column j at V + j*ldv (type T), ncols columns
-//   DOT        : partial[0..ncols) = V^H win, partial[ncols] = ||win||^2 (win type T)
-//   UPDATE_DOT : wd = win - V h ; partial = V^H wd               (win T, wd double)
-//   UPDATE_NORM: wd = wd - V h ; partial[0] = ||wd||^2
-//   UPDATE     : wd = wd - V h (or win - V h if win != null)
-// h: double2 [ncols] at h + b*h_mstride (device).
-// TW: type of win (T, or double for the FP64 residual against an FP32 basis in DOT mode)
-template <typename T, typename TW>
-void cgs_pass(int mode, const typename CT<T>::t* V, int64_t ldv, int64_t v_mstride, int ncols,
-              const typename CT<TW>::t* win, int64_t win_mstride, double2* wd, int64_t wd_mstride,
-              const double2* h, int64_t h_mstride, double2* partial, int nblk, int64_t n, int nmem,
-              hipStream_t st, const int* act = nullptr);
 
 // out[b*out_mstride + c] (+)= sum_blk partial[(b*ncols + c)*nblk + blk], c < ncols
 void reduce_cols(const double2* partial, int nblk, int ncols, double2* out, int64_t out_mstride,
                  double2* add_to, int64_t add_mstride, int nmem, hipStream_t st,
-                 const int* act = nullptr);
-
-// Norm finish for Arnoldi step j of every member: ||w|| = sqrt(sum partial[..].x);
-// H[(j*ldh) + j+1] = ||w||, inv[b] = 1/||w|| or 0 on breakdown (||w|| <= tol_rel*sqrt(w0sq)),
-// brk[b] = j when breakdown happens first. w0sq = ||A v_j||^2 from the DOT pass (out of
-// reduce_cols at h1[ncols]).
-void norm_finish(const double2* partial, int nblk, double2* H, int64_t ldh, int64_t h_mstride,
-                 int j, const double2* w0, int64_t w0_mstride, double* inv, int* brk,
-                 double tol_rel, int nmem, hipStream_t st, const int* act = nullptr);
-
-// v = (T)(wd * inv[b]) batched
-template <typename T>
-void scale_store(const double2* wd, int64_t wd_mstride, const double* inv,
-                 typename CT<T>::t* v, int64_t v_mstride, int64_t n, int nmem, hipStream_t st,
                  const int* act = nullptr);
 
 // out_s = beta_s * out_s + sum_{l<ncols} V_l * coef[l + s*ldc]   (FP64 outputs)
