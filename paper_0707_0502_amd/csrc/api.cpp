@@ -94,11 +94,26 @@ int gdr_ctx_create(int device, void* hip_stream, gdr_ctx* out) {
     gdr_ctx_s* c = new gdr_ctx_s;
     c->device = device;
     c->st = (hipStream_t)hip_stream;
+    if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+        gdr_ctx_destroy(c);
+        return GDR_ERR_HIP;
+    }
     *out = c;
     return GDR_OK;
 }
 
-void gdr_ctx_destroy(gdr_ctx c) { delete c; }
+void gdr_ctx_destroy(gdr_ctx c) {
+    if (!c) return;
+    if (c->aux) {
+        (void)hipStreamSynchronize(c->aux);
+        (void)hipStreamDestroy(c->aux);
+    }
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    delete c;
+}
 
 const char* gdr_last_error(gdr_ctx c) { return c ? c->err.c_str() : "null context"; }
 

@@ -274,7 +274,7 @@ static int dr_run(gdr_op_s* op, int ns, const double2* sig_h, const double2* b_e
         a.brk = A.brk;
         a.coef = coef;
         a.out = &outs[cur];
-        a.restart = 1;
+        a.restart = 0;
         a.k = k;
         a.P = P;
         a.Hnew = Hx;
@@ -284,6 +284,20 @@ static int dr_run(gdr_op_s* op, int ns, const double2* sig_h, const double2* b_e
         S.prof.begin(GDR_K_SMALL);
         cycle_small(a, 1, st);
         S.prof.end(GDR_K_SMALL, 0, 0);
+        // the restart half (harmonic Ritz, Schur form, P, new H and c) runs on
+        // the auxiliary stream while the solution update and the FP64 residual
+        // run here; nothing below reads its outputs before the join
+        gdr_ctx_s* cx_ = op->ctx;
+        HIPCHK(hipEventRecord(cx_->ev_fork, st));
+        HIPCHK(hipStreamWaitEvent(cx_->aux, cx_->ev_fork, 0));
+        {
+            CycleArgs ar = a;
+            ar.restart = 2;
+            hipEvent_t pm = S.prof.mark(GDR_K_SMALL, cx_->aux);
+            cycle_small(ar, 1, cx_->aux);
+            S.prof.span(GDR_K_SMALL, pm, cx_->aux, 0, 0);
+        }
+        HIPCHK(hipEventRecord(cx_->ev_join, cx_->aux));
         S.prof.begin(GDR_K_COMBINE);
         vcombine<T>(Vc, n, 0, m, coef, m + 1, 0, ns, X, n, 0, allx, n, 1, st);
         S.prof.end(GDR_K_COMBINE, (double)n * (m * sizeof(C) + 32.0 * ns), (double)n * m * ns * 8);
@@ -298,6 +312,7 @@ static int dr_run(gdr_op_s* op, int ns, const double2* sig_h, const double2* b_e
             S.prof.end(GDR_K_DSLASH, dslash_bytes<double>(op, 1, true), dslash_flops(op, 1));
             if (S.st) S.st->mvp_fp64 += 1;
         }
+        HIPCHK(hipStreamWaitEvent(st, cx_->ev_join, 0));
         CycleOut o;
         HIPCHK(hipMemcpyAsync(&o, &outs[cur], sizeof(CycleOut), hipMemcpyDeviceToHost, st));
         HIPCHK(hipMemcpyAsync(&brk, A.brk, sizeof(int), hipMemcpyDeviceToHost, st));

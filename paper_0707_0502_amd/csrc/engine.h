@@ -24,7 +24,9 @@ struct GdrError : std::runtime_error {
 
 struct gdr_ctx_s {
     int device = 0;
-    hipStream_t st = nullptr;
+    hipStream_t st = nullptr;    // caller's stream: every result is ordered on it
+    hipStream_t aux = nullptr;   // library stream for work that overlaps st
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::string err;
 };
 
@@ -109,9 +111,22 @@ struct Prof {
         pend.push_back({cls, b, f, cur, e});
         if (pend.size() > 2048) harvest();
     }
+    // interval on another stream: mark() before the work, span() after it
+    hipEvent_t mark(int cls, hipStream_t s) {
+        if (!on(cls)) return nullptr;
+        hipEvent_t e = get();
+        HIPCHK(hipEventRecord(e, s));
+        return e;
+    }
+    void span(int cls, hipEvent_t a, hipStream_t s, double b, double f) {
+        if (!on(cls) || !a) return;
+        hipEvent_t e = get();
+        HIPCHK(hipEventRecord(e, s));
+        pend.push_back({cls, b, f, a, e});
+    }
     void harvest() {
         if (pend.empty()) return;
-        HIPCHK(hipEventSynchronize(pend.back().b));
+        for (auto& r : pend) HIPCHK(hipEventSynchronize(r.b));
         for (auto& r : pend) {
             float t = 0;
             HIPCHK(hipEventElapsedTime(&t, r.a, r.b));

@@ -29,7 +29,8 @@ struct CycleArgs {
     double2* coef;          // (m+1) x (ns+1) column-major: d_i padded, last column s
     int64_t coef_ms;
     CycleOut* out;          // per member
-    // restart (block 0 of member 0 only, when k > 0 or restart requested)
+    // 0: least squares only; 1: least squares and GMRES-DR restart (block 0);
+    // 2: restart only (one block per member; s read from the coefficient block)
     int restart;
     int k;
     double2* P;             // (m+1) x (k+1), ldp = m+1

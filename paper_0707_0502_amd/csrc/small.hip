@@ -369,28 +369,34 @@ __global__ __launch_bounds__(64) void k_cycle_small(CycleArgs a) {
     __shared__ double2 rots[MAXM];
 
     long long t_start = wall_clock64();
-    // ---- base least squares: [Hs | c], Hs = H - sigma_1 I_bar, (p+1) x p
     const double2 s1 = sig[0];
-    for (int c = 0; c <= p; ++c)
+    const bool restart_only = a.restart == 2;
+    if (!restart_only) {
+        // ---- base least squares: [Hs | c], Hs = H - sigma_1 I_bar, (p+1) x p
+        for (int c = 0; c <= p; ++c)
+            for (int r = lane; r <= p; r += 64) {
+                double2 v = c < p ? H[c * ldh + r] : cg[r];
+                if (c < p && r == c) v = csub(v, s1);
+                AT(A, r, c) = v;
+            }
+        __syncthreads();
+        hh_qr(A, p + 1, p, p + 1, hv);
+        for (int r = lane; r < p; r += 64) dv[r] = AT(A, r, p);
+        __syncthreads();
+        back_sub(A, p, dv);
+        // s = c - Hs d_1 (from the original entries)
         for (int r = lane; r <= p; r += 64) {
-            double2 v = c < p ? H[c * ldh + r] : cg[r];
-            if (c < p && r == c) v = csub(v, s1);
-            AT(A, r, c) = v;
+            double2 acc = cg[r];
+            for (int c = 0; c < p; ++c) {
+                double2 h = H[c * ldh + r];
+                if (r == c) h = csub(h, s1);
+                acc = csub(acc, cmul(h, dv[c]));
+            }
+            sv[r] = acc;
         }
-    __syncthreads();
-    hh_qr(A, p + 1, p, p + 1, hv);
-    for (int r = lane; r < p; r += 64) dv[r] = AT(A, r, p);
-    __syncthreads();
-    back_sub(A, p, dv);
-    // s = c - Hs d_1 (from the original entries)
-    for (int r = lane; r <= p; r += 64) {
-        double2 acc = cg[r];
-        for (int c = 0; c < p; ++c) {
-            double2 h = H[c * ldh + r];
-            if (r == c) h = csub(h, s1);
-            acc = csub(acc, cmul(h, dv[c]));
-        }
-        sv[r] = acc;
+    } else {
+        // restart half of a split cycle: s was written by the least-squares half
+        for (int r = lane; r <= p; r += 64) sv[r] = coef[ns * (m + 1) + r];
     }
     __syncthreads();
     double sn = 0, cn = 0;
@@ -404,15 +410,17 @@ __global__ __launch_bounds__(64) void k_cycle_small(CycleArgs a) {
     __syncthreads();
 
     if (role == 0) {
-        for (int r = lane; r <= m; r += 64) {
-            coef[r] = r < p ? dv[r] : mk(0, 0);
-            coef[ns * (m + 1) + r] = r <= p ? sv[r] : mk(0, 0);
+        if (!restart_only) {
+            for (int r = lane; r <= m; r += 64) {
+                coef[r] = r < p ? dv[r] : mk(0, 0);
+                coef[ns * (m + 1) + r] = r <= p ? sv[r] : mk(0, 0);
+            }
+            if (lane == 0) {
+                out->snorm = sn;
+                out->beta[0] = mk(1, 0);
+            }
         }
-        if (lane == 0) {
-            out->snorm = sn;
-            out->beta[0] = mk(1, 0);
-        }
-        if (!a.restart || exact || p < m) return;
+        if (a.restart == 0 || exact || p < m) return;
         // ---------------- GMRES-DR restart (harmonic Ritz, base shift)
         const int k = a.k;
         if (lane == 0) {
@@ -458,7 +466,7 @@ __global__ __launch_bounds__(64) void k_cycle_small(CycleArgs a) {
         if (lane == 0) out->tclk[7] = nrot;
         if (lane == 0) out->tclk[4] = wall_clock64();
         if (fail) {
-            if (lane == 0) out->flags |= 2;
+            if (lane == 0) atomicOr(&out->flags, 2);
             return;
         }
         // selection: k smallest |theta| moved to the top, in order
@@ -584,7 +592,7 @@ __global__ __launch_bounds__(64) void k_cycle_small(CycleArgs a) {
 }
 
 void cycle_small(const CycleArgs& a, int nmem, hipStream_t st) {
-    hipLaunchKernelGGL(k_cycle_small, dim3(a.ns, nmem), dim3(64), 0, st, a);
+    hipLaunchKernelGGL(k_cycle_small, dim3(a.restart == 2 ? 1 : a.ns, nmem), dim3(64), 0, st, a);
 }
 
 // ---------------------------------------------------------------------------
