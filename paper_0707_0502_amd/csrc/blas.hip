@@ -87,11 +87,14 @@ __global__ __launch_bounds__(256) void k_gs_dot(
     const int64_t r1 = r0 + per < n ? r0 + per : n;
     const int nval = NX * nc + 1;
     double2* pout = partial + (int64_t)mem * nval * nblk + blockIdx.x;
+    // columns per accumulation pass: 2 vectors x 6 columns keep the FP64
+    // accumulators within 4 waves per SIMD
+    constexpr int CW = NX > 1 ? 6 : 8;
     const int g = (nc + 3) >> 2;
     const int c0 = wv * g;
     const int c1 = c0 + g < nc ? c0 + g : nc;
-    for (int cs = c0; cs < c1; cs += 8) {
-        const int cnt = c1 - cs < 8 ? c1 - cs : 8;
+    for (int cs = c0; cs < c1; cs += CW) {
+        const int cnt = c1 - cs < CW ? c1 - cs : CW;
         double2 acc[16];
 #pragma unroll
         for (int q = 0; q < 16; ++q) acc[q] = mk(0, 0);
@@ -99,12 +102,12 @@ __global__ __launch_bounds__(256) void k_gs_dot(
         for (int64_t i = r0 + lane; i < r1; i += 64) {
             const double2 xa = to_d(x0[i]);
             const double2 xb = NX > 1 ? to_d(x1[i]) : mk(0, 0);
-            typename CT<T>::t vr[8];
+            typename CT<T>::t vr[CW];
 #pragma unroll
-            for (int c = 0; c < 8; ++c)
+            for (int c = 0; c < CW; ++c)
                 if (c < cnt) vr[c] = vp[(int64_t)c * ldv + i];
 #pragma unroll
-            for (int c = 0; c < 8; ++c)
+            for (int c = 0; c < CW; ++c)
                 if (c < cnt) {
                     const double2 v = to_d(vr[c]);
                     acc[c] = cadd(acc[c], cjmul(v, xa));
