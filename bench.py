@@ -77,6 +77,27 @@ def cpu_baseline(cfg, links, kappa, b, sec_budget, gpu_steps):
                 seconds=time.perf_counter() - t_start, threads=int(threads))
 
 
+def dslash_standalone(gdr, ops, vol, reps=100, nsets=3):
+    """The Wilson operator alone: median per-launch time over `reps` launches
+    rotating over `nsets` buffer sets (so the 256 MB Infinity Cache cannot hold
+    one set), batch sizes 1, 3, 11, 12. Algorithmic bytes per launch count each
+    link and spinor once (links amortised over the batch): FP32 links
+    (288 + 192 nb) B/site, FP16 links (144 + 192 nb), FP64 (576 + 384 nb)."""
+    import numpy as np
+    rows = []
+    per_site = {"f32": (288.0, 192.0), "f16link": (144.0, 192.0), "f64": (576.0, 384.0)}
+    for name, (op, prec) in ops.items():
+        for nb in (1, 3, 11, 12):
+            ms = gdr.gdr_op_dslash_bench(op, prec, nb, nsets, reps)
+            med = float(np.median(ms))
+            lk, sp = per_site[name]
+            gbs = (lk + sp * nb) * vol / (med * 1e-3) / 1e9
+            rows.append(dict(variant=name, nvec=nb, us_median=med * 1e3, gbs=gbs,
+                             frac=gbs / HBM_PEAK_GBS))
+            log("bench: dslash %s nb=%d %.1f us %.0f GB/s" % (name, nb, med * 1e3, gbs))
+    return rows
+
+
 def arnoldi_columns(st, cfg, nrhs):
     """Arnoldi steps of one solve as a list of basis widths j+1 (for the CPU
     extrapolation), from the library's counters."""
@@ -100,6 +121,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-dslash", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -182,6 +204,14 @@ def main():
         log("bench: fp64", fp64)
         del X64
 
+    dsl = None
+    if not a.no_dslash:
+        op16 = gdr.gdr_wilson_create(ctx, dims, (1, 1, 1, -1), kappa, links, gdr.GDR_LINKS_F16)
+        dsl = dslash_standalone(gdr, {"f32": (op, gdr.GDR_PREC_F32),
+                                      "f16link": (op16, gdr.GDR_PREC_F32),
+                                      "f64": (op, gdr.GDR_PREC_F64)}, n // 12)
+        del op16
+
     cpu = None
     if not a.no_cpu:
         b0 = Bd[:n].cpu().numpy()
@@ -214,8 +244,10 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel_share_of_timed_kernel_ms": kd["ms"] / total_ms if total_ms else None},
-        "dslash": {"gbs": dslash_gbs, "frac": (dslash_gbs / HBM_PEAK_GBS) if dslash_gbs else None,
-                   "launches": ds["launches"]},
+        "dslash": {"in_solver_gbs": dslash_gbs,
+                   "in_solver_frac": (dslash_gbs / HBM_PEAK_GBS) if dslash_gbs else None,
+                   "in_solver_launches": ds["launches"],
+                   "standalone": dsl},
         "fp64": fp64,
         "cpu_baseline": cpu,
         "max_true_resid": resid_max,

@@ -84,8 +84,8 @@ const char* gdr_last_error(gdr_ctx ctx);
  * Lx x Ly x Lz x Lt lattice, dims = {Lx, Ly, Lz, Lt}, every extent even and
  * >= 2. bc[mu] is +1 (periodic) or -1 (antiperiodic). `links` is host memory
  * (links_on_device = 0) or device memory (1) in the canonical link layout;
- * it is copied into internal even-odd layouts (FP64 always, plus FP32 or
- * FP16 per link_storage for the FP32 operator) and not retained.
+ * it is copied into internal tile-blocked layouts (FP64 always, plus FP32
+ * or FP16 per link_storage for the FP32 operator) and not retained.
  * Errors: ARG, OOM, HIP. */
 int gdr_wilson_create(gdr_ctx ctx, const int dims[4], const int bc[4], double kappa,
                       const gdr_c64* links, int links_on_device, int link_storage,
@@ -107,6 +107,19 @@ int gdr_op_apply(gdr_op op, gdr_c64 sigma, const gdr_c64* x, gdr_c64* y, int nve
  * and sign[eo][d] = -1 where the hop crosses the time boundary. Host buffers
  * of V, 8V and 8V entries, computed on the device. Errors: ARG, HIP. */
 int gdr_op_tables(gdr_op op, int32_t* eo_of_lex, int32_t* nbr, int8_t* sign);
+
+/* Measurement hook for the operator alone (the matrix-vector product of
+ * Sec. 4, Example 7): `reps` launches of y = (A - sigma I) x on nvec vectors
+ * held in the library's internal layout, rotating over `nsets` separate
+ * input/output buffer sets (allocated and filled by the library, so that the
+ * 256 MB Infinity Cache cannot keep one set resident), each launch timed with
+ * HIP events on the context stream. precision GDR_PREC_F64 (FP64 vectors and
+ * links) or GDR_PREC_F32 (FP32 vectors, the op's FP32 or FP16 links).
+ * ms_each: caller host array of `reps` entries (per-launch milliseconds).
+ * 1 <= nvec <= 16, 1 <= nsets <= 8, 1 <= reps <= 100000.
+ * Errors: ARG, OOM, HIP. */
+int gdr_op_dslash_bench(gdr_op op, int precision, int nvec, int nsets, int reps,
+                        double* ms_each);
 
 /* ------------------------------------------------------------ parameters */
 

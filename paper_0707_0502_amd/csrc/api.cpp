@@ -69,6 +69,49 @@ void stats_reset(gdr_stats* st) {
     st->resid_main = 0;
 }
 
+template <typename T>
+void dslash_bench_run(gdr_op op, int nvec, int nsets, int reps, double* ms_each) {
+    using C = typename CT<T>::t;
+    gdr_ctx_s* c = op->ctx;
+    const int64_t n = op->n;
+    DMem mem;
+    std::vector<C*> xin(nsets), yout(nsets);
+    for (int k = 0; k < nsets; ++k) {
+        xin[k] = mem.get<C>((size_t)n * nvec);
+        yout[k] = mem.get<C>((size_t)n * nvec);
+        // a finite bit pattern: the timing does not depend on the values
+        HIPCHK(hipMemsetAsync(xin[k], 0x3c, (size_t)n * nvec * sizeof(C), c->st));
+    }
+    DiagList dl{};
+    for (int v = 0; v < DSLASH_MAXV; ++v) {
+        dl.d[v] = make_double2(1, 0);
+        dl.alpha[v] = 1;
+    }
+    const void* lk = std::is_same<T, double>::value ? (const void*)op->u64 : op->ulo;
+    const int lst = std::is_same<T, double>::value ? GDR_LINKS_F64 : op->lst;
+    std::vector<hipEvent_t> ev(2 * reps);
+    for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+    try {
+        for (int r = 0; r < reps; ++r) {
+            const int k = r % nsets;
+            HIPCHK(hipEventRecord(ev[2 * r], c->st));
+            dslash<T>(xin[k], n, yout[k], n, nullptr, 0, lk, lst, op->g, op->kappa, dl, nvec, c->st);
+            HIPCHK(hipEventRecord(ev[2 * r + 1], c->st));
+        }
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(c->st));
+        for (int r = 0; r < reps; ++r) {
+            float t = 0;
+            HIPCHK(hipEventElapsedTime(&t, ev[2 * r], ev[2 * r + 1]));
+            ms_each[r] = t;
+        }
+    } catch (...) {
+        for (auto& e : ev) (void)hipEventDestroy(e);
+        throw;
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+}
+
 }  // namespace
 
 #define API_TRY(c) try {
@@ -251,6 +294,26 @@ int gdr_op_tables(gdr_op op, int32_t* eo_of_lex, int32_t* nbr, int8_t* sign) {
     HIPCHK(hipMemcpyAsync(nbr, nb, 8 * vol * sizeof(int32_t), hipMemcpyDeviceToHost, c->st));
     HIPCHK(hipMemcpyAsync(sign, sg, 8 * vol, hipMemcpyDeviceToHost, c->st));
     HIPCHK(hipStreamSynchronize(c->st));
+    return GDR_OK;
+    API_CATCH(c)
+}
+
+int gdr_op_dslash_bench(gdr_op op, int precision, int nvec, int nsets, int reps,
+                        double* ms_each) {
+    if (!op) return GDR_ERR_ARG;
+    gdr_ctx_s* c = op->ctx;
+    if (!ms_each) return fail(c, GDR_ERR_ARG, "null ms_each");
+    if (nvec < 1 || nvec > DSLASH_MAXV) return fail(c, GDR_ERR_ARG, "nvec must be 1..16");
+    if (nsets < 1 || nsets > 8) return fail(c, GDR_ERR_ARG, "nsets must be 1..8");
+    if (reps < 1 || reps > 100000) return fail(c, GDR_ERR_ARG, "reps must be 1..100000");
+    if (precision != GDR_PREC_F64 && precision != GDR_PREC_F32)
+        return fail(c, GDR_ERR_ARG, "precision must be F64 or F32");
+    API_TRY(c)
+    HIPCHK(hipSetDevice(c->device));
+    if (precision == GDR_PREC_F64)
+        dslash_bench_run<double>(op, nvec, nsets, reps, ms_each);
+    else
+        dslash_bench_run<float>(op, nvec, nsets, reps, ms_each);
     return GDR_OK;
     API_CATCH(c)
 }

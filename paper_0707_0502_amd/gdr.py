@@ -31,7 +31,8 @@ K_CLASSES = ["dslash", "cgs_dot", "cgs_update_dot", "cgs_update_norm", "small", 
 
 SYMBOLS = [
     "gdr_ctx_create", "gdr_ctx_destroy", "gdr_last_error", "gdr_wilson_create",
-    "gdr_op_destroy", "gdr_op_size", "gdr_op_apply", "gdr_op_tables", "gdr_params_default",
+    "gdr_op_destroy", "gdr_op_size", "gdr_op_apply", "gdr_op_tables", "gdr_op_dslash_bench",
+    "gdr_params_default",
     "gdr_solve_dr_sh", "gdr_solve_proj_sh", "gdr_solve", "gdr_defl_k", "gdr_defl_export",
     "gdr_defl_import", "gdr_defl_destroy",
 ]
@@ -89,6 +90,7 @@ def load(path=LIB_PATH):
     lib.gdr_op_size.restype = i64
     lib.gdr_op_apply.argtypes = [vp, gdr_c64, vp, vp, ip, ip]
     lib.gdr_op_tables.argtypes = [vp, vp, vp, vp]
+    lib.gdr_op_dslash_bench.argtypes = [vp, ip, ip, ip, ip, vp]
     lib.gdr_params_default.argtypes = [ctypes.POINTER(gdr_params)]
     lib.gdr_params_default.restype = None
     lib.gdr_solve_dr_sh.argtypes = [vp, ip, ctypes.POINTER(gdr_c64), vp, vp,
@@ -253,6 +255,14 @@ def gdr_op_tables(op):
     sign = np.zeros((vol, 8), np.int8)
     op.ctx.check(lib().gdr_op_tables(op.h, _ptr(eo), _ptr(nbr), _ptr(sign)))
     return eo, nbr, sign
+
+
+def gdr_op_dslash_bench(op, precision, nvec, nsets, reps):
+    """Per-launch milliseconds of `reps` operator launches on nvec vectors in the
+    internal layout, rotating over nsets buffer sets."""
+    ms = np.zeros(reps, np.float64)
+    op.ctx.check(lib().gdr_op_dslash_bench(op.h, precision, nvec, nsets, reps, _ptr(ms)))
+    return ms
 
 
 def gdr_solve_dr_sh(op, sigmas, b, x, params, stats=None, want_defl=True):
