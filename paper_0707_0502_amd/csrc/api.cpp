@@ -388,7 +388,7 @@ int gdr_solve_proj_sh(gdr_op op, gdr_defl defl, int ns, const gdr_c64* sigma, in
     double2* Xeo = mem.get<double2>((size_t)nrhs * ns * n);
     pack_spinor<double>((const double2*)B, Beo, n, op->g, nrhs, c->st);
     Stats S(st, (unsigned)p->profile, c->st);
-    int rc = solve_proj_batch(op, defl, ns, (const double2*)sigma, nrhs, Beo, Xeo, *p, S);
+    int rc = solve_proj_batch(op, defl, ns, (const double2*)sigma, nrhs, Beo, Xeo, 0, *p, S);
     if (p->precision == GDR_PREC_MIXED) {
         Timer tc;
         rc = cleanup(op, defl, ns, (const double2*)sigma, nrhs, Beo, Xeo, *p, S);
@@ -432,7 +432,7 @@ int gdr_solve(gdr_op op, int ns, const gdr_c64* sigma, int nrhs, const gdr_c64* 
     if (nrhs > 1) {
         if (!d) throw GdrError(GDR_ERR_BREAKDOWN, "first solve ended in a lucky breakdown: no deflation space");
         int rc2 = solve_proj_batch(op, d, ns, (const double2*)sigma, nrhs - 1, Beo + n,
-                                   Xeo + (int64_t)ns * n, *p, S);
+                                   Xeo + (int64_t)ns * n, 1, *p, S);
         if (rc2 != GDR_OK) rc = rc2;
     }
     if (p->precision == GDR_PREC_MIXED) {

@@ -420,7 +420,10 @@ template <typename T>
 static void proj_run(gdr_op_s* op, gdr_defl_s* defl, int nmem, int ns,
                      const std::vector<double2>& sig_h, const double2* Bm, double2* W,
                      const std::vector<double>& tol, const std::vector<double>& bnorm, int m,
-                     int max_cycles, Stats& S, const std::vector<int>& phase, ProjResult& R) {
+                     int max_cycles, Stats& S, const std::vector<int>& phase, ProjResult& R,
+                     bool start = false) {
+    // start: W already holds an initial guess x_i and the common residual r
+    // (related right-hand sides, Sec. 5); otherwise x_i = 0, r = b
     using C = typename CT<T>::t;
     constexpr bool mixed = std::is_same<T, float>::value;
     hipStream_t st = op->ctx->st;
@@ -451,8 +454,10 @@ static void proj_run(gdr_op_s* op, gdr_defl_s* defl, int nmem, int ns,
 
     HIPCHK(hipMemcpyAsync(sig, sig_h.data(), (size_t)nmem * ns * sizeof(double2),
                           hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemsetAsync(W, 0, (size_t)wms * nmem * sizeof(double2), st));
-    copy_vec(Bm, n, W + (int64_t)ns * n, wms, n, nmem, st);   // r = b
+    if (!start) {
+        HIPCHK(hipMemsetAsync(W, 0, (size_t)wms * nmem * sizeof(double2), st));
+        copy_vec(Bm, n, W + (int64_t)ns * n, wms, n, nmem, st);   // r = b
+    }
     std::vector<CycleOut> init(2 * nmem);
     for (auto& o : init) {
         o = CycleOut{};
@@ -681,9 +686,62 @@ static std::vector<double2> vk1_dot_residuals(gdr_defl_s* d, int ns, const doubl
     return out;
 }
 
+// Related right-hand sides (Sec. 5, eq. (5.2)): project member b's right-hand
+// side over the earlier ones, Bp = [b^1 .. b^np] (the most recent MAXM):
+// (Bp^H Bp) d = Bp^H b (shift independent), x_i = X_i^{prev} d for every
+// shift, and the common residual r = b - Bp d, written into W (member block
+// [x_1 .. x_ns, r]). The extra right-hand side (id < 0) starts from zero.
+static void related_start(gdr_op_s* op, int ns, const double2* Ball, const double2* Xall,
+                          int nsolved, const std::vector<int>& ids, const double2* Bm, double2* W,
+                          hipStream_t st) {
+    const int64_t n = op->n;
+    const int nmem = (int)ids.size();
+    const int64_t wms = (int64_t)(ns + 1) * n;
+    const int np = std::min(nsolved, MAXM);
+    const double2* Bp = Ball + (int64_t)(nsolved - np) * n;
+    const double2* Xp = Xall + (int64_t)(nsolved - np) * ns * n;
+    DMem mem;
+    const int nblk = cgs_nblk(n);
+    double2* part = mem.get<double2>((size_t)(np + 1) * nblk * std::max(np, nmem));
+    double2* G = mem.get<double2>((size_t)(np + 1) * np);
+    double2* g = mem.get<double2>((size_t)(np + 1) * nmem);
+    double2* dv = mem.get<double2>((size_t)np * nmem);
+    double2* dn = mem.get<double2>((size_t)np * nmem);
+    // G column l = Bp^H b^l; g_b = Bp^H b_b (each with a norm slot, ignored)
+    gs_dot<double, double>(Bp, n, 0, np, Bp, n, nullptr, 0, part, nblk, n, np, st);
+    reduce_cols(part, nblk, np + 1, G, np + 1, nullptr, 0, np, st);
+    gs_dot<double, double>(Bp, n, 0, np, Bm, n, nullptr, 0, part, nblk, n, nmem, st);
+    reduce_cols(part, nblk, np + 1, g, np + 1, nullptr, 0, nmem, st);
+    // compact G to ld np
+    double2* Gc = mem.get<double2>((size_t)np * np);
+    for (int l = 0; l < np; ++l)
+        HIPCHK(hipMemcpyAsync(Gc + (int64_t)l * np, G + (int64_t)l * (np + 1), np * sizeof(double2),
+                              hipMemcpyDeviceToDevice, st));
+    gram_solve(Gc, np, g, np + 1, dv, dn, np, nmem, st);
+    HIPCHK(hipMemsetAsync(W, 0, (size_t)wms * nmem * sizeof(double2), st));
+    copy_vec(Bm, n, W + (int64_t)ns * n, wms, n, nmem, st);
+    std::vector<int> acth(nmem);
+    for (int b = 0; b < nmem; ++b) acth[b] = ids[b] >= 0;
+    int* act = mem.get<int>(nmem);
+    HIPCHK(hipMemcpyAsync(act, acth.data(), nmem * sizeof(int), hipMemcpyHostToDevice, st));
+    // x_i = sum_l d_l x_i^l  (previous solutions of shift i are ns*n apart)
+    for (int i = 0; i < ns; ++i)
+        vcombine<double>(Xp + (int64_t)i * n, (int64_t)ns * n, 0, np, dv, np, np, 1, W + (int64_t)i * n,
+                         n, wms, 0u, n, nmem, st, act);
+    // r = b - Bp d
+    vcombine<double>(Bp, n, 0, np, dn, np, np, 1, W + (int64_t)ns * n, n, wms, 1u, n, nmem, st, act);
+    HIPCHK(hipStreamSynchronize(st));
+}
+
+// Later right-hand sides B_eo[0..nrhs) (and the extra right-hand side when
+// needed) by GMRES-Proj-Sh with the correction. The nprev right-hand sides
+// stored just before B_eo (and their solutions just before X_eo) are already
+// solved; with p.related_rhs every batch first projects over all right-hand
+// sides solved before it (Sec. 5, eq. (5.2)).
 template <typename T>
 static int proj_batch(gdr_op_s* op, gdr_defl_s* d, int ns, const double2* sig_h, int nrhs,
-                      const double2* B_eo, double2* X_eo, const gdr_params& p, Stats& S) {
+                      const double2* B_eo, double2* X_eo, int nprev, const gdr_params& p,
+                      Stats& S) {
     hipStream_t st = op->ctx->st;
     const int64_t n = op->n;
     const int m = p.m_proj;
@@ -737,10 +795,24 @@ static int proj_batch(gdr_op_s* op, gdr_defl_s* d, int ns, const double2* sig_h,
         ProjResult R;
         using clock = std::chrono::steady_clock;
         auto t0 = clock::now();
+        // right-hand sides solved before this batch: the nprev given ones and
+        // the earlier batches' (their solutions are final: corrected below)
+        int first_b = -1;
+        for (int b = 0; b < nmem; ++b)
+            if (ids[b] >= 0) {
+                first_b = ids[b];
+                break;
+            }
+        const int nsolved = first_b >= 0 ? nprev + first_b : 0;
+        const bool related = p.related_rhs && nsolved > 0;
+        if (related) related_start(op, ns, B_eo - (int64_t)nprev * n, X_eo - (int64_t)nprev * ns * n,
+                                   nsolved, ids, Bm, W, st);
         if (d->prec == GDR_PREC_MIXED)
-            proj_run<float>(op, d, nmem, ns, sgm, Bm, W, tol, bnorm, m, p.max_cycles, S, phase, R);
+            proj_run<float>(op, d, nmem, ns, sgm, Bm, W, tol, bnorm, m, p.max_cycles, S, phase, R,
+                            related);
         else
-            proj_run<double>(op, d, nmem, ns, sgm, Bm, W, tol, bnorm, m, p.max_cycles, S, phase, R);
+            proj_run<double>(op, d, nmem, ns, sgm, Bm, W, tol, bnorm, m, p.max_cycles, S, phase, R,
+                             related);
         HIPCHK(hipStreamSynchronize(st));
         auto t1 = clock::now();
         if (S.st) S.st->t_phase[2] += std::chrono::duration<double>(t1 - t0).count();
@@ -811,9 +883,10 @@ static int proj_batch(gdr_op_s* op, gdr_defl_s* d, int ns, const double2* sig_h,
 }
 
 int solve_proj_batch(gdr_op_s* op, gdr_defl_s* defl, int ns, const double2* sig, int nrhs,
-                     const double2* B_eo, double2* X_eo, const gdr_params& p, Stats& S) {
-    if (defl->prec == GDR_PREC_MIXED) return proj_batch<float>(op, defl, ns, sig, nrhs, B_eo, X_eo, p, S);
-    return proj_batch<double>(op, defl, ns, sig, nrhs, B_eo, X_eo, p, S);
+                     const double2* B_eo, double2* X_eo, int nprev, const gdr_params& p, Stats& S) {
+    if (defl->prec == GDR_PREC_MIXED)
+        return proj_batch<float>(op, defl, ns, sig, nrhs, B_eo, X_eo, nprev, p, S);
+    return proj_batch<double>(op, defl, ns, sig, nrhs, B_eo, X_eo, nprev, p, S);
 }
 
 // ---------------------------------------------------------------------------

@@ -186,8 +186,10 @@ struct Stats {
 // whole-problem solver (internal layouts); returns GDR_OK / GDR_NOT_CONVERGED
 int solve_dr_sh(gdr_op_s* op, int ns, const double2* sig, const double2* b_eo, double2* X_eo,
                 const gdr_params& p, Stats& S, gdr_defl_s** defl_out, bool* converged);
+// nprev: right-hand sides (and their solutions) already solved, stored just
+// before B_eo and X_eo, used by the related right-hand side projection
 int solve_proj_batch(gdr_op_s* op, gdr_defl_s* defl, int ns, const double2* sig, int nrhs,
-                     const double2* B_eo, double2* X_eo, const gdr_params& p, Stats& S);
+                     const double2* B_eo, double2* X_eo, int nprev, const gdr_params& p, Stats& S);
 // true FP64 residual norms ||b_j - (A - s_i) x_ij|| / ||b_j||, resid[j*ns + i]
 void true_residuals(gdr_op_s* op, int ns, const double2* sig, int nrhs, const double2* B_eo,
                     const double2* X_eo, std::vector<double>& resid);

@@ -61,5 +61,8 @@ struct ProjArgs {
 
 void cycle_small(const CycleArgs& a, int nmem, hipStream_t st);
 void proj_small(const ProjArgs& a, int nmem, hipStream_t st);
+// (B^H B) d = B^H b for related right-hand sides (np <= MAXM), d and -d per member
+void gram_solve(const double2* G, int np, const double2* rhs, int64_t rhs_ms, double2* dout,
+                double2* dneg, int64_t d_ms, int nmem, hipStream_t st);
 
 }  // namespace gdr

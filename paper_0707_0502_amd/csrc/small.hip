@@ -672,4 +672,85 @@ void proj_small(const ProjArgs& a, int nmem, hipStream_t st) {
     hipLaunchKernelGGL(k_proj_small, dim3(nmem), dim3(64), 0, st, a);
 }
 
+
+// ---------------------------------------------------------------------------
+// Related right-hand sides (Sec. 5, eq. (5.2)): the shift-independent normal
+// equations (B^H B) d = B^H b of the minres projection over earlier
+// right-hand sides, one wavefront per member. G: np x np column-major (ld np)
+// shared by all members; rhs: member b's B^H b at rhs + b*rhs_ms. Gaussian
+// elimination with partial pivoting in LDS (lane = row). Output d at
+// dout + b*d_ms and -d at dneg + b*d_ms; a numerically singular G (pivot
+// below 1e-13 of the largest entry) gives d = 0, i.e. no projection.
+__global__ __launch_bounds__(64) void k_gram_solve(const double2* __restrict__ G, int np,
+                                                   const double2* __restrict__ rhs, int64_t rhs_ms,
+                                                   double2* __restrict__ dout,
+                                                   double2* __restrict__ dneg, int64_t d_ms) {
+    const int lane = threadIdx.x;
+    const int b = blockIdx.x;
+    __shared__ double2 A[(MAXM + 2) * LD];
+    __shared__ double2 x[LD + 1];
+    __shared__ int piv;
+    __shared__ int bad;
+    double gmax = 0;
+    for (int c = 0; c <= np; ++c)
+        for (int r = lane; r < np; r += 64) {
+            const double2 v = c < np ? G[(int64_t)c * np + r] : rhs[b * rhs_ms + r];
+            AT(A, r, c) = v;
+            if (c < np) gmax = fmax(gmax, cabs(v));
+        }
+    for (int o = 32; o >= 1; o >>= 1) gmax = fmax(gmax, __shfl_xor(gmax, o, 64));
+    if (lane == 0) bad = 0;
+    __syncthreads();
+    for (int k = 0; k < np; ++k) {
+        if (lane == 0) {
+            int p = k;
+            double best = cabs(AT(A, k, k));
+            for (int r = k + 1; r < np; ++r) {
+                const double v = cabs(AT(A, r, k));
+                if (v > best) {
+                    best = v;
+                    p = r;
+                }
+            }
+            piv = p;
+            if (!(best > 1e-13 * gmax)) bad = 1;
+        }
+        __syncthreads();
+        if (bad) break;
+        const int p = piv;
+        if (p != k)
+            for (int c = lane; c <= np; c += 64) {
+                const double2 t = AT(A, k, c);
+                AT(A, k, c) = AT(A, p, c);
+                AT(A, p, c) = t;
+            }
+        __syncthreads();
+        const double2 pv = AT(A, k, k);
+        for (int r = k + 1 + lane; r < np; r += 64) {
+            const double2 f = cdiv(AT(A, r, k), pv);
+            for (int c = k + 1; c <= np; ++c) AT(A, r, c) = csub(AT(A, r, c), cmul(f, AT(A, k, c)));
+        }
+        __syncthreads();
+    }
+    if (!bad && lane == 0) {
+        for (int r = np - 1; r >= 0; --r) {
+            double2 acc = AT(A, r, np);
+            for (int c = r + 1; c < np; ++c) acc = csub(acc, cmul(AT(A, r, c), x[c]));
+            x[r] = cdiv(acc, AT(A, r, r));
+        }
+    }
+    __syncthreads();
+    for (int r = lane; r < np; r += 64) {
+        const double2 v = bad ? mk(0, 0) : x[r];
+        dout[b * d_ms + r] = v;
+        dneg[b * d_ms + r] = mk(-v.x, -v.y);
+    }
+}
+
+void gram_solve(const double2* G, int np, const double2* rhs, int64_t rhs_ms, double2* dout,
+                double2* dneg, int64_t d_ms, int nmem, hipStream_t st) {
+    hipLaunchKernelGGL(k_gram_solve, dim3(nmem), dim3(64), 0, st, G, np, rhs, rhs_ms, dout, dneg,
+                       d_ms);
+}
+
 }  // namespace gdr

@@ -162,6 +162,66 @@ def test_c2_mixed_batched(c2):
     gdr.gdr_op_destroy(op)
 
 
+def test_c2_related_rhs_fp64_parity(c2):
+    """Related right-hand sides (Sec. 5, eq. (5.2)), sequential order: every
+    later RHS is first projected over all earlier right-hand sides and their
+    solutions. Same products and solutions as the oracle's driver."""
+    from paper_0707_0502_amd import gdr
+    cfg, links, kappa, B, A, sig, _ = c2
+    say("oracle C2 related ...")
+    ref = gmres.solve_all(A, B, sig, cfg["m_dr"], cfg["k"], cfg["m_proj"], cfg["tol"],
+                          cfg["tol_extra"], related=True)
+    say("C2 FP64 gdr_solve, related right-hand sides, sequential")
+    op = make_op(links, kappa)
+    n = op.n
+    nrhs, ns = B.shape[0], len(sig)
+    X = empty(nrhs * ns * n)
+    st = gdr.Stats(nrhs, ns)
+    p = params(cfg, gdr.GDR_PREC_F64)
+    p.related_rhs = 1
+    p.batch = 0
+    rc = gdr.gdr_solve(op, sig, dev(B.ravel()), X, p, st)
+    d = st.as_dict()
+    say("  rc", rc, d, "oracle proj mvps", [r["mvps"] for r in ref["runs"][1:]])
+    assert rc == gdr.GDR_OK
+    assert d["mvp_proj"] == sum(r["mvps"] for r in ref["runs"][1:])
+    Xh = host(X).reshape(nrhs, ns, n)
+    worst = max(rel(Xh[j, i], ref["X"][j, i]) for j in range(nrhs) for i in range(ns))
+    say("  worst rel err vs oracle", worst)
+    assert worst <= 1e-10
+    # the start is only as accurate as the earlier solutions, so non-base
+    # shifts may end slightly above tol: the oracle's driver does the same
+    for j in range(nrhs):
+        for i in range(ns):
+            assert abs(st.resid[j, i] - ref["resid"][j, i]) <= 1e-3 * ref["resid"][j, i] + 1e-13
+    gdr.gdr_op_destroy(op)
+
+
+def test_c2_related_rhs_mixed_batched(c2):
+    """Related right-hand sides in a batch: each later RHS projects over the
+    first one (solved before the batch); every true residual meets 1e-8."""
+    from paper_0707_0502_amd import gdr
+    cfg, links, kappa, B, A, sig, _ = c2
+    op = make_op(links, kappa)
+    n = op.n
+    nrhs, ns = B.shape[0], len(sig)
+    X = empty(nrhs * ns * n)
+    st = gdr.Stats(nrhs, ns)
+    p = params(cfg, gdr.GDR_PREC_MIXED)
+    p.tol = 1e-8
+    p.tol_extra = 1e-4
+    p.related_rhs = 1
+    rc = gdr.gdr_solve(op, sig, dev(B.ravel()), X, p, st)
+    say("  rc", rc, st.as_dict())
+    Xh = host(X).reshape(nrhs, ns, n)
+    for j in range(nrhs):
+        for i in range(ns):
+            r = np.linalg.norm(gmres.true_residual(A, B[j], Xh[j, i], sig[i])) / np.linalg.norm(B[j])
+            assert r <= 1e-8
+    assert rc == gdr.GDR_OK
+    gdr.gdr_op_destroy(op)
+
+
 def test_k0_is_gmres_sh(c1):
     """k = 0: GMRES(m)-Sh (Sec. 2.1), same iterates as the oracle."""
     from paper_0707_0502_amd import gdr
