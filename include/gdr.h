@@ -91,7 +91,18 @@ int gdr_wilson_create(gdr_ctx ctx, const int dims[4], const int bc[4], double ka
                       const gdr_c64* links, int links_on_device, int link_storage,
                       gdr_op* out);
 void gdr_op_destroy(gdr_op op);
-/* Number of complex unknowns n = 12 * volume. */
+
+/* The bidiagonal test matrix of Examples 1-6 (Sec. 2.1, Sec. 3, Sec. 4) as an
+ * operator for the same solvers: M has diagonal diag[0..n-1] and
+ * superdiagonal super[0..n-2] (Example 1: diag = 0.1, 1, 2, ..., n-1 and
+ * super = 1), host arrays, copied (FP64 plus an FP32 copy for mixed
+ * precision) and not retained; the solvers then solve (M - sigma_i I) x = b.
+ * Vectors are plain complex arrays of n entries. gdr_op_tables and the
+ * lattice-only parts do not apply. Errors: ARG (n < 1, null or non-finite
+ * entries), OOM, HIP. */
+int gdr_bidiag_create(gdr_ctx ctx, int64_t n, const gdr_c64* diag, const gdr_c64* super,
+                      gdr_op* out);
+/* Number of complex unknowns n (12 * volume for the Wilson operator). */
 int64_t gdr_op_size(gdr_op op);
 
 /* y_v = (A - sigma I) x_v for v = 0..nvec-1 (eq. (1.1)), canonical layout,

@@ -87,15 +87,13 @@ void dslash_bench_run(gdr_op op, int nvec, int nsets, int reps, double* ms_each)
         dl.d[v] = make_double2(1, 0);
         dl.alpha[v] = 1;
     }
-    const void* lk = std::is_same<T, double>::value ? (const void*)op->u64 : op->ulo;
-    const int lst = std::is_same<T, double>::value ? GDR_LINKS_F64 : op->lst;
     std::vector<hipEvent_t> ev(2 * reps);
     for (auto& e : ev) HIPCHK(hipEventCreate(&e));
     try {
         for (int r = 0; r < reps; ++r) {
             const int k = r % nsets;
             HIPCHK(hipEventRecord(ev[2 * r], c->st));
-            dslash<T>(xin[k], n, yout[k], n, nullptr, 0, lk, lst, op->g, op->kappa, dl, nvec, c->st);
+            op_apply<T>(op, xin[k], n, yout[k], n, nullptr, 0, dl, nvec, c->st);
             HIPCHK(hipEventRecord(ev[2 * r + 1], c->st));
         }
         HIPCHK(hipGetLastError());
@@ -229,7 +227,47 @@ void gdr_op_destroy(gdr_op op) {
     if (!op) return;
     if (op->u64) (void)hipFree(op->u64);
     if (op->ulo) (void)hipFree(op->ulo);
+    if (op->bd64) (void)hipFree(op->bd64);
+    if (op->bd32) (void)hipFree(op->bd32);
     delete op;
+}
+
+int gdr_bidiag_create(gdr_ctx c, int64_t n, const gdr_c64* diag, const gdr_c64* super,
+                      gdr_op* out) {
+    if (!c || !out) return GDR_ERR_ARG;
+    *out = nullptr;
+    if (n < 1 || n > ((int64_t)1 << 30)) return fail(c, GDR_ERR_ARG, "n must be 1..2^30");
+    if (!diag || (n > 1 && !super)) return fail(c, GDR_ERR_ARG, "null diagonal or superdiagonal");
+    std::vector<double2> h((size_t)2 * n, make_double2(0, 0));
+    for (int64_t i = 0; i < n; ++i) {
+        h[i] = make_double2(diag[i].re, diag[i].im);
+        if (i + 1 < n) h[n + i] = make_double2(super[i].re, super[i].im);
+    }
+    for (const double2& v : h)
+        if (!std::isfinite(v.x) || !std::isfinite(v.y))
+            return fail(c, GDR_ERR_ARG, "matrix entries must be finite");
+    gdr_op_s* op = new gdr_op_s;
+    API_TRY(c)
+    HIPCHK(hipSetDevice(c->device));
+    op->ctx = c;
+    op->kind = 1;
+    op->n = n;
+    HIPCHK(hipMalloc(&op->bd64, (size_t)2 * n * sizeof(double2)));
+    HIPCHK(hipMalloc(&op->bd32, (size_t)2 * n * sizeof(float2)));
+    HIPCHK(hipMemcpyAsync(op->bd64, h.data(), (size_t)2 * n * sizeof(double2),
+                          hipMemcpyHostToDevice, c->st));
+    plain_copy<double, float>(op->bd64, 0, op->bd32, 0, 2 * n, 1, c->st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->st));
+    *out = op;
+    return GDR_OK;
+    } catch (const GdrError& e) {
+        gdr_op_destroy(op);
+        return fail(c, e.code, e.what());
+    } catch (const std::exception& e) {
+        gdr_op_destroy(op);
+        return fail(c, GDR_ERR_HIP, e.what());
+    }
 }
 
 int64_t gdr_op_size(gdr_op op) { return op ? op->n : 0; }
@@ -256,19 +294,19 @@ int gdr_op_apply(gdr_op op, gdr_c64 sigma, const gdr_c64* x, gdr_c64* y, int nve
         double2* b = mem.get<double2>((size_t)chunk * n);
         for (int v0 = 0; v0 < nvec; v0 += chunk) {
             const int nb = std::min(chunk, nvec - v0);
-            pack_spinor<double>((const double2*)x + v0 * n, a, n, op->g, nb, c->st);
-            dslash<double>(a, n, b, n, nullptr, 0, op->u64, GDR_LINKS_F64, op->g, op->kappa, dl, nb,
+            op_pack<double>(op, (const double2*)x + v0 * n, a, n, nb, c->st);
+            op_apply<double>(op, a, n, b, n, nullptr, 0, dl, nb,
                            c->st);
-            unpack_spinor<double>(b, n, (double2*)y + v0 * n, op->g, nb, c->st);
+            op_unpack<double>(op, b, n, (double2*)y + v0 * n, nb, c->st);
         }
     } else {
         float2* a = mem.get<float2>((size_t)chunk * n);
         float2* b = mem.get<float2>((size_t)chunk * n);
         for (int v0 = 0; v0 < nvec; v0 += chunk) {
             const int nb = std::min(chunk, nvec - v0);
-            pack_spinor<float>((const double2*)x + v0 * n, a, n, op->g, nb, c->st);
-            dslash<float>(a, n, b, n, nullptr, 0, op->ulo, op->lst, op->g, op->kappa, dl, nb, c->st);
-            unpack_spinor<float>(b, n, (double2*)y + v0 * n, op->g, nb, c->st);
+            op_pack<float>(op, (const double2*)x + v0 * n, a, n, nb, c->st);
+            op_apply<float>(op, a, n, b, n, nullptr, 0, dl, nb, c->st);
+            op_unpack<float>(op, b, n, (double2*)y + v0 * n, nb, c->st);
         }
     }
     HIPCHK(hipGetLastError());
@@ -281,6 +319,7 @@ int gdr_op_tables(gdr_op op, int32_t* eo_of_lex, int32_t* nbr, int8_t* sign) {
     if (!op) return GDR_ERR_ARG;
     gdr_ctx_s* c = op->ctx;
     if (!eo_of_lex || !nbr || !sign) return fail(c, GDR_ERR_ARG, "null table buffer");
+    if (op->kind != 0) return fail(c, GDR_ERR_ARG, "not a lattice operator");
     API_TRY(c)
     HIPCHK(hipSetDevice(c->device));
     DMem mem;
@@ -348,7 +387,7 @@ int gdr_solve_dr_sh(gdr_op op, int ns, const gdr_c64* sigma, const gdr_c64* b, g
     DMem mem;
     double2* beo = mem.get<double2>(n);
     double2* Xeo = mem.get<double2>((size_t)ns * n);
-    pack_spinor<double>((const double2*)b, beo, n, op->g, 1, c->st);
+    op_pack<double>(op, (const double2*)b, beo, n, 1, c->st);
     Stats S(st, (unsigned)p->profile, c->st);
     gdr_defl_s* d = nullptr;
     bool conv = false;
@@ -362,7 +401,7 @@ int gdr_solve_dr_sh(gdr_op op, int ns, const gdr_c64* sigma, const gdr_c64* b, g
     }
     S.flush();
     finish_stats(op, st, ns, (const double2*)sigma, 1, beo, Xeo, t, 0);
-    unpack_spinor<double>(Xeo, n, (double2*)x, op->g, ns, c->st);
+    op_unpack<double>(op, Xeo, n, (double2*)x, ns, c->st);
     HIPCHK(hipStreamSynchronize(c->st));
     if (st) st->t_total = t.sec();
     if (defl_out) *defl_out = d;
@@ -386,7 +425,7 @@ int gdr_solve_proj_sh(gdr_op op, gdr_defl defl, int ns, const gdr_c64* sigma, in
     DMem mem;
     double2* Beo = mem.get<double2>((size_t)nrhs * n);
     double2* Xeo = mem.get<double2>((size_t)nrhs * ns * n);
-    pack_spinor<double>((const double2*)B, Beo, n, op->g, nrhs, c->st);
+    op_pack<double>(op, (const double2*)B, Beo, n, nrhs, c->st);
     Stats S(st, (unsigned)p->profile, c->st);
     int rc = solve_proj_batch(op, defl, ns, (const double2*)sigma, nrhs, Beo, Xeo, 0, *p, S);
     if (p->precision == GDR_PREC_MIXED) {
@@ -396,7 +435,7 @@ int gdr_solve_proj_sh(gdr_op op, gdr_defl defl, int ns, const gdr_c64* sigma, in
     }
     S.flush();
     finish_stats(op, st, ns, (const double2*)sigma, nrhs, Beo, Xeo, t, 0);
-    unpack_spinor<double>(Xeo, n, (double2*)X, op->g, nrhs * ns, c->st);
+    op_unpack<double>(op, Xeo, n, (double2*)X, nrhs * ns, c->st);
     HIPCHK(hipStreamSynchronize(c->st));
     if (st) st->t_total = t.sec();
     return rc;
@@ -417,7 +456,7 @@ int gdr_solve(gdr_op op, int ns, const gdr_c64* sigma, int nrhs, const gdr_c64* 
     DMem mem;
     double2* Beo = mem.get<double2>((size_t)nrhs * n);
     double2* Xeo = mem.get<double2>((size_t)nrhs * ns * n);
-    pack_spinor<double>((const double2*)B, Beo, n, op->g, nrhs, c->st);
+    op_pack<double>(op, (const double2*)B, Beo, n, nrhs, c->st);
     Stats S(st, (unsigned)p->profile, c->st);
     gdr_defl_s* d = nullptr;
     bool conv = false;
@@ -442,7 +481,7 @@ int gdr_solve(gdr_op op, int ns, const gdr_c64* sigma, int nrhs, const gdr_c64* 
     }
     S.flush();
     finish_stats(op, st, ns, (const double2*)sigma, nrhs, Beo, Xeo, t, 0);
-    unpack_spinor<double>(Xeo, n, (double2*)X, op->g, nrhs * ns, c->st);
+    op_unpack<double>(op, Xeo, n, (double2*)X, nrhs * ns, c->st);
     HIPCHK(hipStreamSynchronize(c->st));
     if (st) st->t_total = t.sec();
     return rc;
@@ -459,9 +498,9 @@ int gdr_defl_export(gdr_defl d, gdr_c64* V, gdr_c64* Hbar) {
     HIPCHK(hipSetDevice(c->device));
     if (V) {
         if (d->prec == GDR_PREC_MIXED)
-            unpack_spinor<float>((const float2*)d->V, op->n, (double2*)V, op->g, d->k + 1, c->st);
+            op_unpack<float>(op, (const float2*)d->V, op->n, (double2*)V, d->k + 1, c->st);
         else
-            unpack_spinor<double>((const double2*)d->V, op->n, (double2*)V, op->g, d->k + 1, c->st);
+            op_unpack<double>(op, (const double2*)d->V, op->n, (double2*)V, d->k + 1, c->st);
     }
     if (Hbar && d->k > 0)
         std::memcpy(Hbar, d->Hk_host.data(), d->Hk_host.size() * sizeof(double2));
@@ -490,12 +529,12 @@ int gdr_defl_import(gdr_op op, int k, const gdr_c64* V, const gdr_c64* Hbar, int
         const size_t bytes = (size_t)(k + 1 + BASIS_PAD) * n * sizeof(float2);
         HIPCHK(hipMalloc(&d->V, bytes));
         HIPCHK(hipMemsetAsync(d->V, 0, bytes, c->st));
-        pack_spinor<float>((const double2*)V, (float2*)d->V, n, op->g, k + 1, c->st);
+        op_pack<float>(op, (const double2*)V, (float2*)d->V, n, k + 1, c->st);
     } else {
         const size_t bytes = (size_t)(k + 1 + BASIS_PAD) * n * sizeof(double2);
         HIPCHK(hipMalloc(&d->V, bytes));
         HIPCHK(hipMemsetAsync(d->V, 0, bytes, c->st));
-        pack_spinor<double>((const double2*)V, (double2*)d->V, n, op->g, k + 1, c->st);
+        op_pack<double>(op, (const double2*)V, (double2*)d->V, n, k + 1, c->st);
     }
     if (k > 0) {
         d->Hk_host.assign((const double2*)Hbar, (const double2*)Hbar + (size_t)(k + 1) * k);

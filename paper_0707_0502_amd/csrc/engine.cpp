@@ -39,12 +39,54 @@ static int lst_for(gdr_op_s* op) {
 // every spinor component once (links shared by the vectors of one launch)
 template <typename T>
 static double dslash_bytes(gdr_op_s* op, int nvec, bool add) {
+    double cs = std::is_same<T, double>::value ? 16 : 8;
+    if (op->kind == 1)   // bidiagonal: 2n matrix entries, in, out (, add) per vector
+        return (double)op->n * cs * (2 + nvec * (2 + (add ? 1 : 0)));
     const double vol = op->g.vol;
     double link = std::is_same<T, double>::value ? 16 : (op->lst == GDR_LINKS_F16 ? 4 : 8);
-    double cs = std::is_same<T, double>::value ? 16 : 8;
     return vol * (36 * link + nvec * (12 * cs * 2 + (add ? 12 * cs : 0)));
 }
-static double dslash_flops(gdr_op_s* op, int nvec) { return (double)op->g.vol * nvec * 1368.0; }
+static double dslash_flops(gdr_op_s* op, int nvec) {
+    if (op->kind == 1) return (double)op->n * nvec * 16.0;
+    return (double)op->g.vol * nvec * 1368.0;
+}
+
+template <typename T>
+void op_apply(gdr_op_s* op, const typename CT<T>::t* in, int64_t in_stride,
+              typename CT<T>::t* out, int64_t out_stride, const typename CT<T>::t* add,
+              int64_t add_stride, const DiagList& dl, int nvec, hipStream_t st, const int* act) {
+    if (op->kind == 1) {
+        const typename CT<T>::t* de;
+        if constexpr (std::is_same<T, double>::value) de = op->bd64;
+        else de = op->bd32;
+        bidiag_apply<T>(in, in_stride, out, out_stride, add, add_stride, de, op->n, dl, nvec, st,
+                        act);
+        return;
+    }
+    dslash<T>(in, in_stride, out, out_stride, add, add_stride, links_for<T>(op), lst_for<T>(op),
+              op->g, op->kappa, dl, nvec, st, act);
+}
+template <typename T>
+void op_pack(gdr_op_s* op, const double2* canon, typename CT<T>::t* dst, int64_t stride, int nvec,
+             hipStream_t st) {
+    if (op->kind == 1) plain_copy<double, T>(canon, op->n, dst, stride, op->n, nvec, st);
+    else pack_spinor<T>(canon, dst, stride, op->g, nvec, st);
+}
+template <typename T>
+void op_unpack(gdr_op_s* op, const typename CT<T>::t* src, int64_t stride, double2* canon, int nvec,
+               hipStream_t st) {
+    if (op->kind == 1) plain_copy<T, double>(src, stride, canon, op->n, op->n, nvec, st);
+    else unpack_spinor<T>(src, stride, canon, op->g, nvec, st);
+}
+template void op_apply<double>(gdr_op_s*, const double2*, int64_t, double2*, int64_t,
+                               const double2*, int64_t, const DiagList&, int, hipStream_t,
+                               const int*);
+template void op_apply<float>(gdr_op_s*, const float2*, int64_t, float2*, int64_t, const float2*,
+                              int64_t, const DiagList&, int, hipStream_t, const int*);
+template void op_pack<double>(gdr_op_s*, const double2*, double2*, int64_t, int, hipStream_t);
+template void op_pack<float>(gdr_op_s*, const double2*, float2*, int64_t, int, hipStream_t);
+template void op_unpack<double>(gdr_op_s*, const double2*, int64_t, double2*, int, hipStream_t);
+template void op_unpack<float>(gdr_op_s*, const float2*, int64_t, double2*, int, hipStream_t);
 
 // Krylov bases carry BASIS_PAD zeroed spare columns: the Gram-Schmidt
 // kernels load columns in chunks of 8 without per-column guards.
@@ -139,8 +181,8 @@ struct Arnoldi {
         for (int b0 = 0; b0 < nmem; b0 += DSLASH_MAXV) {
             const int nb = std::min(DSLASH_MAXV, nmem - b0);
             prof->begin(GDR_K_DSLASH);
-            dslash<T>(col + b0 * vms, vms, w + b0 * n, n, nullptr, 0, links_for<T>(op),
-                      lst_for<T>(op), op->g, op->kappa, dl, nb, st, act ? act + b0 : nullptr);
+            op_apply<T>(op, col + b0 * vms, vms, w + b0 * n, n, nullptr, 0, dl, nb, st,
+                        act ? act + b0 : nullptr);
             const int na = std::min(nb, nact - std::min(nact, b0));
             prof->end(GDR_K_DSLASH, dslash_bytes<T>(op, na, false), dslash_flops(op, na));
         }
@@ -307,7 +349,7 @@ static int dr_run(gdr_op_s* op, int ns, const double2* sig_h, const double2* b_e
             dl.d[0] = z(1.0 - sig_h[0].x, -sig_h[0].y);
             dl.alpha[0] = -1;
             S.prof.begin(GDR_K_DSLASH);
-            dslash<double>(X, 0, rtrue, 0, b_eo, 0, op->u64, GDR_LINKS_F64, op->g, op->kappa, dl, 1,
+            op_apply<double>(op, X, 0, rtrue, 0, b_eo, 0, dl, 1,
                            st);
             S.prof.end(GDR_K_DSLASH, dslash_bytes<double>(op, 1, true), dslash_flops(op, 1));
             if (S.st) S.st->mvp_fp64 += 1;
@@ -565,8 +607,8 @@ static void proj_run(gdr_op_s* op, gdr_defl_s* defl, int nmem, int ns,
                 }
                 const int na = std::min(nb, nact0 - std::min(nact0, b0));
                 S.prof.begin(GDR_K_DSLASH);
-                dslash<double>(W + b0 * wms, wms, W + b0 * wms + (int64_t)ns * n, wms,
-                               Bm + b0 * n, n, op->u64, GDR_LINKS_F64, op->g, op->kappa, dl, nb,
+                op_apply<double>(op, W + b0 * wms, wms, W + b0 * wms + (int64_t)ns * n, wms,
+                               Bm + b0 * n, n, dl, nb,
                                st, act + b0);
                 S.prof.end(GDR_K_DSLASH, dslash_bytes<double>(op, na, true), dslash_flops(op, na));
                 if (S.st) S.st->mvp_fp64 += na;
@@ -673,7 +715,7 @@ static std::vector<double2> vk1_dot_residuals(gdr_defl_s* d, int ns, const doubl
         dl.d[i - 1] = z(1.0 - sig_h[i].x, -sig_h[i].y);
         dl.alpha[i - 1] = -1;
     }
-    dslash<double>(xs + n, n, Rt, n, rhs, 0, op->u64, GDR_LINKS_F64, op->g, op->kappa, dl, ns - 1,
+    op_apply<double>(op, xs + n, n, Rt, n, rhs, 0, dl, ns - 1,
                    st);
     gs_dot<T, double>((const C*)d->V + (int64_t)d->k * n, n, 0, 1, Rt, n, nullptr, 0, part, nblk,
                       n, ns - 1, st);
@@ -901,8 +943,7 @@ static void residual_vectors(gdr_op_s* op, int ns, const double2* sig, const dou
             dl.d[v] = z(1.0 - sig[i0 + v].x, -sig[i0 + v].y);
             dl.alpha[v] = -1;
         }
-        dslash<double>(xs + (int64_t)i0 * n, n, R + (int64_t)i0 * n, n, b, 0, op->u64,
-                       GDR_LINKS_F64, op->g, op->kappa, dl, nb, st);
+        op_apply<double>(op, xs + (int64_t)i0 * n, n, R + (int64_t)i0 * n, n, b, 0, dl, nb, st);
     }
 }
 

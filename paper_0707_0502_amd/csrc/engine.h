@@ -39,7 +39,28 @@ struct gdr_op_s {
     double2* u64 = nullptr; // FP64 links (internal layout)
     void* ulo = nullptr;    // FP32 or FP16 links
     int lst = GDR_LINKS_F32;
+    int kind = 0;             // 0: Wilson-Dirac lattice operator, 1: bidiagonal matrix
+    double2* bd64 = nullptr;  // bidiagonal: diagonal (n) then superdiagonal (n), FP64
+    float2* bd32 = nullptr;   //   and the FP32 copy
 };
+
+namespace gdr {
+// The operator behind a handle: out_v = alpha_v (A - sigma_v) in_v [+ add_v]
+// with 1 - sigma_v in dl.d[v] (Wilson: A = I - kappa D; bidiagonal: A = M),
+// and the conversions between the caller's canonical complex128 vectors and
+// the internal layout of type T.
+template <typename T>
+void op_apply(gdr_op_s* op, const typename CT<T>::t* in, int64_t in_stride,
+              typename CT<T>::t* out, int64_t out_stride, const typename CT<T>::t* add,
+              int64_t add_stride, const DiagList& dl, int nvec, hipStream_t st,
+              const int* act = nullptr);
+template <typename T>
+void op_pack(gdr_op_s* op, const double2* canon, typename CT<T>::t* dst, int64_t stride, int nvec,
+             hipStream_t st);
+template <typename T>
+void op_unpack(gdr_op_s* op, const typename CT<T>::t* src, int64_t stride, double2* canon, int nvec,
+               hipStream_t st);
+}  // namespace gdr
 
 struct gdr_defl_s {
     gdr_op_s* op = nullptr;

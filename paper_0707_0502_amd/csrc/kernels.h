@@ -34,6 +34,19 @@ void dslash(const typename CT<TS>::t* in, int64_t in_stride, typename CT<TS>::t*
             const void* links, int link_storage, const Geom& g, double kappa, const DiagList& dl,
             int nvec, hipStream_t st, const int* act = nullptr);
 
+// ------------------------------------------------------------ bidiagonal operator (bidiag.hip)
+// out_v = alpha_v * (M in_v - sigma_v in_v) [+ add_v], sigma_v = 1 - dl.d[v];
+// de: diagonal (n entries) then superdiagonal (n - 1 used), type T
+template <typename T>
+void bidiag_apply(const typename CT<T>::t* in, int64_t in_stride, typename CT<T>::t* out,
+                  int64_t out_stride, const typename CT<T>::t* add, int64_t add_stride,
+                  const typename CT<T>::t* de, int64_t n, const DiagList& dl, int nvec,
+                  hipStream_t st, const int* act = nullptr);
+// y_v = (TO) x_v for plain vectors
+template <typename TI, typename TO>
+void plain_copy(const typename CT<TI>::t* x, int64_t x_stride, typename CT<TO>::t* y,
+                int64_t y_stride, int64_t n, int nvec, hipStream_t st);
+
 // ------------------------------------------------------------ DCGS2 (blas.hip)
 // Column-block sums of V_{0..nc-1}^H x_a (a < 1 or 2; x1 == nullptr for one
 // vector) and ||x_last||^2 into partial[((mem*nval) + a*nc + c)*nblk + blk],

@@ -31,7 +31,7 @@ K_CLASSES = ["dslash", "cgs_dot", "cgs_update_dot", "cgs_update_norm", "small", 
 
 SYMBOLS = [
     "gdr_ctx_create", "gdr_ctx_destroy", "gdr_last_error", "gdr_wilson_create",
-    "gdr_op_destroy", "gdr_op_size", "gdr_op_apply", "gdr_op_tables", "gdr_op_dslash_bench",
+    "gdr_op_destroy", "gdr_bidiag_create", "gdr_op_size", "gdr_op_apply", "gdr_op_tables", "gdr_op_dslash_bench",
     "gdr_params_default",
     "gdr_solve_dr_sh", "gdr_solve_proj_sh", "gdr_solve", "gdr_defl_k", "gdr_defl_export",
     "gdr_defl_import", "gdr_defl_destroy",
@@ -86,6 +86,7 @@ def load(path=LIB_PATH):
                                       vp, ip, ip, ctypes.POINTER(vp)]
     lib.gdr_op_destroy.argtypes = [vp]
     lib.gdr_op_destroy.restype = None
+    lib.gdr_bidiag_create.argtypes = [vp, i64, vp, vp, ctypes.POINTER(vp)]
     lib.gdr_op_size.argtypes = [vp]
     lib.gdr_op_size.restype = i64
     lib.gdr_op_apply.argtypes = [vp, gdr_c64, vp, vp, ip, ip]
@@ -153,9 +154,10 @@ class Ctx:
 
 
 class Op:
-    def __init__(self, ctx, handle, dims):
-        self.ctx, self.h, self.dims = ctx, handle, tuple(dims)
-        self.n = 12 * int(np.prod(dims))
+    def __init__(self, ctx, handle, dims=None, n=None):
+        self.ctx, self.h = ctx, handle
+        self.dims = tuple(dims) if dims is not None else None
+        self.n = 12 * int(np.prod(dims)) if dims is not None else int(n)
 
 
 class Defl:
@@ -232,6 +234,16 @@ def gdr_wilson_create(ctx, dims, bc, kappa, links, link_storage=GDR_LINKS_F32):
     ctx.check(lib().gdr_wilson_create(ctx.h, d, b, float(kappa), _ptr(links), on_dev,
                                       link_storage, ctypes.byref(h)))
     return Op(ctx, h, dims)
+
+
+def gdr_bidiag_create(ctx, diag, super_):
+    """Bidiagonal operator from host sequences of n and n-1 complex entries."""
+    d = np.ascontiguousarray(diag, dtype=np.complex128)
+    e = np.ascontiguousarray(super_, dtype=np.complex128)
+    h = ctypes.c_void_p()
+    ctx.check(lib().gdr_bidiag_create(ctx.h, len(d), _ptr(d), _ptr(e) if len(e) else None,
+                                      ctypes.byref(h)))
+    return Op(ctx, h, n=len(d))
 
 
 def gdr_op_destroy(op):
