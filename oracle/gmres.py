@@ -241,6 +241,32 @@ def minres_projection_sh(Vk1, Hk, sigmas, x, r1, beta, gam):
     return r1
 
 
+def leading_projection_sh(Vk1, Hk, sigmas, x, r1, beta, kp):
+    """Projection over the most accurate approximate eigenvectors only
+    (Sec. 4, Theorem 1 and Example 4 / Table 4.1). The leading kp columns of
+    V_k span the kp approximate eigenvectors of smallest harmonic Ritz value
+    (the restart keeps them in that order), and A V_kp = V_{k+1} Hbar_k[:, :kp].
+    Base shift: minimum residual over span(V_kp). Other shifts: the first kp
+    rows of (H - sigma_i I) d_i = beta_i (H - sigma_1 I) d_1, i.e. step 4 of
+    GMRES-Proj-Sh on the kp-column recurrence; beta_i is unchanged and the
+    residuals stay parallel only for exact eigenvectors (Theorem 1). Updates x
+    in place; returns the new r_1."""
+    k = Hk.shape[1]
+    Vkp = Vk1[:, :kp]
+    c = Vk1.conj().T @ r1
+    Hs = (Hk - sigmas[0] * ibar(k + 1, k))[:, :kp]
+    d1 = np.linalg.lstsq(Hs, c, rcond=None)[0]
+    x[0] += Vkp @ d1
+    r1 = r1 - Vk1 @ (Hs @ d1)
+    Hkk = Hk[:kp, :kp]
+    Ik = np.eye(kp, dtype=np.complex128)
+    for i in range(1, len(sigmas)):
+        t = beta[i] * ((Hkk - sigmas[0] * Ik) @ d1)
+        di = np.linalg.solve(Hkk - sigmas[i] * Ik, t)
+        x[i] += Vkp @ di
+    return r1
+
+
 def gmres_sh_cycle(matvec, x, r1, beta, sigmas, m):
     """One cycle of GMRES(m)-Sh from the current base residual r_1, the
     other shifts holding residuals beta_i r_1 (Sec. 2.1). The new base
@@ -267,13 +293,15 @@ def gmres_sh_cycle(matvec, x, r1, beta, sigmas, m):
 
 
 def gmres_proj_sh(matvec, b, sigmas, defl, m, tol, max_cycles=500, x0=None,
-                  r0=None):
+                  r0=None, kp=None):
     """GMRES(m)-Proj(k)-Sh for one right-hand side (Sec. 4, steps 2-6):
     alternate the projection over V_k with one GMRES(m)-Sh cycle until the
     base residual and every |beta_i| ||r_1|| are below tol ||b|| (the
     component along v_{k+1} is ignored here and removed by the correction).
 
     x0/r0 allow a start from a common-residual initial guess (Sec. 5).
+    kp: project over the leading kp deflation vectors only, the accurate
+    eigenvector variant of Table 4.1 (no v_{k+1} tracking).
     Returns dict with x, beta, gam, r1, mvps, cycles, converged, history.
     """
     Vk1, Hk = defl
@@ -291,7 +319,10 @@ def gmres_proj_sh(matvec, b, sigmas, defl, m, tol, max_cycles=500, x0=None,
     cycles = 0
     for _ in range(max_cycles):
         cycles += 1
-        r1 = minres_projection_sh(Vk1, Hk, sigmas, x, r1, beta, gam)
+        if kp is None:
+            r1 = minres_projection_sh(Vk1, Hk, sigmas, x, r1, beta, gam)
+        else:
+            r1 = leading_projection_sh(Vk1, Hk, sigmas, x, r1, beta, kp)
         r1, beta, used = gmres_sh_cycle(matvec, x, r1, beta, sigmas, m)
         mvps += used
         rn = norm(r1)
