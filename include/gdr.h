@@ -149,6 +149,11 @@ typedef struct {
     int profile;       /* bitmask of GDR_K_* kernel classes to time with HIP events on the
                           context stream (0: none); results in gdr_stats.k_* */
     int m_clean;       /* cycle length of the mixed-precision cleanup solves (0: automatic) */
+    int proj_k;        /* 0: later RHS project over all k deflation vectors with the v_{k+1}
+                          component tracked, the extra RHS and the correction (Sec. 4);
+                          1..k: project over the leading proj_k (most accurate) approximate
+                          eigenvectors only, no extra RHS and no correction (Sec. 4,
+                          Theorem 1 and Table 4.1) */
 } gdr_params;
 
 /* kernel classes of the profiler (gdr_params.profile bit i = class i) */
@@ -162,7 +167,8 @@ typedef struct {
 #define GDR_K_OTHER 7       /* reductions, scaling, conversions */
 
 /* Fill defaults: m_dr 40, k 15, m_proj 40, tol 1e-8, tol_extra sqrt(tol),
- * max_cycles 1000, FP64, batch 1, related 0, max_refine 8, profile 0, m_clean 0. */
+ * max_cycles 1000, FP64, batch 1, related 0, max_refine 8, profile 0, m_clean 0,
+ * proj_k 0. */
 void gdr_params_default(gdr_params* p);
 
 typedef struct {

@@ -18,7 +18,9 @@ transposes):
   method): harmonic Ritz pairs of the base-shifted matrix, i.e. the
   eigenpairs of G = H_m + |h_{m+1,m}|^2 H_m^{-H} e_m e_m^H with
   H_m the leading m x m block of H_bar - sigma_1 I_bar; keep the k of
-  smallest |theta| (ties: smaller Re, then smaller Im); P_k = orthonormal
+  smallest |theta| (ties: smaller Re, then smaller Im; moduli and real parts
+  within 1e-10 relative are ties, so a conjugate pair of real data is split
+  by the sign of Im, not by rounding); P_k = orthonormal
   basis of their eigenvectors padded with a zero row; p_{k+1} = s
   orthogonalised against P_k; H_bar_k <- P_{k+1}^H H_bar P_k (for A);
   V_{k+1} <- V_{m+1} P_{k+1}; c <- P_{k+1}^H s; v_{k+1} is
@@ -116,10 +118,30 @@ def harmonic_ritz(H, sigma1):
     return theta, g
 
 
-def select_smallest(theta, k):
-    """Indices of the k smallest |theta|; ties by smaller Re, then Im."""
-    order = np.lexsort((theta.imag, theta.real, np.abs(theta)))
-    return order[:k]
+def select_smallest(theta, k, rtol=1e-10):
+    """Indices of the k smallest |theta|, in that order; ties by smaller Re,
+    then smaller Im. Moduli and real parts equal to a relative rtol count as
+    ties: for real data the harmonic Ritz values come in conjugate pairs whose
+    computed moduli differ only by rounding, and the pair is then ordered by
+    the sign of Im (negative first) instead of by rounding noise."""
+    def less(a, b):
+        ma, mb = abs(a), abs(b)
+        tol = rtol * max(ma, mb)
+        if abs(ma - mb) > tol:
+            return ma < mb
+        if abs(a.real - b.real) > tol:
+            return a.real < b.real
+        return a.imag < b.imag
+    rest = list(range(len(theta)))
+    out = []
+    for _ in range(min(k, len(rest))):
+        best = rest[0]
+        for j in rest[1:]:
+            if less(theta[j], theta[best]):
+                best = j
+        out.append(best)
+        rest.remove(best)
+    return np.array(out, dtype=int)
 
 
 def dr_restart(V, H, s, sigma1, k):

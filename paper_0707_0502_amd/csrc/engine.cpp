@@ -463,7 +463,9 @@ static void proj_run(gdr_op_s* op, gdr_defl_s* defl, int nmem, int ns,
                      const std::vector<double2>& sig_h, const double2* Bm, double2* W,
                      const std::vector<double>& tol, const std::vector<double>& bnorm, int m,
                      int max_cycles, Stats& S, const std::vector<int>& phase, ProjResult& R,
-                     bool start = false) {
+                     bool start = false, int kp = 0) {
+    // kp > 0: project over the leading kp deflation vectors only (the
+    // accurate-eigenvector variant, Table 4.1); otherwise over all k
     // start: W already holds an initial guess x_i and the common residual r
     // (related right-hand sides, Sec. 5); otherwise x_i = 0, r = b
     using C = typename CT<T>::t;
@@ -535,6 +537,7 @@ static void proj_run(gdr_op_s* op, gdr_defl_s* defl, int nmem, int ns,
             ProjArgs pa{};
             pa.Hk = defl->Hk;
             pa.k = k;
+            pa.kp = (kp > 0 && kp < k) ? kp : k;
             pa.C = Cb;
             pa.c_ms = 80;
             pa.sigma = sig;
@@ -788,7 +791,8 @@ static int proj_batch(gdr_op_s* op, gdr_defl_s* d, int ns, const double2* sig_h,
     const int64_t n = op->n;
     const int m = p.m_proj;
     const double tol_extra = p.tol_extra > 0 ? p.tol_extra : std::sqrt(p.tol);
-    bool need_extra = ns > 1 && d->k > 0;
+    const int kp = std::min(p.proj_k, d->k);   // > 0: accurate-eigenvector variant
+    bool need_extra = ns > 1 && d->k > 0 && kp == 0;
     if (need_extra && d->S && (int)d->extra_sig.size() == ns) {
         need_extra = false;
         for (int i = 0; i < ns; ++i)
@@ -851,10 +855,10 @@ static int proj_batch(gdr_op_s* op, gdr_defl_s* d, int ns, const double2* sig_h,
                                    nsolved, ids, Bm, W, st);
         if (d->prec == GDR_PREC_MIXED)
             proj_run<float>(op, d, nmem, ns, sgm, Bm, W, tol, bnorm, m, p.max_cycles, S, phase, R,
-                            related);
+                            related, kp);
         else
             proj_run<double>(op, d, nmem, ns, sgm, Bm, W, tol, bnorm, m, p.max_cycles, S, phase, R,
-                             related);
+                             related, kp);
         HIPCHK(hipStreamSynchronize(st));
         auto t1 = clock::now();
         if (S.st) S.st->t_phase[2] += std::chrono::duration<double>(t1 - t0).count();
@@ -906,7 +910,7 @@ static int proj_batch(gdr_op_s* op, gdr_defl_s* d, int ns, const double2* sig_h,
         for (int b = 0; b < nmem; ++b) {
             if (ids[b] < 0) continue;
             double2* xs = W + b * wms;
-            if (ns > 1 && d->k > 0) {
+            if (ns > 1 && d->k > 0 && kp == 0) {
                 auto gh = d->prec == GDR_PREC_MIXED
                               ? vk1_dot_residuals<float>(d, ns, sig_h, xs, Bm + b * n, Rt, part, nblk, g)
                               : vk1_dot_residuals<double>(d, ns, sig_h, xs, Bm + b * n, Rt, part, nblk, g);

@@ -44,6 +44,8 @@ struct CycleArgs {
 struct ProjArgs {
     const double2* Hk;      // (k+1) x k column-major (ld k+1)
     int k;
+    int kp;                 // leading deflation vectors used, 1..k (k: full projection
+                            // with the v_{k+1} component tracked in gam)
     const double2* C;       // per member k+1 coefficients V_{k+1}^H r (+ b*c_ms)
     int64_t c_ms;
     const double2* sigma;   // shifts of member b: sigma + b*sig_ms

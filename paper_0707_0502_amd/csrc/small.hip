@@ -40,10 +40,16 @@ __device__ __forceinline__ double2 csqrt_(double2 z) {
 }
 
 // lexicographic key (|theta|, Re, Im)
+// Selection order of harmonic Ritz values: smaller |theta|, then smaller
+// Re theta, then smaller Im theta, where moduli and real parts equal to a
+// relative 1e-10 count as ties (for real data the values come in conjugate
+// pairs whose computed moduli differ only by rounding; the tie then goes to
+// the member with negative imaginary part).
 __device__ __forceinline__ bool key_less(double2 a, double2 b) {
-    double aa = cabs(a), ab = cabs(b);
-    if (aa != ab) return aa < ab;
-    if (a.x != b.x) return a.x < b.x;
+    const double aa = cabs(a), ab = cabs(b);
+    const double tol = 1e-10 * fmax(aa, ab);
+    if (fabs(aa - ab) > tol) return aa < ab;
+    if (fabs(a.x - b.x) > tol) return a.x < b.x;
     return a.y < b.y;
 }
 
@@ -601,6 +607,7 @@ __global__ __launch_bounds__(64) void k_proj_small(ProjArgs a) {
     const int b = blockIdx.x;
     if (a.act && !a.act[b]) return;
     const int k = a.k;
+    const int kp = a.kp;   // leading columns used (k: the full projection)
     const int ns = a.ns;
     const int ldk = k + 1;
     const double2* C = a.C + b * a.c_ms;
@@ -611,22 +618,22 @@ __global__ __launch_bounds__(64) void k_proj_small(ProjArgs a) {
     __shared__ double2 A[(MAXM + 2) * LD];
     __shared__ double2 hv[LD + 1], d1[LD + 1], y[LD + 1], di[LD + 1];
     const double2 s1 = sig[0];
-    // [Hk - sigma_1 I_bar | C]
-    for (int c = 0; c <= k; ++c)
+    // [Hk(:, 0..kp-1) - sigma_1 I_bar | C]
+    for (int c = 0; c <= kp; ++c)
         for (int r = lane; r <= k; r += 64) {
-            double2 v = c < k ? a.Hk[c * ldk + r] : C[r];
-            if (c < k && r == c) v = csub(v, s1);
+            double2 v = c < kp ? a.Hk[c * ldk + r] : C[r];
+            if (c < kp && r == c) v = csub(v, s1);
             AT(A, r, c) = v;
         }
     __syncthreads();
-    hh_qr(A, k + 1, k, k + 1, hv);
-    for (int r = lane; r < k; r += 64) d1[r] = AT(A, r, k);
+    hh_qr(A, k + 1, kp, kp + 1, hv);
+    for (int r = lane; r < kp; r += 64) d1[r] = AT(A, r, kp);
     __syncthreads();
-    bool bad = !back_sub(A, k, d1);
-    // y = (Hk - sigma_1 I_bar) d1
+    bool bad = !back_sub(A, kp, d1);
+    // y = (Hk(:, 0..kp-1) - sigma_1 I_bar) d1
     for (int r = lane; r <= k; r += 64) {
         double2 acc = mk(0, 0);
-        for (int c = 0; c < k; ++c) {
+        for (int c = 0; c < kp; ++c) {
             double2 h = a.Hk[c * ldk + r];
             if (r == c) h = csub(h, s1);
             acc = cadd(acc, cmul(h, d1[c]));
@@ -635,16 +642,17 @@ __global__ __launch_bounds__(64) void k_proj_small(ProjArgs a) {
     }
     __syncthreads();
     for (int r = lane; r <= k; r += 64) {
-        coef[r] = r < k ? d1[r] : mk(0, 0);
+        coef[r] = r < kp ? d1[r] : mk(0, 0);
         coef[ns * (k + 1) + r] = mk(-y[r].x, -y[r].y);
     }
     for (int i = 1; i < ns; ++i) {
         const double2 si = sig[i], bi = beta[i];
         __syncthreads();
-        for (int c = 0; c <= k; ++c)
-            for (int r = lane; r < k; r += 64) {
+        // first kp rows: (H - sigma_i I) d_i = beta_i (H - sigma_1 I) d_1
+        for (int c = 0; c <= kp; ++c)
+            for (int r = lane; r < kp; r += 64) {
                 double2 v;
-                if (c < k) {
+                if (c < kp) {
                     v = a.Hk[c * ldk + r];
                     if (r == c) v = csub(v, si);
                 } else {
@@ -653,17 +661,19 @@ __global__ __launch_bounds__(64) void k_proj_small(ProjArgs a) {
                 AT(A, r, c) = v;
             }
         __syncthreads();
-        hh_qr(A, k, k, k + 1, hv);
-        for (int r = lane; r < k; r += 64) di[r] = AT(A, r, k);
+        hh_qr(A, kp, kp, kp + 1, hv);
+        for (int r = lane; r < kp; r += 64) di[r] = AT(A, r, kp);
         __syncthreads();
-        if (!back_sub(A, k, di)) bad = true;
-        // gamma_i += h_{k+1,:} (beta_i d1 - d_i)
-        double2 g = mk(0, 0);
-        for (int c = lane; c < k; c += 64)
-            g = cadd(g, cmul(a.Hk[c * ldk + k], csub(cmul(bi, d1[c]), di[c])));
-        g = mk(wred(g.x), wred(g.y));
-        for (int r = lane; r <= k; r += 64) coef[i * (k + 1) + r] = r < k ? di[r] : mk(0, 0);
-        if (lane == 0) gam[i] = cadd(gam[i], g);
+        if (!back_sub(A, kp, di)) bad = true;
+        for (int r = lane; r <= k; r += 64) coef[i * (k + 1) + r] = r < kp ? di[r] : mk(0, 0);
+        if (kp == k) {
+            // gamma_i += h_{k+1,:} (beta_i d1 - d_i): the v_{k+1} component (eq. (4.1))
+            double2 g = mk(0, 0);
+            for (int c = lane; c < k; c += 64)
+                g = cadd(g, cmul(a.Hk[c * ldk + k], csub(cmul(bi, d1[c]), di[c])));
+            g = mk(wred(g.x), wred(g.y));
+            if (lane == 0) gam[i] = cadd(gam[i], g);
+        }
     }
     if (lane == 0 && bad) a.flags[b] |= 1;
 }

@@ -128,3 +128,40 @@ def test_two_rhs_proj_sh_with_correction(bop):
             r = np.linalg.norm(B[j] - (mv(Xh[j, i]) - sig[i] * Xh[j, i])) / np.linalg.norm(B[j])
             assert r <= 1e-8
     assert rc == gdr.GDR_OK
+
+
+def test_table41_accurate_eigenvector_projection(bop):
+    """Example 4 / Table 4.1 on the GPU: RHS 1 by GMRES-DR(25,10)-Sh to 1e-10,
+    RHS 2 by GMRES(15)-Proj-Sh over the leading k' approximate eigenvectors
+    only (proj_k = k'): products and solutions equal the oracle's, and the
+    products grow as k' shrinks (the printed trend)."""
+    from paper_0707_0502_amd import gdr
+    op, d, e, mv = bop
+    sig = [0, -0.4, -2]
+    b1 = np.random.default_rng(0).standard_normal(1000) + 0j
+    b2 = np.random.default_rng(100).standard_normal(1000) + 0j
+    ref1 = gmres.gmres_dr_sh(mv, b1, sig, 25, 10, 1e-10)
+    x1 = empty(3 * 1000)
+    p = gdr.gdr_params_default(m_dr=25, k=10, m_proj=15, tol=1e-10, precision=gdr.GDR_PREC_F64)
+    rc, defl = gdr.gdr_solve_dr_sh(op, sig, dev(b1), x1, p, gdr.Stats(1, 3))
+    assert rc == gdr.GDR_OK and defl is not None
+    counts = []
+    for kp in (10, 6, 2):
+        ref = gmres.gmres_proj_sh(mv, b2, sig, ref1["defl"], 15, 1e-10, 200, kp=kp)
+        X = empty(3 * 1000)
+        st = gdr.Stats(1, 3)
+        p.proj_k = kp
+        rc = gdr.gdr_solve_proj_sh(op, defl, sig, dev(b2), X, p, st)
+        say("k'", kp, "rc", rc, "gpu mvps", st.s.mvp_proj, "oracle", ref["mvps"],
+            "extra", st.s.mvp_extra)
+        assert st.s.mvp_proj == ref["mvps"]
+        assert st.s.mvp_extra == 0
+        Xh = host(X).reshape(3, 1000)
+        errs = [rel(Xh[i], ref["x"][i]) for i in range(3)]
+        say("  rel err per shift", errs, "gpu resid", st.resid[0],
+            "oracle resid", [np.linalg.norm(gmres.true_residual(mv, b2, ref["x"][i], sig[i]))
+                             / np.linalg.norm(b2) for i in range(3)])
+        assert max(errs) <= 1e-10
+        counts.append(st.s.mvp_proj)
+    assert counts[0] <= counts[1] <= counts[2]
+    gdr.gdr_defl_destroy(defl)

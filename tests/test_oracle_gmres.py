@@ -460,3 +460,17 @@ def test_leading_projection_full_k_equals_standard():
     for i in range(1, 3):
         ri = beta[i] * r0 - (M @ x[i] - sig[i] * x[i])
         assert norm(ri - beta[i] * r1) <= 1e-10 * norm(r0)
+
+
+def test_selection_order_and_conjugate_ties():
+    """Harmonic Ritz selection: smallest |theta| first, ties by Re then Im;
+    a conjugate pair whose computed moduli differ by rounding is a tie and
+    its member with negative imaginary part comes first."""
+    rng = np.random.default_rng(4)
+    th = rng.standard_normal(40) + 1j * rng.standard_normal(40)
+    sel = gmres.select_smallest(th, 12)
+    assert list(sel) == list(np.lexsort((th.imag, th.real, np.abs(th)))[:12])
+    a = 3.0 + 0.25j
+    pair = np.array([5.0, a * (1 + 3e-16), np.conj(a), 0.5, 7.0 + 1j])
+    sel = gmres.select_smallest(pair, 3)
+    assert list(sel) == [3, 2, 1]
