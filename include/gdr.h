@@ -158,9 +158,9 @@ typedef struct {
 
 /* kernel classes of the profiler (gdr_params.profile bit i = class i) */
 #define GDR_K_DSLASH 0      /* Wilson operator launches (solver and residuals) */
-#define GDR_K_CGS_DOT 1     /* Gram-Schmidt pass 1: h = V^H w */
-#define GDR_K_CGS_UPDOT 2   /* pass 2: w -= V h, h2 = V^H w */
-#define GDR_K_CGS_UPNORM 3  /* pass 3: w -= V h2, ||w|| */
+#define GDR_K_GS_PROJECT 1  /* Gram-Schmidt projection sweep V^H [r_j, A r_j] */
+#define GDR_K_GS_UPDATE 2   /* Gram-Schmidt update sweep (finishes q_j, forms r_{j+1}) */
+#define GDR_K_GS_CLOSE 3    /* closing second pass of the last basis column */
 #define GDR_K_SMALL 4       /* device small dense problems */
 #define GDR_K_COMBINE 5     /* x_i += V d_i, r = V s */
 #define GDR_K_RECOMBINE 6   /* V_{k+1} = V_{m+1} P */

@@ -187,16 +187,16 @@ struct Arnoldi {
             prof->end(GDR_K_DSLASH, dslash_bytes<T>(op, na, false), dslash_flops(op, na));
         }
         const double nc = j + 1;
-        prof->begin(GDR_K_CGS_DOT);
+        prof->begin(GDR_K_GS_PROJECT);
         gs_dot<T, T>(V, n, vms, j + 1, col, vms, w, n, partial, nblk, n, nmem, st, act);
-        prof->end(GDR_K_CGS_DOT, dn * (nc + 1) * cs, dn * 16 * (nc + 1));
+        prof->end(GDR_K_GS_PROJECT, dn * (nc + 1) * cs, dn * 16 * (nc + 1));
         reduce_cols(partial, nblk, 2 * (j + 1) + 1, G, GMS, nullptr, 0, nmem, st, act);
         dcgs_coef(G, GMS, j, 2, j == j0, H, m + 1, hms, coef, GS_COEF_MS, ref, brk, 1e-14, nmem,
                   st, act);
-        prof->begin(GDR_K_CGS_UPDOT);
+        prof->begin(GDR_K_GS_UPDATE);
         gs_update<T>(V, n, vms, j, col, vms, w, n, col, vms, col + n, vms, coef, GS_COEF_MS, n,
                      nmem, st, act);
-        prof->end(GDR_K_CGS_UPDOT, dn * (j + 4) * cs, dn * 16 * j);
+        prof->end(GDR_K_GS_UPDATE, dn * (j + 4) * cs, dn * 16 * j);
     }
 
     // Finish the last candidate (column m): second pass against columns 0..m-1.
@@ -204,14 +204,14 @@ struct Arnoldi {
         const double cs = sizeof(C);
         const double dn = (double)n * nact;
         C* col = V + (int64_t)m * n;
-        prof->begin(GDR_K_CGS_UPNORM);
+        prof->begin(GDR_K_GS_CLOSE);
         gs_dot<T, T>(V, n, vms, m + 1, col, vms, (const C*)nullptr, 0, partial, nblk, n, nmem, st,
                      act);
         reduce_cols(partial, nblk, m + 2, G, GMS, nullptr, 0, nmem, st, act);
         dcgs_coef(G, GMS, m, 1, 0, H, m + 1, hms, coef, GS_COEF_MS, ref, brk, 1e-14, nmem, st, act);
         gs_update<T>(V, n, vms, m, col, vms, (const C*)nullptr, 0, col, vms, (C*)nullptr, 0, coef,
                      GS_COEF_MS, n, nmem, st, act);
-        prof->end(GDR_K_CGS_UPNORM, dn * (2.0 * (m + 1) + 1) * cs, dn * 16.0 * m);
+        prof->end(GDR_K_GS_CLOSE, dn * (2.0 * (m + 1) + 1) * cs, dn * 16.0 * m);
     }
 };
 

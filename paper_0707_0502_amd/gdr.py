@@ -26,7 +26,7 @@ GDR_PREC_F32 = 1
 GDR_LINKS_F64 = 0
 GDR_LINKS_F32 = 1
 GDR_LINKS_F16 = 2
-K_CLASSES = ["dslash", "cgs_dot", "cgs_update_dot", "cgs_update_norm", "small", "combine",
+K_CLASSES = ["dslash", "gs_project", "gs_update", "gs_close", "small", "combine",
              "recombine", "other"]
 
 SYMBOLS = [
