@@ -98,6 +98,32 @@ def dslash_standalone(gdr, ops, vol, reps=100, nsets=3):
     return rows
 
 
+def counter_traffic(kernel_class, workload):
+    """HBM bytes per launch of a kernel class from the committed rocprofv3
+    counter summary (profiles/*_traffic.md), if it covers this class and
+    workload and the kernel source is unchanged since the counters were taken;
+    otherwise None."""
+    import glob
+    import hashlib
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*_traffic.md")):
+        fields = {}
+        for line in open(path):
+            if ":" in line and not line.startswith(("|", "#", "`")):
+                key, _, val = line.partition(":")
+                fields[key.strip()] = val.strip()
+        if fields.get("kernel_class") != kernel_class or fields.get("workload") != workload:
+            continue
+        src, _, digest = fields.get("source", "").partition(" sha256 ")
+        try:
+            data = open(os.path.join(ROOT, src), "rb").read()
+        except OSError:
+            return None
+        if hashlib.sha256(data).hexdigest() != digest.strip():
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    return None
+
+
 def arnoldi_columns(st, cfg, nrhs):
     """Arnoldi steps of one solve as a list of basis widths j+1 (for the CPU
     extrapolation), from the library's counters."""
@@ -122,6 +148,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-dslash", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="end with a 256 MiB device copy (calibrates hardware byte counters)")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -242,7 +270,9 @@ def main():
                                 "accumulation and refinement",
                    "nrhs": nrhs, "shifts": ns, "global_batch": nrhs, "parallelism": "1 GPU"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": counter_traffic(dom, a.workload),
+                     "algorithmic_bytes_per_launch": kd["bytes"] / kd["launches"] if kd["launches"] else None,
                      "kernel_share_of_timed_kernel_ms": kd["ms"] / total_ms if total_ms else None},
         "dslash": {"in_solver_gbs": dslash_gbs,
                    "in_solver_frac": (dslash_gbs / HBM_PEAK_GBS) if dslash_gbs else None,
@@ -255,6 +285,12 @@ def main():
         "kernels": kern,
     }
     print(json.dumps(out), flush=True)
+    if a.copy_probe:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("bench: copy probe 268435456 bytes read, 268435456 written")
 
 
 if __name__ == "__main__":
