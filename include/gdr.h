@@ -154,6 +154,8 @@ typedef struct {
                           1..k: project over the leading proj_k (most accurate) approximate
                           eigenvectors only, no extra RHS and no correction (Sec. 4,
                           Theorem 1 and Table 4.1) */
+    int use_graph;     /* 1: each Arnoldi cycle is captured once into a HIP graph and replayed
+                          (fewer launches for small lattices; ignored while profiling) */
 } gdr_params;
 
 /* kernel classes of the profiler (gdr_params.profile bit i = class i) */
@@ -168,7 +170,7 @@ typedef struct {
 
 /* Fill defaults: m_dr 40, k 15, m_proj 40, tol 1e-8, tol_extra sqrt(tol),
  * max_cycles 1000, FP64, batch 1, related 0, max_refine 8, profile 0, m_clean 0,
- * proj_k 0. */
+ * proj_k 0, use_graph 0. */
 void gdr_params_default(gdr_params* p);
 
 typedef struct {

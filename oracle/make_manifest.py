@@ -34,8 +34,9 @@ def compute(name):
         # converge in hours on a few cores; a restarted Arnoldi estimate of the
         # rightmost eigenvalue (Ritz residual recorded) is used instead --
         # kappa = 0.98 kappa_c needs kappa_c only to far better than 2 %
-        ev, res = kappa.rightmost_restarted_arnoldi(links, m=60, restarts=8)
-        method = "restarted Arnoldi m=60, 8 restarts, Ritz residual %.2e" % res
+        m, restarts = (60, 8) if n <= 10_000_000 else (40, 6)
+        ev, res = kappa.rightmost_restarted_arnoldi(links, m=m, restarts=restarts)
+        method = "restarted Arnoldi m=%d, %d restarts, Ritz residual %.2e" % (m, restarts, res)
     kc = kappa.kappa_c_from_eigs(ev)
     kb = kappa.bisect_kappa_c(ev)
     if abs(kb - kc) > 1e-9 * kc:

@@ -199,6 +199,51 @@ struct Arnoldi {
         prof->end(GDR_K_GS_UPDATE, dn * (j + 4) * cs, dn * 16 * j);
     }
 
+    // One Arnoldi cycle: steps j0..m-1 and the closing pass, breakdown flags
+    // reset first. With `graph`, the cycle is captured once per (basis, H,
+    // j0) into a HIP graph and replayed (every argument of these launches is
+    // fixed; the per-member active flags are read from device memory).
+    struct Cached {
+        const void* v;
+        const void* h;
+        int j0;
+        hipGraph_t g;
+        hipGraphExec_t e;
+    };
+    std::vector<Cached> graphs;
+    bool use_graph = false;
+
+    void cycle(int j0, const int* act, int nact) {
+        // the legacy null stream cannot be captured: eager launches there
+        if (!use_graph || prof->mask || st == nullptr) {
+            fill_int(brk, -1, nmem, st);
+            for (int j = j0; j < m; ++j) step(j, j0, act, nact);
+            close(act, nact);
+            return;
+        }
+        for (auto& c : graphs)
+            if (c.v == V && c.h == H && c.j0 == j0) {
+                HIPCHK(hipGraphLaunch(c.e, st));
+                return;
+            }
+        Cached c{V, H, j0, nullptr, nullptr};
+        HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        fill_int(brk, -1, nmem, st);
+        for (int j = j0; j < m; ++j) step(j, j0, act, nact);
+        close(act, nact);
+        HIPCHK(hipStreamEndCapture(st, &c.g));
+        HIPCHK(hipGraphInstantiate(&c.e, c.g, nullptr, nullptr, 0));
+        graphs.push_back(c);
+        HIPCHK(hipGraphLaunch(c.e, st));
+    }
+
+    ~Arnoldi() {
+        for (auto& c : graphs) {
+            if (c.e) (void)hipGraphExecDestroy(c.e);
+            if (c.g) (void)hipGraphDestroy(c.g);
+        }
+    }
+
     // Finish the last candidate (column m): second pass against columns 0..m-1.
     void close(const int* act, int nact) {
         const double cs = sizeof(C);
@@ -249,6 +294,7 @@ static int dr_run(gdr_op_s* op, int ns, const double2* sig_h, const double2* b_e
     C* Vb = alloc_basis<T>(mem, m + 1, n, st);
     Arnoldi<T> A;
     A.init(mem, op, m, 1, Va, 0);
+    A.use_graph = p.use_graph != 0;
     A.prof = &S.prof;
     double2* Hn = mem.get<double2>((size_t)(m + 1) * m);
     double2* c0 = mem.get<double2>(m + 1);
@@ -303,9 +349,7 @@ static int dr_run(gdr_op_s* op, int ns, const double2* sig_h, const double2* b_e
         ++cycles;
         A.V = Vc;
         A.H = Hc;
-        fill_int(A.brk, -1, 1, st);
-        for (int j = j0; j < m; ++j) A.step(j, j0, nullptr, 1);
-        A.close(nullptr, 1);
+        A.cycle(j0, nullptr, 1);
         mvps += m - j0;
         HIPCHK(hipMemsetAsync(&outs[cur].flags, 0, sizeof(int), st));
         CycleArgs a{};
@@ -463,9 +507,10 @@ static void proj_run(gdr_op_s* op, gdr_defl_s* defl, int nmem, int ns,
                      const std::vector<double2>& sig_h, const double2* Bm, double2* W,
                      const std::vector<double>& tol, const std::vector<double>& bnorm, int m,
                      int max_cycles, Stats& S, const std::vector<int>& phase, ProjResult& R,
-                     bool start = false, int kp = 0) {
+                     bool start = false, int kp = 0, bool graph = false) {
     // kp > 0: project over the leading kp deflation vectors only (the
-    // accurate-eigenvector variant, Table 4.1); otherwise over all k
+    // accurate-eigenvector variant, Table 4.1); otherwise over all k.
+    // graph: replay the Arnoldi cycle from a captured HIP graph
     // start: W already holds an initial guess x_i and the common residual r
     // (related right-hand sides, Sec. 5); otherwise x_i = 0, r = b
     using C = typename CT<T>::t;
@@ -480,6 +525,7 @@ static void proj_run(gdr_op_s* op, gdr_defl_s* defl, int nmem, int ns,
     C* Vb = alloc_basis<T>(mem, (m + 1 + BASIS_PAD) * nmem - BASIS_PAD, n, st);
     Arnoldi<T> A;
     A.init(mem, op, m, nmem, Vb, vms);
+    A.use_graph = graph;
     A.prof = &S.prof;
     double2* sig = mem.get<double2>((size_t)nmem * ns);
     double2* Cb = mem.get<double2>((size_t)80 * nmem);
@@ -566,9 +612,7 @@ static void proj_run(gdr_op_s* op, gdr_defl_s* defl, int nmem, int ns,
         reduce_cols(A.partial, A.nblk, 1, rn2, 1, nullptr, 0, nmem, st, act);
         start_cycle(rn2, 1, cvec, m + 1, m, A.inv, nmem, st, act);
         convert_scale<T>(W + (int64_t)ns * n, wms, A.inv, 1, Vb, vms, n, nmem, st, act);
-        fill_int(A.brk, -1, nmem, st);
-        for (int j = 0; j < m; ++j) A.step(j, 0, act, nact0);
-        A.close(act, nact0);
+        A.cycle(0, act, nact0);
         HIPCHK(hipMemcpyAsync(outs + cur * nmem, init.data(), nmem * sizeof(CycleOut),
                               hipMemcpyHostToDevice, st));
         CycleArgs a{};
@@ -855,10 +899,10 @@ static int proj_batch(gdr_op_s* op, gdr_defl_s* d, int ns, const double2* sig_h,
                                    nsolved, ids, Bm, W, st);
         if (d->prec == GDR_PREC_MIXED)
             proj_run<float>(op, d, nmem, ns, sgm, Bm, W, tol, bnorm, m, p.max_cycles, S, phase, R,
-                            related, kp);
+                            related, kp, p.use_graph != 0);
         else
             proj_run<double>(op, d, nmem, ns, sgm, Bm, W, tol, bnorm, m, p.max_cycles, S, phase, R,
-                             related, kp);
+                             related, kp, p.use_graph != 0);
         HIPCHK(hipStreamSynchronize(st));
         auto t1 = clock::now();
         if (S.st) S.st->t_phase[2] += std::chrono::duration<double>(t1 - t0).count();
@@ -1029,9 +1073,11 @@ int cleanup(gdr_op_s* op, gdr_defl_s* defl, int ns, const double2* sig, int nrhs
             }
             ProjResult Rr;
             if (defl && defl->prec == GDR_PREC_F64)
-                proj_run<double>(op, defl, nmem, 1, sgm, Bm, W, tol, bnorm, mc, p.max_cycles, S, phase, Rr);
+                proj_run<double>(op, defl, nmem, 1, sgm, Bm, W, tol, bnorm, mc, p.max_cycles, S, phase, Rr,
+                                 false, 0, p.use_graph != 0);
             else
-                proj_run<float>(op, defl, nmem, 1, sgm, Bm, W, tol, bnorm, mc, p.max_cycles, S, phase, Rr);
+                proj_run<float>(op, defl, nmem, 1, sgm, Bm, W, tol, bnorm, mc, p.max_cycles, S, phase, Rr,
+                                false, 0, p.use_graph != 0);
             for (int b = 0; b < nmem; ++b) {
                 const Pair& q = todo[pos + b];
                 axpy_dev(X_eo + ((int64_t)q.j * ns + q.i) * n, 0, W + (int64_t)b * 2 * n, 0,

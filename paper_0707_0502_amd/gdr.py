@@ -48,7 +48,8 @@ class gdr_params(ctypes.Structure):
                 ("max_cycles", ctypes.c_int), ("precision", ctypes.c_int),
                 ("batch", ctypes.c_int), ("related_rhs", ctypes.c_int),
                 ("max_refine", ctypes.c_int), ("profile", ctypes.c_int),
-                ("m_clean", ctypes.c_int), ("proj_k", ctypes.c_int)]
+                ("m_clean", ctypes.c_int), ("proj_k", ctypes.c_int),
+                ("use_graph", ctypes.c_int)]
 
 
 class gdr_stats(ctypes.Structure):

@@ -124,7 +124,25 @@ CONFIGS = {
                sigmas=[0.0, -0.01, -0.02, -0.05, -0.1, -0.2],
                rhs=[("z4", 1000 + j) for j in range(12)], m_dr=60, k=20,
                m_proj=40, tol=1e-8, tol_extra=1e-4, precision="mixed"),
+    # the uneven mixed batch: one 32^3x64 lattice (FP16-stored links, 8 shifts,
+    # 4 RHS) solved concurrently with six 12^4 and four 16^4 lattices (2 RHS,
+    # 4 shifts each)
+    "C5": dict(dims=(32, 32, 32, 64), eps=0.5, seed=0, kappa_factor=0.98,
+               sigmas=[0.0, -0.005, -0.01, -0.02, -0.05, -0.1, -0.2, -0.3],
+               rhs=[("z4", 2000 + j) for j in range(4)], m_dr=60, k=20, m_proj=40,
+               tol=1e-8, tol_extra=1e-4, precision="mixed", links="f16"),
 }
+for _s in range(1, 7):
+    CONFIGS["C5a%d" % _s] = dict(dims=(12, 12, 12, 12), eps=0.5, seed=_s, kappa_factor=0.98,
+                                sigmas=[0.0, -0.02, -0.05, -0.1],
+                                rhs=[("z4", 3000 + 10 * _s + j) for j in range(2)], m_dr=40,
+                                k=15, m_proj=40, tol=1e-8, tol_extra=1e-4, precision="mixed")
+for _s in range(7, 11):
+    CONFIGS["C5b%d" % _s] = dict(dims=(16, 16, 16, 16), eps=0.5, seed=_s, kappa_factor=0.98,
+                                sigmas=[0.0, -0.02, -0.05, -0.1],
+                                rhs=[("z4", 3000 + 10 * _s + j) for j in range(2)], m_dr=40,
+                                k=15, m_proj=40, tol=1e-8, tol_extra=1e-4, precision="mixed")
+C5_GROUP = ["C5"] + ["C5a%d" % s for s in range(1, 7)] + ["C5b%d" % s for s in range(7, 11)]
 
 
 def make_rhs(cfg_or_dims, kind, seed):
