@@ -148,6 +148,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-dslash", action="store_true")
+    ap.add_argument("--m-clean", type=int, default=0,
+                    help="cycle length of the mixed-precision cleanup (0: library default)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="end with a 256 MiB device copy (calibrates hardware byte counters)")
     a = ap.parse_args()
@@ -181,7 +183,8 @@ def main():
     def params(prec, profile):
         return gdr.gdr_params_default(m_dr=cfg["m_dr"], k=cfg["k"], m_proj=cfg["m_proj"],
                                       tol=cfg["tol"], tol_extra=cfg["tol_extra"],
-                                      precision=prec, batch=1, profile=profile)
+                                      precision=prec, batch=1, profile=profile,
+                                      m_clean=a.m_clean)
 
     pm = params(gdr.GDR_PREC_MIXED, 0xFF)
     for w in range(a.warmup):
