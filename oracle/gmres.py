@@ -25,6 +25,12 @@ transposes):
   orthogonalised against P_k; H_bar_k <- P_{k+1}^H H_bar P_k (for A);
   V_{k+1} <- V_{m+1} P_{k+1}; c <- P_{k+1}^H s; v_{k+1} is
   re-orthogonalised against V_k.
+* FOM-Sh / FOM-DR-Sh (Sec. 3, Examples 2 and 3): each shift takes the
+  Galerkin solution (H_m - sigma_i I) y_i = beta_i c_{1:m}; the residuals are
+  then all multiples of v_{m+1} and beta_i^new = (y_i)_m / (y_1)_m. FOM-DR
+  deflates with Ritz pairs of H_m - sigma_1 I (smallest |theta|, same ties)
+  and otherwise restarts exactly as GMRES-DR (the residual direction s is
+  then e_{m+1}).
 * Convergence is tested at the end of a cycle only, on
   max_i |beta_i| ||r_1|| / ||b|| (the shortcut norm of eq. (2.6)).
 * After the last GMRES-DR-Sh cycle one more restart compression is made
@@ -102,6 +108,31 @@ def shifted_small_solves(H, c, sigmas, beta):
     return ds, s, beta_new
 
 
+def fom_small_solves(H, c, sigmas, beta):
+    """FOM-Sh small problems (Sec. 3, Examples 2-3): the Galerkin conditions
+    (H_m - sigma_i I) y_i = beta_i c_{1:m} on the square part of the
+    recurrence. Every residual is then a multiple of v_{m+1},
+    r_i = -h_{m+1,m} (e_m^T y_i) v_{m+1}, so the residuals of all shifts are
+    parallel without any extra condition. Same return shape as
+    shifted_small_solves: (ys, s, beta_new) with s = c - (H_bar - sigma_1 I_bar) y_1."""
+    p = H.shape[1]
+    Hm = H[:p, :]
+    Ip = np.eye(p, dtype=np.complex128)
+    ys = [np.linalg.solve(Hm - sigmas[i] * Ip, beta[i] * c[:p]) for i in range(len(sigmas))]
+    s = c - (H - sigmas[0] * ibar(p + 1, p)) @ ys[0]
+    beta_new = np.ones(len(sigmas), dtype=np.complex128)
+    for i in range(1, len(sigmas)):
+        beta_new[i] = ys[i][p - 1] / ys[0][p - 1]
+    return ys, s, beta_new
+
+
+def ritz(H, sigma1):
+    """Ritz values/vectors of the base-shifted square part H_m - sigma_1 I
+    (the deflation of FOM-DR)."""
+    m = H.shape[1]
+    return np.linalg.eig(H[:m, :] - sigma1 * np.eye(m, dtype=np.complex128))
+
+
 # ----------------------------------------------------------------------------
 # GMRES-DR restart: harmonic Ritz deflation (eqs. (2.7)-(2.9))
 # ----------------------------------------------------------------------------
@@ -144,15 +175,15 @@ def select_smallest(theta, k, rtol=1e-10):
     return np.array(out, dtype=int)
 
 
-def dr_restart(V, H, s, sigma1, k):
+def dr_restart(V, H, s, sigma1, k, fom=False):
     """Compress V_{m+1}, H_bar_m to V_{k+1}, H_bar_k around k harmonic Ritz
-    vectors and the residual direction s. Returns (V_{k+1}, H_bar_k, c_new,
-    selected theta)."""
+    vectors (Ritz vectors for FOM-DR) and the residual direction s. Returns
+    (V_{k+1}, H_bar_k, c_new, selected theta)."""
     m = H.shape[1]
     P = np.zeros((m + 1, k + 1), dtype=np.complex128)
     theta_sel = np.zeros(0, dtype=np.complex128)
     if k > 0:
-        theta, g = harmonic_ritz(H, sigma1)
+        theta, g = ritz(H, sigma1) if fom else harmonic_ritz(H, sigma1)
         sel = select_smallest(theta, k)
         theta_sel = theta[sel]
         Pk, _ = np.linalg.qr(g[:, sel])
@@ -174,8 +205,10 @@ def dr_restart(V, H, s, sigma1, k):
 # ----------------------------------------------------------------------------
 # GMRES-DR-Sh (Sec. 3, algorithm GMRES-DR-Sh)
 # ----------------------------------------------------------------------------
-def gmres_dr_sh(matvec, b, sigmas, m, k, tol, max_cycles=500):
+def gmres_dr_sh(matvec, b, sigmas, m, k, tol, max_cycles=500, fom=False):
     """Solve (A - sigma_i I) x_i = b for all shifts in one deflated space.
+    fom: FOM-DR-Sh instead (Galerkin small problems, Ritz deflation; Sec. 3,
+    Example 3); with k = 0 this is FOM(m)-Sh / GMRES(m)-Sh.
 
     Returns a dict: x (ns, n), beta, cycles, mvps, converged, history (per
     cycle: mvps, ||r_1||/||b||, max_i |beta_i| ||r_1||/||b||, selected
@@ -209,8 +242,8 @@ def gmres_dr_sh(matvec, b, sigmas, m, k, tol, max_cycles=500):
             if arnoldi_step(matvec, V, H, j):
                 mdim = j + 1
                 break
-        ds, s, beta_new = shifted_small_solves(H[:mdim + 1, :mdim], c[:mdim + 1],
-                                               sigmas, beta)
+        small = fom_small_solves if fom else shifted_small_solves
+        ds, s, beta_new = small(H[:mdim + 1, :mdim], c[:mdim + 1], sigmas, beta)
         for i in range(ns):
             x[i] += V[:, :mdim] @ ds[i]
         beta = beta_new
@@ -222,7 +255,7 @@ def gmres_dr_sh(matvec, b, sigmas, m, k, tol, max_cycles=500):
         if mdim < m:
             history.append(entry)
             break
-        Vk1, Hk, c_k, theta = dr_restart(V, H, s, sigmas[0], k)
+        Vk1, Hk, c_k, theta = dr_restart(V, H, s, sigmas[0], k, fom=fom)
         entry["theta"] = theta
         history.append(entry)
         if converged:
@@ -408,9 +441,11 @@ def related_rhs_start(B, X, b):
 # Driver: first RHS by GMRES-DR-Sh, extra RHS, later RHS by GMRES-Proj-Sh
 # ----------------------------------------------------------------------------
 def solve_all(matvec, B, sigmas, m_dr, k, m_proj, tol, tol_extra,
-              max_cycles=500, related=False):
+              max_cycles=500, related=False, fom=False):
     """Order of use (Sec. 4): RHS 1 by GMRES-DR-Sh, then the extra RHS
     v_{k+1}, then RHS 2.. by GMRES-Proj-Sh followed by the correction.
+    fom: RHS 1 by FOM-DR-Sh instead; its (V_{k+1}, H_bar_k) satisfies the
+    same recurrence, so the later right-hand sides are unchanged.
 
     Returns dict with X (nrhs, ns, n), per-RHS run records, the deflation
     pair, the extra-RHS solutions s and the true residual norms
@@ -422,7 +457,7 @@ def solve_all(matvec, B, sigmas, m_dr, k, m_proj, tol, tol_extra,
     ns = len(sigmas)
     X = np.zeros((nrhs, ns, n), dtype=np.complex128)
     runs = []
-    first = gmres_dr_sh(matvec, B[0], sigmas, m_dr, k, tol, max_cycles)
+    first = gmres_dr_sh(matvec, B[0], sigmas, m_dr, k, tol, max_cycles, fom=fom)
     X[0] = first["x"]
     runs.append(first)
     defl = first["defl"]
