@@ -156,6 +156,12 @@ typedef struct {
                           Theorem 1 and Table 4.1) */
     int use_graph;     /* 1: each Arnoldi cycle is captured once into a HIP graph and replayed
                           (fewer launches for small lattices; ignored while profiling) */
+    int galerkin;      /* 0: the deflated first-RHS phase is GMRES-DR-Sh (minimum residual
+                          base system, Sec. 3); 1: FOM-DR-Sh instead (Galerkin condition for
+                          every shift, residuals parallel by construction, Ritz deflation;
+                          Sec. 3, Examples 2 and 3), and with k = 0 FOM(m)-Sh. Later RHS
+                          keep GMRES-Proj-Sh. A singular Galerkin system returns
+                          GDR_ERR_BREAKDOWN. */
 } gdr_params;
 
 /* kernel classes of the profiler (gdr_params.profile bit i = class i) */
@@ -170,7 +176,7 @@ typedef struct {
 
 /* Fill defaults: m_dr 40, k 15, m_proj 40, tol 1e-8, tol_extra sqrt(tol),
  * max_cycles 1000, FP64, batch 1, related 0, max_refine 8, profile 0, m_clean 0,
- * proj_k 0, use_graph 0. */
+ * proj_k 0, use_graph 0, galerkin 0. */
 void gdr_params_default(gdr_params* p);
 
 typedef struct {

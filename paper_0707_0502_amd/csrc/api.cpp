@@ -51,6 +51,10 @@ bool check_params(gdr_ctx_s* c, const gdr_params* p, int ns, bool need_dr) {
         c->err = "use_graph must be 0 or 1";
         return false;
     }
+    if (p->galerkin != 0 && p->galerkin != 1) {
+        c->err = "galerkin must be 0 or 1";
+        return false;
+    }
     if (!(p->tol > 0) || p->max_cycles < 1 || p->max_refine < 0) {
         c->err = "need tol > 0, max_cycles >= 1, max_refine >= 0";
         return false;
@@ -182,6 +186,7 @@ void gdr_params_default(gdr_params* p) {
     p->m_clean = 0;
     p->proj_k = 0;
     p->use_graph = 0;
+    p->galerkin = 0;
 }
 
 int gdr_wilson_create(gdr_ctx c, const int dims[4], const int bc[4], double kappa,

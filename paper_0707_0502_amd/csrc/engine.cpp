@@ -1,4 +1,4 @@
-// Solver drivers: GMRES-DR-Sh for the first right-hand side (Sec. 3), the
+// Solver drivers: GMRES-DR-Sh (or FOM-DR-Sh) for the first right-hand side (Sec. 3), the
 // batched GMRES-Proj-Sh phase for the extra right-hand side v_{k+1} and the
 // later right-hand sides with the correction (Sec. 4), and the FP64-refined
 // cleanup of the mixed-precision path.
@@ -367,6 +367,7 @@ static int dr_run(gdr_op_s* op, int ns, const double2* sig_h, const double2* b_e
         a.cnew = cx;
         a.m = m;
         a.ns = ns;
+        a.galerkin = p.galerkin;
         S.prof.begin(GDR_K_SMALL);
         cycle_small(a, 1, st);
         S.prof.end(GDR_K_SMALL, 0, 0);
@@ -404,8 +405,12 @@ static int dr_run(gdr_op_s* op, int ns, const double2* sig_h, const double2* b_e
         HIPCHK(hipMemcpyAsync(&brk, A.brk, sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         if (mixed) rtn = vec_norm(op, rtrue);
-        if (o.flags & 1) throw GdrError(GDR_ERR_BREAKDOWN, "GMRES-DR-Sh: singular shifted system ((Q^H s)_{m+1} = 0)");
-        if (o.flags & 2) throw GdrError(GDR_ERR_BREAKDOWN, "GMRES-DR-Sh: harmonic Ritz eigensolver did not converge");
+        if (o.flags & 1)
+            throw GdrError(GDR_ERR_BREAKDOWN, p.galerkin ? "FOM-DR-Sh: singular Galerkin system (H_m - sigma_i I)"
+                                                         : "GMRES-DR-Sh: singular shifted system ((Q^H s)_{m+1} = 0)");
+        if (o.flags & 2)
+            throw GdrError(GDR_ERR_BREAKDOWN, p.galerkin ? "FOM-DR-Sh: Ritz eigensolver did not converge"
+                                                         : "GMRES-DR-Sh: harmonic Ritz eigensolver did not converge");
         const double r1 = (mixed ? rtn : o.snorm) / bnorm;
         double bmax = 1;
         for (int i = 1; i < ns; ++i) bmax = std::max(bmax, zabs(o.beta[i]));

@@ -9,7 +9,7 @@ namespace gdr {
 // Per-cycle results read back by the host (one small copy per cycle).
 struct CycleOut {
     double snorm;               // ||s|| = ||r_1|| (shortcut norm, eq. (2.6))
-    int flags;                  // bit0 breakdown in a shift solve, bit1 Schur failed
+    int flags;                  // bit0 singular shifted system, bit1 Schur failed
     int pad;
     double2 beta[MAXNS];        // beta_i^new
     double2 theta[MAXM];        // kept harmonic Ritz values (restart only)
@@ -39,6 +39,9 @@ struct CycleArgs {
     int m;
     int ns;
     const int* act;         // per member active flag (nullable)
+    // 0: GMRES-Sh (base least squares, Ritz deflation by harmonic Ritz pairs);
+    // 1: FOM-Sh (square Galerkin systems for every shift, Ritz pairs)
+    int galerkin;
 };
 
 struct ProjArgs {

@@ -377,19 +377,25 @@ __global__ __launch_bounds__(64) void k_cycle_small(CycleArgs a) {
     long long t_start = wall_clock64();
     const double2 s1 = sig[0];
     const bool restart_only = a.restart == 2;
+    const bool fom = a.galerkin != 0;
+    bool base_ok = true;
+    double2 y1_last = mk(0, 0);
     if (!restart_only) {
-        // ---- base least squares: [Hs | c], Hs = H - sigma_1 I_bar, (p+1) x p
+        // ---- base system: [Hs | c], Hs = H - sigma_1 I_bar. GMRES: least
+        // squares over all p+1 rows; FOM: the square Galerkin system (first p rows)
+        const int rows = fom ? p : p + 1;
         for (int c = 0; c <= p; ++c)
-            for (int r = lane; r <= p; r += 64) {
+            for (int r = lane; r < rows; r += 64) {
                 double2 v = c < p ? H[c * ldh + r] : cg[r];
                 if (c < p && r == c) v = csub(v, s1);
                 AT(A, r, c) = v;
             }
         __syncthreads();
-        hh_qr(A, p + 1, p, p + 1, hv);
+        hh_qr(A, rows, p, p + 1, hv);
         for (int r = lane; r < p; r += 64) dv[r] = AT(A, r, p);
         __syncthreads();
-        back_sub(A, p, dv);
+        base_ok = back_sub(A, p, dv);
+        y1_last = dv[p - 1];
         // s = c - Hs d_1 (from the original entries)
         for (int r = lane; r <= p; r += 64) {
             double2 acc = cg[r];
@@ -424,10 +430,12 @@ __global__ __launch_bounds__(64) void k_cycle_small(CycleArgs a) {
             if (lane == 0) {
                 out->snorm = sn;
                 out->beta[0] = mk(1, 0);
+                if (fom && !base_ok && !exact) atomicOr(&out->flags, 1);
             }
         }
         if (a.restart == 0 || exact || p < m) return;
-        // ---------------- GMRES-DR restart (harmonic Ritz, base shift)
+        // ---------------- DR restart (harmonic Ritz pairs for GMRES, Ritz pairs
+        // for FOM, of the base-shifted matrix)
         const int k = a.k;
         if (lane == 0) {
             out->tclk[0] = t_start;
@@ -435,6 +443,8 @@ __global__ __launch_bounds__(64) void k_cycle_small(CycleArgs a) {
         }
         __syncthreads();
         if (k > 0) {
+        double h2 = 0;
+        if (!fom) {
         // f = Hm^{-H} e_m :  A = [Hm^H | e_m]
         for (int c = 0; c <= m; ++c)
             for (int r = lane; r < m; r += 64) {
@@ -453,14 +463,15 @@ __global__ __launch_bounds__(64) void k_cycle_small(CycleArgs a) {
         for (int r = lane; r < m; r += 64) fv[r] = AT(A, r, m);
         __syncthreads();
         back_sub(A, m, fv);
+        h2 = cabs2(H[(m - 1) * ldh + m]);
+        }  // !fom
         if (lane == 0) out->tclk[2] = wall_clock64();
-        const double h2 = cabs2(H[(m - 1) * ldh + m]);
-        // G = Hm + h2 f e_m^H  into A (m x m); Z = I
+        // G = Hm + h2 f e_m^H (GMRES) or Hm (FOM) into A (m x m); Z = I
         for (int c = 0; c < m; ++c)
             for (int r = lane; r < m; r += 64) {
                 double2 v = H[c * ldh + r];
                 if (r == c) v = csub(v, s1);
-                if (c == m - 1) v = cadd(v, cscale(fv[r], h2));
+                if (!fom && c == m - 1) v = cadd(v, cscale(fv[r], h2));
                 AT(A, r, c) = v;
                 AT(Zs, r, c) = mk(r == c ? 1.0 : 0.0, 0);
             }
@@ -557,11 +568,37 @@ __global__ __launch_bounds__(64) void k_cycle_small(CycleArgs a) {
         return;
     }
 
-    // ---------------- shift `role`: [H - sigma_i I_bar | c | s]
     const int i = role;
     if (i >= ns) return;
     const double2 si = sig[i];
     const double2 bi = beta[i];
+    if (fom) {
+        // ---------------- shift `role`, FOM: (H_p - sigma_i I) y_i = beta_i c_{1:p};
+        // r_i = -h_{p+1,p} (y_i)_p v_{p+1}, hence beta_i^new = (y_i)_p / (y_1)_p
+        for (int c = 0; c <= p; ++c)
+            for (int r = lane; r < p; r += 64) {
+                double2 v = c < p ? H[c * ldh + r] : cmul(bi, cg[r]);
+                if (c < p && r == c) v = csub(v, si);
+                AT(A, r, c) = v;
+            }
+        __syncthreads();
+        hh_qr(A, p, p, p + 1, hv);
+        for (int r = lane; r < p; r += 64) dv[r] = AT(A, r, p);
+        __syncthreads();
+        bool bad = !back_sub(A, p, dv);
+        double2 bnew = mk(0, 0);
+        if (!exact) {
+            if (!(cabs(y1_last) > 0)) bad = true;
+            else bnew = cdiv(dv[p - 1], y1_last);
+        }
+        for (int r = lane; r <= m; r += 64) coef[i * (m + 1) + r] = r < p ? dv[r] : mk(0, 0);
+        if (lane == 0) {
+            out->beta[i] = bnew;
+            if (bad) atomicOr(&out->flags, 1);
+        }
+        return;
+    }
+    // ---------------- shift `role`, GMRES: [H - sigma_i I_bar | c | s]
     for (int c = 0; c < p + 2; ++c)
         for (int r = lane; r <= p; r += 64) {
             double2 v;
