@@ -9,6 +9,9 @@
 // all-reduce over 2,1) leaves value (lane>>2)&15 on four lanes. Blocks write
 // per-column partial sums; a second kernel adds them in a fixed order, so
 // every result is bitwise reproducible. All accumulation is FP64.
+#include <cstdint>
+#include <initializer_list>
+
 #include "kernels.h"
 
 namespace gdr {
@@ -52,29 +55,91 @@ __device__ __forceinline__ double wsum(double v) {
     return v;
 }
 
-int cgs_nblk(int64_t n) {
+int cgs_nblk(int64_t n, int nmem, bool wide) {
     int64_t tiles = (n + 63) / 64;
     int64_t nb = (tiles + 7) / 8;   // >= 2 tiles per wave on average
-    if (nb > 1024) nb = 1024;
+    // one FP32 member alone on the chip keeps more loads in flight with 2048
+    // blocks; batched members already fill it with 1024 each
+    const int64_t cap = wide && nmem == 1 ? 2048 : 1024;
+    if (nb > cap) nb = cap;
     if (nb < 1) nb = 1;
     return (int)nb;
+}
+
+// ---------------------------------------------------------------------------
+// Row access of the sweeps. R = 2 (FP32 data only): a lane owns two adjacent
+// complex rows and moves them as one 16-byte access; R = 1: one complex row
+// (8 bytes FP32, 16 bytes FP64). The basis V is streamed once per sweep and
+// not reused before it would be evicted, so its loads are non-temporal.
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+
+template <typename T, int R> struct RowIO;
+template <> struct RowIO<float, 1> {
+    using V = float2;
+    static __device__ __forceinline__ V ld(const float2* p) { return *p; }
+    static __device__ __forceinline__ V ldnt(const float2* p) {
+        const f2v v = __builtin_nontemporal_load((const f2v*)p);
+        return make_float2(v.x, v.y);
+    }
+    static __device__ __forceinline__ void get(const V& v, double2* d) { d[0] = to_d(v); }
+    static __device__ __forceinline__ void put(float2* p, const double2* d) { *p = from_d<float>(d[0]); }
+};
+template <> struct RowIO<float, 2> {
+    using V = float4;
+    static __device__ __forceinline__ V ld(const float2* p) { return *(const float4*)p; }
+    static __device__ __forceinline__ V ldnt(const float2* p) {
+        const f4v v = __builtin_nontemporal_load((const f4v*)p);
+        return make_float4(v.x, v.y, v.z, v.w);
+    }
+    static __device__ __forceinline__ void get(const V& v, double2* d) {
+        d[0] = mk(v.x, v.y);
+        d[1] = mk(v.z, v.w);
+    }
+    static __device__ __forceinline__ void put(float2* p, const double2* d) {
+        const float2 a = from_d<float>(d[0]), b = from_d<float>(d[1]);
+        *(float4*)p = make_float4(a.x, a.y, b.x, b.y);
+    }
+};
+template <> struct RowIO<double, 1> {
+    using V = double2;
+    static __device__ __forceinline__ V ld(const double2* p) { return *p; }
+    static __device__ __forceinline__ V ldnt(const double2* p) {
+        const d2v v = __builtin_nontemporal_load((const d2v*)p);
+        return mk(v.x, v.y);
+    }
+    static __device__ __forceinline__ void get(const V& v, double2* d) { d[0] = v; }
+    static __device__ __forceinline__ void put(double2* p, const double2* d) { *p = d[0]; }
+};
+
+// 16-byte row pairs need even sizes and strides and 16-byte aligned bases
+static inline bool pairable(int64_t n, std::initializer_list<int64_t> strides,
+                            std::initializer_list<const void*> ptrs) {
+    if (n & 1) return false;
+    for (int64_t s : strides)
+        if (s & 1) return false;
+    for (const void* p : ptrs)
+        if (p && ((uintptr_t)p & 15)) return false;
+    return true;
 }
 
 // ---------------------------------------------------------------------------
 // Delayed classical Gram-Schmidt (DCGS2) passes of the Arnoldi step.
 //
 // k_gs_dot: one sweep over V forms V_{0..nc-1}^H x_a for NX right-hand
-// vectors x_a, plus ||x_{NX-1}||^2. A block owns a contiguous row range; its
-// four waves split the columns, each wave accumulates up to 8 columns x NX
-// vectors per lane in FP64 over the rows, then a butterfly reduce-scatter
-// over the wavefront leaves one sum per four lanes. Partial sums go to
-// partial[((mem*nval) + a*nc + c)*nblk + blk], nval = NX*nc + 1.
-template <typename T, typename TX, int NX>
+// vectors x_a (NX = 2: r_j and w = A r_j) plus ||x_{NX-1}||^2, as per-block
+// partial sums (value v of member b at partial[(b*nval + v)*nblk + block],
+// nval = NX*nc + 1). A block owns a contiguous row range; its four waves
+// split the columns, each wave sweeping its rows for CW columns at a time.
+template <typename T, typename TX, int NX, int R>
 __global__ __launch_bounds__(256) void k_gs_dot(
     const typename CT<T>::t* __restrict__ V, int64_t ldv, int64_t v_ms, int nc,
     const typename CT<TX>::t* __restrict__ x0, int64_t x0_ms,
     const typename CT<TX>::t* __restrict__ x1, int64_t x1_ms, double2* __restrict__ partial,
     int nblk, int64_t n, const int* __restrict__ act) {
+    using IV = RowIO<T, R>;
+    using IX = RowIO<TX, R>;
     const int mem = blockIdx.y;
     if (act && !act[mem]) return;
     V += mem * v_ms;
@@ -82,7 +147,8 @@ __global__ __launch_bounds__(256) void k_gs_dot(
     if (NX > 1) x1 += mem * x1_ms;
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    const int64_t per = ((n + nblk - 1) / nblk + 63) & ~(int64_t)63;
+    constexpr int RW = 64 * R;   // rows per wave iteration
+    const int64_t per = ((n + nblk - 1) / nblk + RW - 1) / RW * RW;
     const int64_t r0 = (int64_t)blockIdx.x * per;
     const int64_t r1 = r0 + per < n ? r0 + per : n;
     const int nval = NX * nc + 1;
@@ -99,19 +165,24 @@ __global__ __launch_bounds__(256) void k_gs_dot(
 #pragma unroll
         for (int q = 0; q < 16; ++q) acc[q] = mk(0, 0);
         const typename CT<T>::t* vp = V + (int64_t)cs * ldv;
-        for (int64_t i = r0 + lane; i < r1; i += 64) {
-            const double2 xa = to_d(x0[i]);
-            const double2 xb = NX > 1 ? to_d(x1[i]) : mk(0, 0);
-            typename CT<T>::t vr[CW];
+        for (int64_t i = r0 + lane * R; i < r1; i += RW) {
+            double2 xa[R], xb[R];
+            IX::get(IX::ld(x0 + i), xa);
+            if (NX > 1) IX::get(IX::ld(x1 + i), xb);
+            typename IV::V vr[CW];
 #pragma unroll
             for (int c = 0; c < CW; ++c)
-                if (c < cnt) vr[c] = vp[(int64_t)c * ldv + i];
+                if (c < cnt) vr[c] = IV::ldnt(vp + (int64_t)c * ldv + i);
 #pragma unroll
             for (int c = 0; c < CW; ++c)
                 if (c < cnt) {
-                    const double2 v = to_d(vr[c]);
-                    acc[c] = cadd(acc[c], cjmul(v, xa));
-                    if (NX > 1) acc[8 + c] = cadd(acc[8 + c], cjmul(v, xb));
+                    double2 v[R];
+                    IV::get(vr[c], v);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        acc[c] = cadd(acc[c], cjmul(v[r], xa[r]));
+                        if (NX > 1) acc[8 + c] = cadd(acc[8 + c], cjmul(v[r], xb[r]));
+                    }
                 }
         }
         const double2 sum = rs16(acc, lane);
@@ -135,14 +206,14 @@ __global__ __launch_bounds__(256) void k_gs_dot(
 // with coefficients coef[mem*coef_ms + o*(MAXM+1) + c] and
 // beta[mem*coef_ms + 2*(MAXM+1) + 2*o + a]. y_0 may alias x_0 (each row is
 // read before it is written by the same thread).
-template <typename T, int NX, int NO>
+template <typename T, int NX, int NO, int R>
 __global__ __launch_bounds__(256) void k_gs_update(
     const typename CT<T>::t* __restrict__ V, int64_t ldv, int64_t v_ms, int nc,
     const typename CT<T>::t* x0, int64_t x0_ms, const typename CT<T>::t* __restrict__ x1,
     int64_t x1_ms, typename CT<T>::t* y0, int64_t y0_ms, typename CT<T>::t* __restrict__ y1,
     int64_t y1_ms, const double2* __restrict__ coef, int64_t coef_ms, int64_t n,
     const int* __restrict__ act) {
-    using C = typename CT<T>::t;
+    using IO = RowIO<T, R>;
     constexpr int CH = std::is_same<T, float>::value ? 16 : 8;
     const int mem = blockIdx.y;
     if (act && !act[mem]) return;
@@ -160,28 +231,37 @@ __global__ __launch_bounds__(256) void k_gs_update(
     }
     if (threadIdx.x < 2 * NO) bt[threadIdx.x >> 1][threadIdx.x & 1] = coef[2 * (MAXM + 1) + threadIdx.x];
     __syncthreads();
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const double2 xa = to_d(x0[i]);
-        const double2 xb = NX > 1 ? to_d(x1[i]) : mk(0, 0);
-        double2 o0 = cmul(bt[0][0], xa), o1 = mk(0, 0);
-        if (NX > 1) o0 = cadd(o0, cmul(bt[0][1], xb));
-        if (NO > 1) o1 = cadd(cmul(bt[NO - 1][0], xa), cmul(bt[NO - 1][1], xb));
+    for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * R; i < n;
+         i += (int64_t)gridDim.x * blockDim.x * R) {
+        double2 xa[R], xb[R], o0[R], o1[R];
+        IO::get(IO::ld(x0 + i), xa);
+        if (NX > 1) IO::get(IO::ld(x1 + i), xb);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            o0[r] = cmul(bt[0][0], xa[r]);
+            o1[r] = mk(0, 0);
+            if (NX > 1) o0[r] = cadd(o0[r], cmul(bt[0][1], xb[r]));
+            if (NO > 1) o1[r] = cadd(cmul(bt[NO - 1][0], xa[r]), cmul(bt[NO - 1][1], xb[r]));
+        }
         for (int cb = 0; cb < nc; cb += CH) {
-            C vr[CH];
+            typename IO::V vr[CH];
 #pragma unroll
             for (int c = 0; c < CH; ++c)
-                if (cb + c < nc) vr[c] = V[(int64_t)(cb + c) * ldv + i];
+                if (cb + c < nc) vr[c] = IO::ldnt(V + (int64_t)(cb + c) * ldv + i);
 #pragma unroll
             for (int c = 0; c < CH; ++c)
                 if (cb + c < nc) {
-                    const double2 v = to_d(vr[c]);
-                    o0 = csub(o0, cmul(v, cf[0][cb + c]));
-                    if (NO > 1) o1 = csub(o1, cmul(v, cf[NO - 1][cb + c]));
+                    double2 v[R];
+                    IO::get(vr[c], v);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        o0[r] = csub(o0[r], cmul(v[r], cf[0][cb + c]));
+                        if (NO > 1) o1[r] = csub(o1[r], cmul(v[r], cf[NO - 1][cb + c]));
+                    }
                 }
         }
-        y0[i] = from_d<T>(o0);
-        if (NO > 1) y1[i] = from_d<T>(o1);
+        IO::put(y0 + i, o0);
+        if (NO > 1) IO::put(y1 + i, o1);
     }
 }
 
@@ -191,12 +271,19 @@ void gs_dot(const typename CT<T>::t* V, int64_t ldv, int64_t v_ms, int nc,
             int64_t x1_ms, double2* partial, int nblk, int64_t n, int nmem, hipStream_t st,
             const int* act) {
     dim3 grid(nblk, nmem), blk(256);
-    if (x1)
-        hipLaunchKernelGGL((k_gs_dot<T, TX, 2>), grid, blk, 0, st, V, ldv, v_ms, nc, x0, x0_ms, x1,
-                           x1_ms, partial, nblk, n, act);
-    else
-        hipLaunchKernelGGL((k_gs_dot<T, TX, 1>), grid, blk, 0, st, V, ldv, v_ms, nc, x0, x0_ms, x1,
-                           x1_ms, partial, nblk, n, act);
+    constexpr bool f32 = std::is_same<T, float>::value && std::is_same<TX, float>::value;
+    const bool r2 = f32 && pairable(n, {ldv, v_ms, x0_ms, x1 ? x1_ms : 0}, {V, x0, x1});
+#define GS_DOT(NX, R)                                                                          \
+    hipLaunchKernelGGL((k_gs_dot<T, TX, NX, R>), grid, blk, 0, st, V, ldv, v_ms, nc, x0, x0_ms, \
+                       x1, x1_ms, partial, nblk, n, act)
+    if (f32 && r2) {
+        if (x1) GS_DOT(2, f32 ? 2 : 1);
+        else GS_DOT(1, f32 ? 2 : 1);
+    } else {
+        if (x1) GS_DOT(2, 1);
+        else GS_DOT(1, 1);
+    }
+#undef GS_DOT
 }
 
 template <typename T>
@@ -205,13 +292,21 @@ void gs_update(const typename CT<T>::t* V, int64_t ldv, int64_t v_ms, int nc,
                int64_t x1_ms, typename CT<T>::t* y0, int64_t y0_ms, typename CT<T>::t* y1,
                int64_t y1_ms, const double2* coef, int64_t coef_ms, int64_t n, int nmem,
                hipStream_t st, const int* act) {
-    dim3 grid(cgs_nblk(n), nmem), blk(256);
-    if (x1)
-        hipLaunchKernelGGL((k_gs_update<T, 2, 2>), grid, blk, 0, st, V, ldv, v_ms, nc, x0, x0_ms,
-                           x1, x1_ms, y0, y0_ms, y1, y1_ms, coef, coef_ms, n, act);
-    else
-        hipLaunchKernelGGL((k_gs_update<T, 1, 1>), grid, blk, 0, st, V, ldv, v_ms, nc, x0, x0_ms,
-                           x1, x1_ms, y0, y0_ms, y1, y1_ms, coef, coef_ms, n, act);
+    constexpr bool f32 = std::is_same<T, float>::value;
+    dim3 grid(cgs_nblk(n, nmem, f32), nmem), blk(256);
+    const bool r2 = f32 && pairable(n, {ldv, v_ms, x0_ms, x1 ? x1_ms : 0, y0_ms, y1 ? y1_ms : 0},
+                                    {V, x0, x1, y0, y1});
+#define GS_UPD(NX, R)                                                                            \
+    hipLaunchKernelGGL((k_gs_update<T, NX, NX, R>), grid, blk, 0, st, V, ldv, v_ms, nc, x0, x0_ms, \
+                       x1, x1_ms, y0, y0_ms, y1, y1_ms, coef, coef_ms, n, act)
+    if (f32 && r2) {
+        if (x1) GS_UPD(2, f32 ? 2 : 1);
+        else GS_UPD(1, f32 ? 2 : 1);
+    } else {
+        if (x1) GS_UPD(2, 1);
+        else GS_UPD(1, 1);
+    }
+#undef GS_UPD
 }
 
 template void gs_dot<float, float>(const float2*, int64_t, int64_t, int, const float2*, int64_t,

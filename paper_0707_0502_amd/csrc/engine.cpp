@@ -160,7 +160,7 @@ struct Arnoldi {
         H = mem.get<double2>(hms * nmem);
         inv = mem.get<double>(nmem);
         brk = mem.get<int>(nmem);
-        nblk = cgs_nblk(n);
+        nblk = cgs_nblk(n, nmem, std::is_same<T, float>::value);
         partial = mem.get<double2>((size_t)std::max(80, 2 * m + 4) * nblk * nmem);
         G = mem.get<double2>((size_t)GMS * nmem);
         coef = mem.get<double2>((size_t)GS_COEF_MS * nmem);

@@ -74,7 +74,7 @@ void dcgs_coef(const double2* G, int64_t g_ms, int j, int nx, int first, double2
 // ------------------------------------------------------------ BLAS (blas.hip)
 // Block-partial buffers: partial[(member*ncols_tot + col)*nblk + blk] (double2);
 // blocks per sweep over n rows
-int cgs_nblk(int64_t n);
+int cgs_nblk(int64_t n, int nmem = 1, bool wide = false);
 
 // out[b*out_mstride + c] (+)= sum_blk partial[(b*ncols + c)*nblk + blk], c < ncols
 void reduce_cols(const double2* partial, int nblk, int ncols, double2* out, int64_t out_mstride,
