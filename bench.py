@@ -138,6 +138,39 @@ def arnoldi_columns(st, cfg, nrhs):
     return steps
 
 
+def operator_timings(a, gdr, synth, ctx, op, dims, kappa, links, n):
+    """Standalone Wilson operator timings on the workload's lattice and, unless
+    skipped, on the 32^3x64 lattice."""
+    op16 = gdr.gdr_wilson_create(ctx, dims, (1, 1, 1, -1), kappa, links, gdr.GDR_LINKS_F16)
+    dsl = dslash_standalone(gdr, {"f32": (op, gdr.GDR_PREC_F32),
+                                  "f16link": (op16, gdr.GDR_PREC_F32),
+                                  "f64": (op, gdr.GDR_PREC_F64)}, n // 12)
+    gdr.gdr_op_destroy(op16)
+    if a.workload != "C5" and not a.no_big_dslash:
+        # the operator alone on the largest lattice (32^3x64, 25.2M unknowns):
+        # its working set is far above the 256 MB Infinity Cache
+        c5 = synth.CONFIGS["C5"]
+        links5 = synth.gauge_links(c5["dims"], c5["eps"], c5["seed"])
+        try:
+            kappa5 = synth.kappa("C5")
+        except KeyError:
+            kappa5 = kappa   # the timing does not depend on the value
+        ops5 = {}
+        for name, storage in (("f32", gdr.GDR_LINKS_F32), ("f16link", gdr.GDR_LINKS_F16)):
+            ops5[name] = gdr.gdr_wilson_create(ctx, c5["dims"], (1, 1, 1, -1), kappa5, links5,
+                                               storage)
+        del links5
+        big = dslash_standalone(gdr, {"f32": (ops5["f32"], gdr.GDR_PREC_F32),
+                                      "f16link": (ops5["f16link"], gdr.GDR_PREC_F32),
+                                      "f64": (ops5["f32"], gdr.GDR_PREC_F64)},
+                                ops5["f32"].n // 12)
+        dsl = {"24x24x24x48": dsl, "32x32x32x64": big}
+        for o in ops5.values():
+            gdr.gdr_op_destroy(o)
+
+    return dsl
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -148,6 +181,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-dslash", action="store_true")
+    ap.add_argument("--no-big-dslash", action="store_true",
+                    help="skip the standalone operator timing on the 32^3x64 lattice")
+    ap.add_argument("--dslash-only", action="store_true",
+                    help="only the standalone operator timings (no solves); prints their JSON")
     ap.add_argument("--m-clean", type=int, default=0,
                     help="cycle length of the mixed-precision cleanup (0: library default)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -176,6 +213,10 @@ def main():
     ctx = gdr.gdr_ctx_create(0, torch.cuda.current_stream().cuda_stream)
     op = gdr.gdr_wilson_create(ctx, dims, (1, 1, 1, -1), kappa, links, gdr.GDR_LINKS_F32)
     n = op.n
+    if a.dslash_only:
+        print(json.dumps({"dslash_standalone": operator_timings(a, gdr, synth, ctx, op, dims, kappa,
+                                                                links, n)}), flush=True)
+        return
     Bd = torch.from_numpy(B.ravel()).cuda()
     X = torch.zeros(nrhs * ns * n, dtype=torch.complex128, device="cuda")
     del B
@@ -235,13 +276,7 @@ def main():
         log("bench: fp64", fp64)
         del X64
 
-    dsl = None
-    if not a.no_dslash:
-        op16 = gdr.gdr_wilson_create(ctx, dims, (1, 1, 1, -1), kappa, links, gdr.GDR_LINKS_F16)
-        dsl = dslash_standalone(gdr, {"f32": (op, gdr.GDR_PREC_F32),
-                                      "f16link": (op16, gdr.GDR_PREC_F32),
-                                      "f64": (op, gdr.GDR_PREC_F64)}, n // 12)
-        del op16
+    dsl = None if a.no_dslash else operator_timings(a, gdr, synth, ctx, op, dims, kappa, links, n)
 
     cpu = None
     if not a.no_cpu:
