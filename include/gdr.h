@@ -162,6 +162,12 @@ typedef struct {
                           Sec. 3, Examples 2 and 3), and with k = 0 FOM(m)-Sh. Later RHS
                           keep GMRES-Proj-Sh. A singular Galerkin system returns
                           GDR_ERR_BREAKDOWN. */
+    int sstep;         /* FP32 Arnoldi of the mixed path: 0 or 1 one vector per step (delayed
+                          classical Gram-Schmidt twice, two sweeps over the basis per step);
+                          2..4 blocks of sstep vectors (powers of (A - c)/r on a disc holding
+                          the spectrum, block Gram-Schmidt twice and a Cholesky factor: four
+                          sweeps per block). Same Krylov space and Arnoldi relation; the FP64
+                          path always takes one vector per step. */
 } gdr_params;
 
 /* kernel classes of the profiler (gdr_params.profile bit i = class i) */
@@ -176,7 +182,7 @@ typedef struct {
 
 /* Fill defaults: m_dr 40, k 15, m_proj 40, tol 1e-8, tol_extra sqrt(tol),
  * max_cycles 1000, FP64, batch 1, related 0, max_refine 8, profile 0, m_clean 0,
- * proj_k 0, use_graph 0, galerkin 0. */
+ * proj_k 0, use_graph 0, galerkin 0, sstep 4. */
 void gdr_params_default(gdr_params* p);
 
 typedef struct {

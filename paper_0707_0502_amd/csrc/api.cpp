@@ -1,5 +1,6 @@
 // The C-ABI of include/gdr.h: argument checks, canonical <-> internal layout
 // conversion at the boundary, and error reporting.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -53,6 +54,10 @@ bool check_params(gdr_ctx_s* c, const gdr_params* p, int ns, bool need_dr) {
     }
     if (p->galerkin != 0 && p->galerkin != 1) {
         c->err = "galerkin must be 0 or 1";
+        return false;
+    }
+    if (p->sstep < 0 || p->sstep > BLK_MAX) {
+        c->err = "need 0 <= sstep <= 4";
         return false;
     }
     if (!(p->tol > 0) || p->max_cycles < 1 || p->max_refine < 0) {
@@ -124,7 +129,7 @@ void dslash_bench_run(gdr_op op, int nvec, int nsets, int reps, double* ms_each)
 
 }  // namespace
 
-#define API_TRY(c) try {
+#define API_TRY(c) try { gdr::PoolScope pool_scope_((c));
 #define API_CATCH(c)                                                \
     }                                                               \
     catch (const GdrError& e) {                                     \
@@ -153,6 +158,11 @@ int gdr_ctx_create(int device, void* hip_stream, gdr_ctx* out) {
         gdr_ctx_destroy(c);
         return GDR_ERR_HIP;
     }
+    {
+        // keep at most a third of the device's memory idle in the cache
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) == hipSuccess) c->pool.cap = tot / 3;
+    }
     *out = c;
     return GDR_OK;
 }
@@ -165,6 +175,9 @@ void gdr_ctx_destroy(gdr_ctx c) {
     }
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
     if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
+    (void)hipStreamSynchronize(c->st);
+    c->pool.release();
     delete c;
 }
 
@@ -187,6 +200,7 @@ void gdr_params_default(gdr_params* p) {
     p->proj_k = 0;
     p->use_graph = 0;
     p->galerkin = 0;
+    p->sstep = 4;
 }
 
 int gdr_wilson_create(gdr_ctx c, const int dims[4], const int bc[4], double kappa,
@@ -210,6 +224,9 @@ int gdr_wilson_create(gdr_ctx c, const int dims[4], const int bc[4], double kapp
     for (int mu = 0; mu < 4; ++mu) op->bc[mu] = bc[mu];
     op->g = make_geom(dims);
     op->kappa = kappa;
+    // A = I - kappa D with |lambda(D)| <= 8 for SU(3) links
+    op->spec_c = make_double2(1, 0);
+    op->spec_r = 8 * std::fabs(kappa) > 0 ? 8 * std::fabs(kappa) : 1;
     op->n = 12 * vol;
     op->lst = link_storage == GDR_LINKS_F64 ? GDR_LINKS_F32 : link_storage;
     const size_t nl = (size_t)36 * vol;
@@ -267,6 +284,23 @@ int gdr_bidiag_create(gdr_ctx c, int64_t n, const gdr_c64* diag, const gdr_c64* 
     op->ctx = c;
     op->kind = 1;
     op->n = n;
+    {
+        // Gershgorin: centre of the diagonal's bounding box, radius to the
+        // farthest diagonal entry plus the largest superdiagonal modulus
+        double xmin = h[0].x, xmax = h[0].x, ymin = h[0].y, ymax = h[0].y, emax = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            xmin = std::min(xmin, h[i].x);
+            xmax = std::max(xmax, h[i].x);
+            ymin = std::min(ymin, h[i].y);
+            ymax = std::max(ymax, h[i].y);
+            if (i + 1 < n) emax = std::max(emax, std::hypot(h[n + i].x, h[n + i].y));
+        }
+        op->spec_c = make_double2(0.5 * (xmin + xmax), 0.5 * (ymin + ymax));
+        double r = 0;
+        for (int64_t i = 0; i < n; ++i)
+            r = std::max(r, std::hypot(h[i].x - op->spec_c.x, h[i].y - op->spec_c.y));
+        op->spec_r = r + emax > 0 ? r + emax : 1;
+    }
     HIPCHK(hipMalloc(&op->bd64, (size_t)2 * n * sizeof(double2)));
     HIPCHK(hipMalloc(&op->bd32, (size_t)2 * n * sizeof(float2)));
     HIPCHK(hipMemcpyAsync(op->bd64, h.data(), (size_t)2 * n * sizeof(double2),
@@ -403,7 +437,7 @@ int gdr_solve_dr_sh(gdr_op op, int ns, const gdr_c64* sigma, const gdr_c64* b, g
     double2* beo = mem.get<double2>(n);
     double2* Xeo = mem.get<double2>((size_t)ns * n);
     op_pack<double>(op, (const double2*)b, beo, n, 1, c->st);
-    Stats S(st, (unsigned)p->profile, c->st);
+    Stats S(st, (unsigned)p->profile, c->st, &c->evpool);
     gdr_defl_s* d = nullptr;
     bool conv = false;
     Timer tdr;
@@ -441,7 +475,7 @@ int gdr_solve_proj_sh(gdr_op op, gdr_defl defl, int ns, const gdr_c64* sigma, in
     double2* Beo = mem.get<double2>((size_t)nrhs * n);
     double2* Xeo = mem.get<double2>((size_t)nrhs * ns * n);
     op_pack<double>(op, (const double2*)B, Beo, n, nrhs, c->st);
-    Stats S(st, (unsigned)p->profile, c->st);
+    Stats S(st, (unsigned)p->profile, c->st, &c->evpool);
     int rc = solve_proj_batch(op, defl, ns, (const double2*)sigma, nrhs, Beo, Xeo, 0, *p, S);
     if (p->precision == GDR_PREC_MIXED) {
         Timer tc;
@@ -472,7 +506,7 @@ int gdr_solve(gdr_op op, int ns, const gdr_c64* sigma, int nrhs, const gdr_c64* 
     double2* Beo = mem.get<double2>((size_t)nrhs * n);
     double2* Xeo = mem.get<double2>((size_t)nrhs * ns * n);
     op_pack<double>(op, (const double2*)B, Beo, n, nrhs, c->st);
-    Stats S(st, (unsigned)p->profile, c->st);
+    Stats S(st, (unsigned)p->profile, c->st, &c->evpool);
     gdr_defl_s* d = nullptr;
     bool conv = false;
     Timer tdr;

@@ -309,6 +309,191 @@ void gs_update(const typename CT<T>::t* V, int64_t ldv, int64_t v_ms, int nc,
 #undef GS_UPD
 }
 
+// ---------------------------------------------------------------------------
+// Block Gram-Schmidt sweeps of the s-step Arnoldi cycle: the same row
+// partition and reductions as the DCGS2 sweeps, with NX (<= BLK_MAX) block
+// vectors X_a = X + a*ldx in place of r_j and w.
+template <typename T, int NX, int R>
+__global__ __launch_bounds__(256) void k_blk_dot(
+    const typename CT<T>::t* __restrict__ V, int64_t ldv, int64_t v_ms, int nc,
+    const typename CT<T>::t* __restrict__ X, int64_t ldx, int64_t x_ms,
+    double2* __restrict__ partial, int nblk, int64_t n, const int* __restrict__ act) {
+    using IO = RowIO<T, R>;
+    const int mem = blockIdx.y;
+    if (act && !act[mem]) return;
+    V += mem * v_ms;
+    X += mem * x_ms;
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    constexpr int RW = 64 * R;
+    const int64_t per = ((n + nblk - 1) / nblk + RW - 1) / RW * RW;
+    const int64_t r0 = (int64_t)blockIdx.x * per;
+    const int64_t r1 = r0 + per < n ? r0 + per : n;
+    const int nval = NX * nc;
+    double2* pout = partial + (int64_t)mem * nval * nblk + blockIdx.x;
+    // accumulators: CW columns x NX vectors <= 16 (one reduce-scatter)
+    constexpr int CW = NX == 1 ? 8 : 16 / NX;
+    const int g = (nc + 3) >> 2;
+    const int c0 = wv * g;
+    const int c1 = c0 + g < nc ? c0 + g : nc;
+    for (int cs = c0; cs < c1; cs += CW) {
+        const int cnt = c1 - cs < CW ? c1 - cs : CW;
+        double2 acc[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc[q] = mk(0, 0);
+        const typename CT<T>::t* vp = V + (int64_t)cs * ldv;
+        for (int64_t i = r0 + lane * R; i < r1; i += RW) {
+            double2 xv[NX][R];
+#pragma unroll
+            for (int a = 0; a < NX; ++a) IO::get(IO::ld(X + (int64_t)a * ldx + i), xv[a]);
+            typename IO::V vr[CW];
+#pragma unroll
+            for (int c = 0; c < CW; ++c)
+                if (c < cnt) vr[c] = IO::ldnt(vp + (int64_t)c * ldv + i);
+#pragma unroll
+            for (int c = 0; c < CW; ++c)
+                if (c < cnt) {
+                    double2 v[R];
+                    IO::get(vr[c], v);
+#pragma unroll
+                    for (int a = 0; a < NX; ++a)
+#pragma unroll
+                        for (int r = 0; r < R; ++r) acc[a * CW + c] = cadd(acc[a * CW + c], cjmul(v[r], xv[a][r]));
+                }
+        }
+        const double2 sum = rs16(acc, lane);
+        if ((lane & 3) == 0) {
+            const int q = (lane >> 2) & 15;
+            const int a = q / CW, c = q % CW;
+            if (a < NX && c < cnt) pout[(int64_t)(a * nc + cs + c) * nblk] = sum;
+        }
+    }
+}
+
+template <typename T, int NB, int R>
+__global__ __launch_bounds__(256) void k_blk_update(
+    const typename CT<T>::t* __restrict__ V, int64_t ldv, int64_t v_ms, int nc,
+    typename CT<T>::t* X, int64_t ldx, int64_t x_ms, const double2* __restrict__ coef,
+    int64_t coef_ms, int64_t n, const int* __restrict__ act) {
+    using IO = RowIO<T, R>;
+    constexpr int CH = std::is_same<T, float>::value ? 8 : 4;
+    const int mem = blockIdx.y;
+    if (act && !act[mem]) return;
+    V += mem * v_ms;
+    X += mem * x_ms;
+    coef += mem * coef_ms;
+    __shared__ double2 cf[NB][MAXM + 1];
+    __shared__ double2 bt[NB][NB];
+    for (int t = threadIdx.x; t < NB * nc; t += blockDim.x) {
+        const int o = t / nc, c = t % nc;
+        cf[o][c] = coef[o * (MAXM + 1) + c];
+    }
+    if (threadIdx.x < NB * NB) {
+        const int o = threadIdx.x / NB, a = threadIdx.x % NB;
+        bt[o][a] = coef[BLK_MAX * (MAXM + 1) + o * BLK_MAX + a];
+    }
+    __syncthreads();
+    for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * R; i < n;
+         i += (int64_t)gridDim.x * blockDim.x * R) {
+        double2 o[NB][R];
+        {
+            double2 xv[NB][R];
+#pragma unroll
+            for (int a = 0; a < NB; ++a) IO::get(IO::ld(X + (int64_t)a * ldx + i), xv[a]);
+#pragma unroll
+            for (int q = 0; q < NB; ++q)
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    double2 acc = mk(0, 0);
+#pragma unroll
+                    for (int a = 0; a < NB; ++a) acc = cadd(acc, cmul(bt[q][a], xv[a][r]));
+                    o[q][r] = acc;
+                }
+        }
+        for (int cb = 0; cb < nc; cb += CH) {
+            typename IO::V vr[CH];
+#pragma unroll
+            for (int c = 0; c < CH; ++c)
+                if (cb + c < nc) vr[c] = IO::ldnt(V + (int64_t)(cb + c) * ldv + i);
+#pragma unroll
+            for (int c = 0; c < CH; ++c)
+                if (cb + c < nc) {
+                    double2 v[R];
+                    IO::get(vr[c], v);
+#pragma unroll
+                    for (int q = 0; q < NB; ++q)
+#pragma unroll
+                        for (int r = 0; r < R; ++r) o[q][r] = csub(o[q][r], cmul(v[r], cf[q][cb + c]));
+                }
+        }
+#pragma unroll
+        for (int q = 0; q < NB; ++q) IO::put(X + (int64_t)q * ldx + i, o[q]);
+    }
+}
+
+template <typename T>
+void blk_dot(const typename CT<T>::t* V, int64_t ldv, int64_t v_ms, int nc,
+             const typename CT<T>::t* X, int64_t ldx, int64_t x_ms, int nx, double2* partial,
+             int nblk, int64_t n, int nmem, hipStream_t st, const int* act) {
+    dim3 grid(nblk, nmem), blk(256);
+    constexpr bool f32 = std::is_same<T, float>::value;
+    const bool r2 = f32 && pairable(n, {ldv, v_ms, ldx, x_ms}, {V, X});
+#define BLK_DOT(NX, R)                                                                              \
+    hipLaunchKernelGGL((k_blk_dot<T, NX, R>), grid, blk, 0, st, V, ldv, v_ms, nc, X, ldx, x_ms, \
+                       partial, nblk, n, act)
+#define BLK_DOT_R(R)          \
+    switch (nx) {             \
+        case 1: BLK_DOT(1, R); break; \
+        case 2: BLK_DOT(2, R); break; \
+        case 3: BLK_DOT(3, R); break; \
+        default: BLK_DOT(4, R); break; \
+    }
+    if (r2) {
+        BLK_DOT_R(f32 ? 2 : 1)
+    } else {
+        BLK_DOT_R(1)
+    }
+#undef BLK_DOT_R
+#undef BLK_DOT
+}
+
+template <typename T>
+void blk_update(const typename CT<T>::t* V, int64_t ldv, int64_t v_ms, int nc,
+                typename CT<T>::t* X, int64_t ldx, int64_t x_ms, int nx, const double2* coef,
+                int64_t coef_ms, int64_t n, int nmem, hipStream_t st, const int* act) {
+    constexpr bool f32 = std::is_same<T, float>::value;
+    dim3 grid(cgs_nblk(n, nmem, f32), nmem), blk(256);
+    const bool r2 = f32 && pairable(n, {ldv, v_ms, ldx, x_ms}, {V, X});
+#define BLK_UPD(NB, R)                                                                             \
+    hipLaunchKernelGGL((k_blk_update<T, NB, R>), grid, blk, 0, st, V, ldv, v_ms, nc, X, ldx, x_ms, \
+                       coef, coef_ms, n, act)
+#define BLK_UPD_R(R)          \
+    switch (nx) {             \
+        case 1: BLK_UPD(1, R); break; \
+        case 2: BLK_UPD(2, R); break; \
+        case 3: BLK_UPD(3, R); break; \
+        default: BLK_UPD(4, R); break; \
+    }
+    if (r2) {
+        BLK_UPD_R(f32 ? 2 : 1)
+    } else {
+        BLK_UPD_R(1)
+    }
+#undef BLK_UPD_R
+#undef BLK_UPD
+}
+
+template void blk_dot<float>(const float2*, int64_t, int64_t, int, const float2*, int64_t, int64_t,
+                             int, double2*, int, int64_t, int, hipStream_t, const int*);
+template void blk_dot<double>(const double2*, int64_t, int64_t, int, const double2*, int64_t,
+                              int64_t, int, double2*, int, int64_t, int, hipStream_t, const int*);
+template void blk_update<float>(const float2*, int64_t, int64_t, int, float2*, int64_t, int64_t,
+                                int, const double2*, int64_t, int64_t, int, hipStream_t,
+                                const int*);
+template void blk_update<double>(const double2*, int64_t, int64_t, int, double2*, int64_t,
+                                 int64_t, int, const double2*, int64_t, int64_t, int, hipStream_t,
+                                 const int*);
+
 template void gs_dot<float, float>(const float2*, int64_t, int64_t, int, const float2*, int64_t,
                                    const float2*, int64_t, double2*, int, int64_t, int,
                                    hipStream_t, const int*);

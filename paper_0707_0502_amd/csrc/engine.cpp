@@ -24,6 +24,8 @@ gdr_defl_s::~gdr_defl_s() {
 namespace gdr {
 
 static inline double2 z(double r, double i = 0) { return make_double2(r, i); }
+
+thread_local DevPool* g_pool = nullptr;
 static inline double zabs(double2 a) { return std::hypot(a.x, a.y); }
 
 template <typename T>
@@ -146,6 +148,15 @@ struct Arnoldi {
     static constexpr int GMS = 2 * (MAXM + 1) + 2;
     DiagList dl{};
     Prof* prof = nullptr;
+    // s-step cycle (FP32 only): block size, reduced block sums, P1, raw norms,
+    // block coefficients, and the scaled shifted operator of the powers
+    int sblk = 0;
+    static constexpr int BGS = BLK_MAX * (MAXM + 1 + BLK_MAX);
+    double2* Gb = nullptr;
+    double2* Psave = nullptr;
+    double* znorm = nullptr;
+    double2* bcoef = nullptr;
+    DiagList dlp{};
 
     void init(DMem& mem, gdr_op_s* op_, int m_, int nmem_, C* Vbuf, int64_t vms_) {
         op = op_;
@@ -161,13 +172,83 @@ struct Arnoldi {
         inv = mem.get<double>(nmem);
         brk = mem.get<int>(nmem);
         nblk = cgs_nblk(n, nmem, std::is_same<T, float>::value);
-        partial = mem.get<double2>((size_t)std::max(80, 2 * m + 4) * nblk * nmem);
+        partial = mem.get<double2>((size_t)std::max({80, 2 * m + 4, BLK_MAX * (m + 1 + BLK_MAX)}) *
+                                   nblk * nmem);
+        Gb = mem.get<double2>((size_t)BGS * nmem);
+        Psave = mem.get<double2>((size_t)(MAXM + 1) * BLK_MAX * nmem);
+        znorm = mem.get<double>((size_t)BLK_MAX * nmem);
+        bcoef = mem.get<double2>((size_t)BLK_COEF_MS * nmem);
         G = mem.get<double2>((size_t)GMS * nmem);
         coef = mem.get<double2>((size_t)GS_COEF_MS * nmem);
         ref = mem.get<double>(nmem);
         for (int v = 0; v < DSLASH_MAXV; ++v) {
             dl.d[v] = z(1);
             dl.alpha[v] = 1;
+            // (A - c) / r: the operator's diagonal factor 1 - c, scale 1 / r
+            dlp.d[v] = z(1.0 - op->spec_c.x, -op->spec_c.y);
+            dlp.alpha[v] = 1.0 / op->spec_r;
+        }
+    }
+
+    // Block size of the cycle: s-step blocks only for the FP32 basis
+    void set_block(int s) { sblk = (std::is_same<T, float>::value && s >= 2) ? std::min(s, BLK_MAX) : 0; }
+
+    // s-step cycle: from the orthonormal column j, sb = min(sblk, m - j) powers
+    // z_i = (A - c) z_{i-1} / r go straight into columns j+1..j+sb; two block
+    // Gram-Schmidt passes against columns 0..j (projection sweep, update sweep,
+    // each twice; the second projection also forms the block's Gram matrix)
+    // and the Cholesky factor of the twice-projected block give the new
+    // orthonormal columns, and H columns j..j+sb-1 follow from the change of
+    // basis (sstep_small). Four sweeps over the basis per block of sb steps.
+    void blocks(int j0, const int* act, int nact) {
+        const double cs = sizeof(C);
+        const double dn = (double)n * nact;
+        for (int j = j0; j < m;) {
+            const int sb = std::min(sblk, m - j);
+            C* Z = V + (int64_t)(j + 1) * n;
+            for (int i = 1; i <= sb; ++i) {
+                const C* src = V + (int64_t)(j + i - 1) * n;
+                C* dst = V + (int64_t)(j + i) * n;
+                for (int b0 = 0; b0 < nmem; b0 += DSLASH_MAXV) {
+                    const int nb = std::min(DSLASH_MAXV, nmem - b0);
+                    prof->begin(GDR_K_DSLASH);
+                    op_apply<T>(op, src + b0 * vms, vms, dst + b0 * vms, vms, nullptr, 0, dlp, nb, st,
+                                act ? act + b0 : nullptr);
+                    const int na = std::min(nb, nact - std::min(nact, b0));
+                    prof->end(GDR_K_DSLASH, dslash_bytes<T>(op, na, false), dslash_flops(op, na));
+                }
+            }
+            const int nc = j + 1 + sb;
+            SstepArgs sa{};
+            sa.G = Gb;
+            sa.g_ms = BGS;
+            sa.j = j;
+            sa.sb = sb;
+            sa.m = m;
+            sa.Psave = Psave;
+            sa.p_ms = (int64_t)(MAXM + 1) * BLK_MAX;
+            sa.znorm = znorm;
+            sa.coef = bcoef;
+            sa.coef_ms = BLK_COEF_MS;
+            sa.H = H;
+            sa.ldh = m + 1;
+            sa.h_ms = hms;
+            sa.theta = op->spec_c;
+            sa.rho = op->spec_r;
+            sa.brk = brk;
+            sa.act = act;
+            for (int pass = 1; pass <= 2; ++pass) {
+                prof->begin(GDR_K_GS_PROJECT);
+                blk_dot<T>(V, n, vms, nc, Z, n, vms, sb, partial, nblk, n, nmem, st, act);
+                prof->end(GDR_K_GS_PROJECT, dn * (nc + sb) * cs, dn * 16.0 * nc * sb);
+                reduce_cols(partial, nblk, sb * nc, Gb, BGS, nullptr, 0, nmem, st, act);
+                sa.mode = pass;
+                sstep_small(sa, nmem, st);
+                prof->begin(GDR_K_GS_UPDATE);
+                blk_update<T>(V, n, vms, j + 1, Z, n, vms, sb, bcoef, BLK_COEF_MS, n, nmem, st, act);
+                prof->end(GDR_K_GS_UPDATE, dn * (j + 1 + 2.0 * sb) * cs, dn * 16.0 * (j + 1 + sb) * sb);
+            }
+            j += sb;
         }
     }
 
@@ -213,12 +294,20 @@ struct Arnoldi {
     std::vector<Cached> graphs;
     bool use_graph = false;
 
+    void body(int j0, const int* act, int nact) {
+        fill_int(brk, -1, nmem, st);
+        if (sblk >= 2) {
+            blocks(j0, act, nact);
+            return;
+        }
+        for (int j = j0; j < m; ++j) step(j, j0, act, nact);
+        close(act, nact);
+    }
+
     void cycle(int j0, const int* act, int nact) {
         // the legacy null stream cannot be captured: eager launches there
         if (!use_graph || prof->mask || st == nullptr) {
-            fill_int(brk, -1, nmem, st);
-            for (int j = j0; j < m; ++j) step(j, j0, act, nact);
-            close(act, nact);
+            body(j0, act, nact);
             return;
         }
         for (auto& c : graphs)
@@ -228,9 +317,7 @@ struct Arnoldi {
             }
         Cached c{V, H, j0, nullptr, nullptr};
         HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        fill_int(brk, -1, nmem, st);
-        for (int j = j0; j < m; ++j) step(j, j0, act, nact);
-        close(act, nact);
+        body(j0, act, nact);
         HIPCHK(hipStreamEndCapture(st, &c.g));
         HIPCHK(hipGraphInstantiate(&c.e, c.g, nullptr, nullptr, 0));
         graphs.push_back(c);
@@ -295,6 +382,7 @@ static int dr_run(gdr_op_s* op, int ns, const double2* sig_h, const double2* b_e
     Arnoldi<T> A;
     A.init(mem, op, m, 1, Va, 0);
     A.use_graph = p.use_graph != 0;
+    A.set_block(p.sstep);
     A.prof = &S.prof;
     double2* Hn = mem.get<double2>((size_t)(m + 1) * m);
     double2* c0 = mem.get<double2>(m + 1);
@@ -512,7 +600,7 @@ static void proj_run(gdr_op_s* op, gdr_defl_s* defl, int nmem, int ns,
                      const std::vector<double2>& sig_h, const double2* Bm, double2* W,
                      const std::vector<double>& tol, const std::vector<double>& bnorm, int m,
                      int max_cycles, Stats& S, const std::vector<int>& phase, ProjResult& R,
-                     bool start = false, int kp = 0, bool graph = false) {
+                     bool start = false, int kp = 0, bool graph = false, int sblk = 0) {
     // kp > 0: project over the leading kp deflation vectors only (the
     // accurate-eigenvector variant, Table 4.1); otherwise over all k.
     // graph: replay the Arnoldi cycle from a captured HIP graph
@@ -531,6 +619,7 @@ static void proj_run(gdr_op_s* op, gdr_defl_s* defl, int nmem, int ns,
     Arnoldi<T> A;
     A.init(mem, op, m, nmem, Vb, vms);
     A.use_graph = graph;
+    A.set_block(sblk);
     A.prof = &S.prof;
     double2* sig = mem.get<double2>((size_t)nmem * ns);
     double2* Cb = mem.get<double2>((size_t)80 * nmem);
@@ -904,7 +993,7 @@ static int proj_batch(gdr_op_s* op, gdr_defl_s* d, int ns, const double2* sig_h,
                                    nsolved, ids, Bm, W, st);
         if (d->prec == GDR_PREC_MIXED)
             proj_run<float>(op, d, nmem, ns, sgm, Bm, W, tol, bnorm, m, p.max_cycles, S, phase, R,
-                            related, kp, p.use_graph != 0);
+                            related, kp, p.use_graph != 0, p.sstep);
         else
             proj_run<double>(op, d, nmem, ns, sgm, Bm, W, tol, bnorm, m, p.max_cycles, S, phase, R,
                              related, kp, p.use_graph != 0);
@@ -1084,7 +1173,7 @@ int cleanup(gdr_op_s* op, gdr_defl_s* defl, int ns, const double2* sig, int nrhs
                                  false, 0, p.use_graph != 0);
             else
                 proj_run<float>(op, defl, nmem, 1, sgm, Bm, W, tol, bnorm, mc, p.max_cycles, S, phase, Rr,
-                                false, 0, p.use_graph != 0);
+                                false, 0, p.use_graph != 0, p.sstep);
             for (int b = 0; b < nmem; ++b) {
                 const Pair& q = todo[pos + b];
                 axpy_dev(X_eo + ((int64_t)q.j * ns + q.i) * n, 0, W + (int64_t)b * 2 * n, 0,

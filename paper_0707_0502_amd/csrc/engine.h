@@ -1,7 +1,10 @@
 // Host engine: handles behind the C-ABI and the solver drivers.
 #pragma once
 
+#include <map>
+#include <new>
 #include <stdexcept>
+#include <unordered_map>
 #include <string>
 #include <vector>
 
@@ -22,12 +25,75 @@ struct GdrError : std::runtime_error {
                            std::string(#x) + ": " + hipGetErrorString(e_));               \
     } while (0)
 
+namespace gdr {
+// Device memory cache of a context. Solves allocate their work buffers per
+// call; returning them here instead of to the driver lets the next call (or
+// the next batch of the same call) reuse them without mapping new memory.
+// Best fit within +25 % (sizes rounded up to 2 MiB); at most `cap` bytes are
+// kept idle; a failed allocation releases the idle blocks and retries once.
+// Blocks are only reused in stream order on the context's stream.
+struct DevPool {
+    std::multimap<size_t, void*> idle;
+    std::unordered_map<void*, size_t> used;
+    size_t idle_bytes = 0;
+    size_t cap = 0;
+    static size_t round(size_t b) {
+        const size_t g = b >= (1u << 20) ? (size_t)2 << 20 : (size_t)4 << 10;
+        return (b + g - 1) / g * g;
+    }
+    void* get(size_t bytes) {
+        bytes = round(bytes);
+        auto it = idle.lower_bound(bytes);
+        if (it != idle.end() && it->first <= bytes + bytes / 4) {
+            void* p = it->second;
+            used[p] = it->first;
+            idle_bytes -= it->first;
+            idle.erase(it);
+            return p;
+        }
+        void* p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            release();
+            if (hipMalloc(&p, bytes) != hipSuccess) {
+                (void)hipGetLastError();
+                throw std::bad_alloc();
+            }
+        }
+        used[p] = bytes;
+        return p;
+    }
+    void put(void* p) {
+        auto it = used.find(p);
+        if (it == used.end()) return;
+        const size_t sz = it->second;
+        used.erase(it);
+        if (idle_bytes + sz > cap) {
+            (void)hipFree(p);
+            return;
+        }
+        idle.emplace(sz, p);
+        idle_bytes += sz;
+    }
+    void release() {
+        for (auto& kv : idle) (void)hipFree(kv.second);
+        idle.clear();
+        idle_bytes = 0;
+    }
+};
+}  // namespace gdr
+
 struct gdr_ctx_s {
     int device = 0;
     hipStream_t st = nullptr;    // caller's stream: every result is ordered on it
     hipStream_t aux = nullptr;   // library stream for work that overlaps st
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::string err;
+    // timing events of the optional kernel profiler, reused by every solve on
+    // this context (creating and destroying thousands per solve costs more
+    // than the solve's small kernels)
+    std::vector<hipEvent_t> evpool;
+    gdr::DevPool pool;
 };
 
 struct gdr_op_s {
@@ -42,6 +108,10 @@ struct gdr_op_s {
     int kind = 0;             // 0: Wilson-Dirac lattice operator, 1: bidiagonal matrix
     double2* bd64 = nullptr;  // bidiagonal: diagonal (n) then superdiagonal (n), FP64
     float2* bd32 = nullptr;   //   and the FP32 copy
+    // a disc holding the spectrum of A (centre, radius): the s-step basis is
+    // built from powers of (A - centre) / radius
+    double2 spec_c = {1, 0};
+    double spec_r = 1;
 };
 
 namespace gdr {
@@ -78,17 +148,41 @@ struct gdr_defl_s {
 
 namespace gdr {
 
-// device allocation list freed on scope exit
+// the memory cache of the context whose API call runs on this thread (set by
+// PoolScope at every entry point; one context per host thread)
+extern thread_local DevPool* g_pool;
+struct PoolScope {
+    DevPool* prev;
+    explicit PoolScope(gdr_ctx_s* c) : prev(g_pool) { g_pool = c ? &c->pool : nullptr; }
+    ~PoolScope() { g_pool = prev; }
+};
+
+// device allocation list handed back on scope exit (to the context's cache
+// when one is active, else to the driver)
 struct DMem {
     std::vector<void*> ptrs;
+    DevPool* pool = g_pool;
     ~DMem() {
-        for (void* p : ptrs) (void)hipFree(p);
+        for (void* p : ptrs) {
+            if (pool)
+                pool->put(p);
+            else
+                (void)hipFree(p);
+        }
     }
     template <class X>
     X* get(size_t count) {
         void* p = nullptr;
         if (count == 0) count = 1;
-        HIPCHK(hipMalloc(&p, count * sizeof(X)));
+        if (pool) {
+            try {
+                p = pool->get(count * sizeof(X));
+            } catch (const std::bad_alloc&) {
+                throw GdrError(GDR_ERR_OOM, "device allocation failed");
+            }
+        } else {
+            HIPCHK(hipMalloc(&p, count * sizeof(X)));
+        }
         ptrs.push_back(p);
         return (X*)p;
     }
@@ -105,16 +199,17 @@ struct Prof {
         hipEvent_t a, b;
     };
     std::vector<Rec> pend;
-    std::vector<hipEvent_t> pool;
+    std::vector<hipEvent_t> own;
+    std::vector<hipEvent_t>* pool = &own;   // the context's pool when one is given
     hipEvent_t cur = nullptr;
     double ms[8] = {}, bytes[8] = {}, flops[8] = {};
     int64_t cnt[8] = {};
     bool on(int cls) const { return (mask >> cls) & 1u; }
     hipEvent_t get() {
         hipEvent_t e;
-        if (!pool.empty()) {
-            e = pool.back();
-            pool.pop_back();
+        if (!pool->empty()) {
+            e = pool->back();
+            pool->pop_back();
         } else {
             HIPCHK(hipEventCreate(&e));
         }
@@ -155,26 +250,29 @@ struct Prof {
             bytes[r.cls] += r.bytes;
             flops[r.cls] += r.flops;
             cnt[r.cls] += 1;
-            pool.push_back(r.a);
-            pool.push_back(r.b);
+            pool->push_back(r.a);
+            pool->push_back(r.b);
         }
         pend.clear();
     }
     ~Prof() {
         for (auto& r : pend) {
-            pool.push_back(r.a);
-            pool.push_back(r.b);
+            pool->push_back(r.a);
+            pool->push_back(r.b);
         }
-        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+        for (hipEvent_t e : own) (void)hipEventDestroy(e);
     }
 };
 
 struct Stats {
     gdr_stats* st = nullptr;
     Prof prof;
-    Stats(gdr_stats* s, unsigned mask, hipStream_t stream) : st(s) {
+    Stats(gdr_stats* s, unsigned mask, hipStream_t stream,
+          std::vector<hipEvent_t>* evpool = nullptr)
+        : st(s) {
         prof.mask = mask;
         prof.st = stream;
+        if (evpool) prof.pool = evpool;
     }
     void flush() {
         prof.harvest();

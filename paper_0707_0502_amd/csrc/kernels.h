@@ -65,6 +65,19 @@ void gs_update(const typename CT<T>::t* V, int64_t ldv, int64_t v_ms, int nc,
                int64_t x1_ms, typename CT<T>::t* y0, int64_t y0_ms, typename CT<T>::t* y1,
                int64_t y1_ms, const double2* coef, int64_t coef_ms, int64_t n, int nmem,
                hipStream_t st, const int* act = nullptr);
+// Block Gram-Schmidt of the s-step Arnoldi cycle (block of nx <= BLK_MAX new
+// vectors X_a = X + a*ldx, member b at + b*x_ms):
+//   blk_dot:    partial sums of V_c^H X_a, c < nc, value a*nc + c (nval = nx*nc)
+//   blk_update: in place, X_o <- sum_a X_a beta[o][a] - sum_{c<nc} V_c coef[o][c]
+// with coef[o*(MAXM+1) + c] and beta[BLK_MAX*(MAXM+1) + o*BLK_MAX + a].
+template <typename T>
+void blk_dot(const typename CT<T>::t* V, int64_t ldv, int64_t v_ms, int nc,
+             const typename CT<T>::t* X, int64_t ldx, int64_t x_ms, int nx, double2* partial,
+             int nblk, int64_t n, int nmem, hipStream_t st, const int* act = nullptr);
+template <typename T>
+void blk_update(const typename CT<T>::t* V, int64_t ldv, int64_t v_ms, int nc,
+                typename CT<T>::t* X, int64_t ldx, int64_t x_ms, int nx, const double2* coef,
+                int64_t coef_ms, int64_t n, int nmem, hipStream_t st, const int* act = nullptr);
 // DCGS2 bookkeeping of step j (see blas.hip): H corrections, next H column and
 // the update coefficients, breakdown flag.
 void dcgs_coef(const double2* G, int64_t g_ms, int j, int nx, int first, double2* H, int64_t ldh,

@@ -64,6 +64,37 @@ struct ProjArgs {
     const int* act;         // per member active flag (nullable)
 };
 
+// Small FP64 part of one block of the s-step Arnoldi cycle (one wavefront per
+// member). The block starts from the orthonormal column j; Z = [z_1..z_sb]
+// (columns j+1..j+sb) holds z_i = (A - theta) z_{i-1} / rho with z_0 = v_j.
+// G holds the reduced sums [V_{0..j}, Z]^H Z of the sweep just made (value
+// a*nc + c, nc = j+1+sb).
+//   mode 1 (after the first projection): keep P1 = V_{0..j}^H Z and the raw
+//     norms ||z_a||^2; coefficients of Z' = Z - V_{0..j} P1.
+//   mode 2 (after the second projection, Z'): P2 = V_{0..j}^H Z', the Cholesky
+//     factor R of Z'^H Z' - P2^H P2 (Z'' = Q R); coefficients of
+//     Q = (Z' - V_{0..j} P2) R^{-1}; H columns j..j+sb-1 from
+//     A Zhat = Z diag(rho) + Zhat diag(theta) in the basis [V_{0..j}, Q].
+// A pivot below 1e-10 of the raw ||z_a||^2 is a breakdown (the Krylov space
+// is invariant): brk = j + a, the later block vectors are zero.
+struct SstepArgs {
+    const double2* G;
+    int64_t g_ms;
+    int j, sb, mode, m;
+    double2* Psave;   // per member (MAXM+1) x BLK_MAX, P1[c][a] at c*BLK_MAX + a
+    int64_t p_ms;
+    double* znorm;    // per member BLK_MAX
+    double2* coef;    // per member BLK_COEF_MS
+    int64_t coef_ms;
+    double2* H;       // (m+1) x m column-major per member
+    int64_t ldh, h_ms;
+    double2 theta;
+    double rho;
+    int* brk;
+    const int* act;
+};
+void sstep_small(const SstepArgs& a, int nmem, hipStream_t st);
+
 void cycle_small(const CycleArgs& a, int nmem, hipStream_t st);
 void proj_small(const ProjArgs& a, int nmem, hipStream_t st);
 // (B^H B) d = B^H b for related right-hand sides (np <= MAXM), d and -d per member

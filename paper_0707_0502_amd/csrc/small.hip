@@ -634,6 +634,149 @@ __global__ __launch_bounds__(64) void k_cycle_small(CycleArgs a) {
     }
 }
 
+__global__ __launch_bounds__(64) void k_sstep_small(SstepArgs a) {
+    const int lane = threadIdx.x;
+    const int b = blockIdx.x;
+    if (a.act && !a.act[b]) return;
+    const int j = a.j, sb = a.sb, nc = j + 1 + sb;
+    const double2* G = a.G + b * a.g_ms;
+    double2* Ps = a.Psave + b * a.p_ms;
+    double* zn = a.znorm + b * BLK_MAX;
+    double2* coef = a.coef + b * a.coef_ms;
+    double2* beta = coef + BLK_MAX * (MAXM + 1);
+    if (a.mode == 1) {
+        for (int t = lane; t < (j + 1) * sb; t += 64) {
+            const int c = t / sb, q = t % sb;
+            const double2 p = G[q * nc + c];
+            Ps[c * BLK_MAX + q] = p;
+            coef[q * (MAXM + 1) + c] = p;
+        }
+        if (lane < sb) zn[lane] = G[lane * nc + j + 1 + lane].x;
+        if (lane < BLK_MAX * BLK_MAX) beta[lane] = mk((lane / BLK_MAX) == (lane % BLK_MAX) ? 1.0 : 0.0, 0);
+        return;
+    }
+    __shared__ double2 P2[(MAXM + 1) * BLK_MAX];
+    __shared__ double2 Ch[(MAXM + 1) * BLK_MAX];
+    __shared__ double2 G2[BLK_MAX * BLK_MAX];
+    __shared__ double2 R[BLK_MAX * BLK_MAX];      // R[l*BLK_MAX + c], upper
+    __shared__ double2 Ri[BLK_MAX * BLK_MAX];     // inverse of the leading nq x nq block
+    __shared__ int sh_fi;
+    for (int t = lane; t < (j + 1) * BLK_MAX; t += 64) {
+        const int c = t / BLK_MAX, q = t % BLK_MAX;
+        const double2 p = q < sb ? G[q * nc + c] : mk(0, 0);
+        P2[t] = p;
+        Ch[t] = q < sb ? cadd(Ps[t], p) : mk(0, 0);
+    }
+    __syncthreads();
+    // G2 = Z'^H Z' - P2^H P2
+    for (int e = 0; e < sb * sb; ++e) {
+        const int r = e / sb, q = e % sb;   // G2[r][q] = z'_r^H z'_q - sum_c conj(P2[c][r]) P2[c][q]
+        double sx = 0, sy = 0;
+        for (int c = lane; c <= j; c += 64) {
+            const double2 v = cjmul(P2[c * BLK_MAX + r], P2[c * BLK_MAX + q]);
+            sx += v.x;
+            sy += v.y;
+        }
+        sx = wred(sx);
+        sy = wred(sy);
+        if (lane == 0) G2[r * BLK_MAX + q] = csub(G[q * nc + j + 1 + r], mk(sx, sy));
+    }
+    __syncthreads();
+    if (lane == 0) {
+        int fi = -1;
+        for (int t = 0; t < BLK_MAX * BLK_MAX; ++t) {
+            R[t] = mk(0, 0);
+            Ri[t] = mk(0, 0);
+        }
+        for (int i = 0; i < sb && fi < 0; ++i) {
+            // row i of R: R[i][c] = (G2[i][c] - sum_{l<i} conj(R[l][i]) R[l][c]) / R[i][i]
+            double piv = G2[i * BLK_MAX + i].x;
+            for (int l = 0; l < i; ++l) piv -= cabs2(R[l * BLK_MAX + i]);
+            if (!(piv > 1e-10 * zn[i])) {
+                fi = i;
+                break;
+            }
+            const double rii = sqrt(piv);
+            R[i * BLK_MAX + i] = mk(rii, 0);
+            for (int c = i + 1; c < sb; ++c) {
+                double2 v = G2[i * BLK_MAX + c];
+                for (int l = 0; l < i; ++l) v = csub(v, cjmul(R[l * BLK_MAX + i], R[l * BLK_MAX + c]));
+                R[i * BLK_MAX + c] = cscale(v, 1.0 / rii);
+            }
+        }
+        if (fi >= 0) {
+            // the dependent vector z_{fi+1}: keep its coordinates on q_1..q_fi
+            for (int c = fi; c < sb; ++c)
+                for (int l = fi; l < BLK_MAX; ++l) R[l * BLK_MAX + c] = mk(0, 0);
+            if (a.brk[b] < 0) a.brk[b] = j + fi;
+        }
+        const int nq = fi >= 0 ? fi : sb;
+        // inverse of the leading nq x nq upper triangle
+        for (int c = 0; c < nq; ++c) {
+            Ri[c * BLK_MAX + c] = cdiv(mk(1, 0), R[c * BLK_MAX + c]);
+            for (int r = c - 1; r >= 0; --r) {
+                double2 v = mk(0, 0);
+                for (int l = r + 1; l <= c; ++l) v = cadd(v, cmul(R[r * BLK_MAX + l], Ri[l * BLK_MAX + c]));
+                Ri[r * BLK_MAX + c] = cscale(cdiv(v, R[r * BLK_MAX + r]), -1.0);
+            }
+        }
+        sh_fi = fi;
+    }
+    __syncthreads();
+    const int fi = sh_fi;
+    const int nq = fi >= 0 ? fi : sb;           // new orthonormal columns
+    const int bs = fi >= 0 ? fi + 1 : sb;       // H columns produced by this block
+    // final update: q_o = sum_a z'_a Ri[a][o] - sum_c v_c (P2 Ri)[c][o]
+    for (int t = lane; t < BLK_MAX * BLK_MAX; t += 64) {
+        const int o = t / BLK_MAX, q = t % BLK_MAX;
+        beta[t] = (o < nq && q < nq) ? Ri[q * BLK_MAX + o] : mk(0, 0);
+    }
+    for (int t = lane; t < (j + 1) * BLK_MAX; t += 64) {
+        const int c = t / BLK_MAX, o = t % BLK_MAX;
+        double2 v = mk(0, 0);
+        if (o < nq)
+            for (int q = 0; q <= o; ++q) v = cadd(v, cmul(P2[c * BLK_MAX + q], Ri[q * BLK_MAX + o]));
+        coef[o * (MAXM + 1) + c] = v;
+    }
+    // H columns j..j+bs-1 (rows 0..m), by rows across the lanes
+    double2* H = a.H + b * a.h_ms;
+    const double2 th = a.theta;
+    const double rho = a.rho;
+    for (int r = lane; r <= a.m; r += 64) {
+        double2 X[BLK_MAX];
+        for (int c = 0; c < bs; ++c) {
+            // coordinates of z_{c+1} (Zc) and of z_c (Zh) on row r
+            auto zc = [&](int cc) -> double2 {
+                if (r <= j) return Ch[r * BLK_MAX + cc];
+                const int l = r - j - 1;
+                return (l <= cc && l < BLK_MAX) ? R[l * BLK_MAX + cc] : mk(0, 0);
+            };
+            const double2 zh = c == 0 ? mk(r == j ? 1.0 : 0.0, 0) : zc(c - 1);
+            double2 t = cadd(cscale(zc(c), rho), cmul(th, zh));
+            if (c >= 1 && r <= j) {
+                // (H_old M_a)[r][c] over all columns l < j: after a deflated
+                // restart the leading (k+1) x k block of H_old is full, not
+                // Hessenberg
+                double2 hm = mk(0, 0);
+                for (int l = 0; l < j; ++l)
+                    hm = cadd(hm, cmul(H[(int64_t)l * a.ldh + r], Ch[l * BLK_MAX + c - 1]));
+                t = csub(t, hm);
+            }
+            // X[:, c] = (T[:, c] - sum_{l<c} X[:, l] Mb[l][c]) / Mb[c][c]
+            for (int l = 0; l < c; ++l) {
+                const double2 mb = l == 0 ? Ch[j * BLK_MAX + c - 1] : R[(l - 1) * BLK_MAX + c - 1];
+                t = csub(t, cmul(X[l], mb));
+            }
+            X[c] = c == 0 ? t : cdiv(t, R[(c - 1) * BLK_MAX + c - 1]);
+        }
+        for (int c = 0; c < bs; ++c) H[(int64_t)(j + c) * a.ldh + r] = r <= j + c + 1 ? X[c] : mk(0, 0);
+    }
+}
+
+void sstep_small(const SstepArgs& a, int nmem, hipStream_t st) {
+    hipLaunchKernelGGL(k_sstep_small, dim3(nmem), dim3(64), 0, st, a);
+}
+
 void cycle_small(const CycleArgs& a, int nmem, hipStream_t st) {
     hipLaunchKernelGGL(k_cycle_small, dim3(a.restart == 2 ? 1 : a.ns, nmem), dim3(64), 0, st, a);
 }

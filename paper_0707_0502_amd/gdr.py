@@ -49,7 +49,8 @@ class gdr_params(ctypes.Structure):
                 ("batch", ctypes.c_int), ("related_rhs", ctypes.c_int),
                 ("max_refine", ctypes.c_int), ("profile", ctypes.c_int),
                 ("m_clean", ctypes.c_int), ("proj_k", ctypes.c_int),
-                ("use_graph", ctypes.c_int), ("galerkin", ctypes.c_int)]
+                ("use_graph", ctypes.c_int), ("galerkin", ctypes.c_int),
+                ("sstep", ctypes.c_int)]
 
 
 class gdr_stats(ctypes.Structure):
