@@ -1,6 +1,7 @@
 // Host engine: handles behind the C-ABI and the solver drivers.
 #pragma once
 
+#include <list>
 #include <map>
 #include <new>
 #include <stdexcept>
@@ -29,11 +30,17 @@ namespace gdr {
 // Device memory cache of a context. Solves allocate their work buffers per
 // call; returning them here instead of to the driver lets the next call (or
 // the next batch of the same call) reuse them without mapping new memory.
-// Best fit within +25 % (sizes rounded up to 2 MiB); at most `cap` bytes are
-// kept idle; a failed allocation releases the idle blocks and retries once.
-// Blocks are only reused in stream order on the context's stream.
+// Best fit within +25 % (sizes rounded up to 2 MiB); at most `cap` bytes stay
+// idle, the least recently returned blocks going back to the driver first; a
+// failed allocation releases every idle block and retries once. Blocks are
+// only reused in stream order on the context's stream.
 struct DevPool {
-    std::multimap<size_t, void*> idle;
+    struct Idle {
+        size_t sz;
+        void* p;
+    };
+    std::list<Idle> lru;   // idle blocks, least recently returned first
+    std::multimap<size_t, std::list<Idle>::iterator> bysize;
     std::unordered_map<void*, size_t> used;
     size_t idle_bytes = 0;
     size_t cap = 0;
@@ -41,14 +48,20 @@ struct DevPool {
         const size_t g = b >= (1u << 20) ? (size_t)2 << 20 : (size_t)4 << 10;
         return (b + g - 1) / g * g;
     }
+    void drop(std::multimap<size_t, std::list<Idle>::iterator>::iterator it, bool to_driver) {
+        auto li = it->second;
+        idle_bytes -= li->sz;
+        if (to_driver) (void)hipFree(li->p);
+        lru.erase(li);
+        bysize.erase(it);
+    }
     void* get(size_t bytes) {
         bytes = round(bytes);
-        auto it = idle.lower_bound(bytes);
-        if (it != idle.end() && it->first <= bytes + bytes / 4) {
-            void* p = it->second;
+        auto it = bysize.lower_bound(bytes);
+        if (it != bysize.end() && it->first <= bytes + bytes / 4) {
+            void* p = it->second->p;
             used[p] = it->first;
-            idle_bytes -= it->first;
-            idle.erase(it);
+            drop(it, false);
             return p;
         }
         void* p = nullptr;
@@ -64,20 +77,31 @@ struct DevPool {
         return p;
     }
     void put(void* p) {
-        auto it = used.find(p);
-        if (it == used.end()) return;
-        const size_t sz = it->second;
-        used.erase(it);
-        if (idle_bytes + sz > cap) {
+        auto u = used.find(p);
+        if (u == used.end()) return;
+        const size_t sz = u->second;
+        used.erase(u);
+        if (sz > cap) {
             (void)hipFree(p);
             return;
         }
-        idle.emplace(sz, p);
+        lru.push_back({sz, p});
+        bysize.emplace(sz, std::prev(lru.end()));
         idle_bytes += sz;
+        while (idle_bytes > cap) {
+            auto oldest = lru.begin();
+            auto range = bysize.equal_range(oldest->sz);
+            for (auto it = range.first; it != range.second; ++it)
+                if (it->second == oldest) {
+                    drop(it, true);
+                    break;
+                }
+        }
     }
     void release() {
-        for (auto& kv : idle) (void)hipFree(kv.second);
-        idle.clear();
+        for (auto& b : lru) (void)hipFree(b.p);
+        lru.clear();
+        bysize.clear();
         idle_bytes = 0;
     }
 };
