@@ -240,7 +240,9 @@ struct Arnoldi {
             for (int pass = 1; pass <= 2; ++pass) {
                 prof->begin(GDR_K_GS_PROJECT);
                 blk_dot<T>(V, n, vms, nc, Z, n, vms, sb, partial, nblk, n, nmem, st, act);
-                prof->end(GDR_K_GS_PROJECT, dn * (nc + sb) * cs, dn * 16.0 * nc * sb);
+                // algorithmic bytes: columns 0..j and the block once each (the
+                // sweep reads the block twice, as basis columns and as inputs)
+                prof->end(GDR_K_GS_PROJECT, dn * nc * cs, dn * 16.0 * nc * sb);
                 reduce_cols(partial, nblk, sb * nc, Gb, BGS, nullptr, 0, nmem, st, act);
                 sa.mode = pass;
                 sstep_small(sa, nmem, st);
