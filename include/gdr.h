@@ -168,13 +168,19 @@ typedef struct {
                           the spectrum, block Gram-Schmidt twice and a Cholesky factor: four
                           sweeps per block). Same Krylov space and Arnoldi relation; the FP64
                           path always takes one vector per step. */
+    double sstep_reorth; /* s-step blocks: one projection and one update sweep per block unless
+                          the projection removed more than this ratio of a block vector's norm
+                          squared (its FP32 rounding would then leave components along the
+                          basis): then a second pair. 0: always two pairs. Default 20. */
 } gdr_params;
 
 /* kernel classes of the profiler (gdr_params.profile bit i = class i) */
 #define GDR_K_DSLASH 0      /* Wilson operator launches (solver and residuals) */
 #define GDR_K_GS_PROJECT 1  /* Gram-Schmidt projection sweep V^H [r_j, A r_j] */
 #define GDR_K_GS_UPDATE 2   /* Gram-Schmidt update sweep (finishes q_j, forms r_{j+1}) */
-#define GDR_K_GS_CLOSE 3    /* closing second pass of the last basis column */
+#define GDR_K_GS_CLOSE 3    /* second Gram-Schmidt passes: the closing pass of the last basis
+                               column (one vector per step), or the second block sweep pair of the
+                               s-step cycle, masked per member on the device (no bytes counted) */
 #define GDR_K_SMALL 4       /* device small dense problems */
 #define GDR_K_COMBINE 5     /* x_i += V d_i, r = V s */
 #define GDR_K_RECOMBINE 6   /* V_{k+1} = V_{m+1} P */
@@ -182,7 +188,7 @@ typedef struct {
 
 /* Fill defaults: m_dr 40, k 15, m_proj 40, tol 1e-8, tol_extra sqrt(tol),
  * max_cycles 1000, FP64, batch 1, related 0, max_refine 8, profile 0, m_clean 0,
- * proj_k 0, use_graph 0, galerkin 0, sstep 4. */
+ * proj_k 0, use_graph 0, galerkin 0, sstep 4, sstep_reorth 20. */
 void gdr_params_default(gdr_params* p);
 
 typedef struct {

@@ -60,6 +60,10 @@ bool check_params(gdr_ctx_s* c, const gdr_params* p, int ns, bool need_dr) {
         c->err = "need 0 <= sstep <= 4";
         return false;
     }
+    if (!(p->sstep_reorth >= 0)) {
+        c->err = "need sstep_reorth >= 0";
+        return false;
+    }
     if (!(p->tol > 0) || p->max_cycles < 1 || p->max_refine < 0) {
         c->err = "need tol > 0, max_cycles >= 1, max_refine >= 0";
         return false;
@@ -201,6 +205,7 @@ void gdr_params_default(gdr_params* p) {
     p->use_graph = 0;
     p->galerkin = 0;
     p->sstep = 4;
+    p->sstep_reorth = 20;
 }
 
 int gdr_wilson_create(gdr_ctx c, const int dims[4], const int bc[4], double kappa,

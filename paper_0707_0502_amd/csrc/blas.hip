@@ -313,7 +313,9 @@ void gs_update(const typename CT<T>::t* V, int64_t ldv, int64_t v_ms, int nc,
 // Block Gram-Schmidt sweeps of the s-step Arnoldi cycle: the same row
 // partition and reductions as the DCGS2 sweeps, with NX (<= BLK_MAX) block
 // vectors X_a = X + a*ldx in place of r_j and w.
-template <typename T, int NX, int R>
+// SECOND: the conditional second sweep pair of the s-step cycle (the same
+// code under its own name, so that profiles keep the two pairs apart)
+template <typename T, int NX, int R, bool SECOND>
 __global__ __launch_bounds__(256) void k_blk_dot(
     const typename CT<T>::t* __restrict__ V, int64_t ldv, int64_t v_ms, int nc,
     const typename CT<T>::t* __restrict__ X, int64_t ldx, int64_t x_ms,
@@ -370,7 +372,7 @@ __global__ __launch_bounds__(256) void k_blk_dot(
     }
 }
 
-template <typename T, int NB, int R>
+template <typename T, int NB, int R, bool SECOND>
 __global__ __launch_bounds__(256) void k_blk_update(
     const typename CT<T>::t* __restrict__ V, int64_t ldv, int64_t v_ms, int nc,
     typename CT<T>::t* X, int64_t ldx, int64_t x_ms, const double2* __restrict__ coef,
@@ -434,13 +436,19 @@ __global__ __launch_bounds__(256) void k_blk_update(
 template <typename T>
 void blk_dot(const typename CT<T>::t* V, int64_t ldv, int64_t v_ms, int nc,
              const typename CT<T>::t* X, int64_t ldx, int64_t x_ms, int nx, double2* partial,
-             int nblk, int64_t n, int nmem, hipStream_t st, const int* act) {
+             int nblk, int64_t n, int nmem, hipStream_t st, const int* act, bool second) {
     dim3 grid(nblk, nmem), blk(256);
     constexpr bool f32 = std::is_same<T, float>::value;
     const bool r2 = f32 && pairable(n, {ldv, v_ms, ldx, x_ms}, {V, X});
-#define BLK_DOT(NX, R)                                                                              \
-    hipLaunchKernelGGL((k_blk_dot<T, NX, R>), grid, blk, 0, st, V, ldv, v_ms, nc, X, ldx, x_ms, \
-                       partial, nblk, n, act)
+#define BLK_DOT(NX, R)                                                                          \
+    do {                                                                                        \
+        if (second)                                                                             \
+            hipLaunchKernelGGL((k_blk_dot<T, NX, R, true>), grid, blk, 0, st, V, ldv, v_ms, nc, X, \
+                               ldx, x_ms, partial, nblk, n, act);                               \
+        else                                                                                    \
+            hipLaunchKernelGGL((k_blk_dot<T, NX, R, false>), grid, blk, 0, st, V, ldv, v_ms, nc, \
+                               X, ldx, x_ms, partial, nblk, n, act);                            \
+    } while (0)
 #define BLK_DOT_R(R)          \
     switch (nx) {             \
         case 1: BLK_DOT(1, R); break; \
@@ -460,13 +468,19 @@ void blk_dot(const typename CT<T>::t* V, int64_t ldv, int64_t v_ms, int nc,
 template <typename T>
 void blk_update(const typename CT<T>::t* V, int64_t ldv, int64_t v_ms, int nc,
                 typename CT<T>::t* X, int64_t ldx, int64_t x_ms, int nx, const double2* coef,
-                int64_t coef_ms, int64_t n, int nmem, hipStream_t st, const int* act) {
+                int64_t coef_ms, int64_t n, int nmem, hipStream_t st, const int* act, bool second) {
     constexpr bool f32 = std::is_same<T, float>::value;
     dim3 grid(cgs_nblk(n, nmem, f32), nmem), blk(256);
     const bool r2 = f32 && pairable(n, {ldv, v_ms, ldx, x_ms}, {V, X});
-#define BLK_UPD(NB, R)                                                                             \
-    hipLaunchKernelGGL((k_blk_update<T, NB, R>), grid, blk, 0, st, V, ldv, v_ms, nc, X, ldx, x_ms, \
-                       coef, coef_ms, n, act)
+#define BLK_UPD(NB, R)                                                                         \
+    do {                                                                                       \
+        if (second)                                                                            \
+            hipLaunchKernelGGL((k_blk_update<T, NB, R, true>), grid, blk, 0, st, V, ldv, v_ms, nc, \
+                               X, ldx, x_ms, coef, coef_ms, n, act);                           \
+        else                                                                                   \
+            hipLaunchKernelGGL((k_blk_update<T, NB, R, false>), grid, blk, 0, st, V, ldv, v_ms, \
+                               nc, X, ldx, x_ms, coef, coef_ms, n, act);                       \
+    } while (0)
 #define BLK_UPD_R(R)          \
     switch (nx) {             \
         case 1: BLK_UPD(1, R); break; \
@@ -484,15 +498,16 @@ void blk_update(const typename CT<T>::t* V, int64_t ldv, int64_t v_ms, int nc,
 }
 
 template void blk_dot<float>(const float2*, int64_t, int64_t, int, const float2*, int64_t, int64_t,
-                             int, double2*, int, int64_t, int, hipStream_t, const int*);
+                             int, double2*, int, int64_t, int, hipStream_t, const int*, bool);
 template void blk_dot<double>(const double2*, int64_t, int64_t, int, const double2*, int64_t,
-                              int64_t, int, double2*, int, int64_t, int, hipStream_t, const int*);
+                              int64_t, int, double2*, int, int64_t, int, hipStream_t, const int*,
+                              bool);
 template void blk_update<float>(const float2*, int64_t, int64_t, int, float2*, int64_t, int64_t,
                                 int, const double2*, int64_t, int64_t, int, hipStream_t,
-                                const int*);
+                                const int*, bool);
 template void blk_update<double>(const double2*, int64_t, int64_t, int, double2*, int64_t,
                                  int64_t, int, const double2*, int64_t, int64_t, int, hipStream_t,
-                                 const int*);
+                                 const int*, bool);
 
 template void gs_dot<float, float>(const float2*, int64_t, int64_t, int, const float2*, int64_t,
                                    const float2*, int64_t, double2*, int, int64_t, int,

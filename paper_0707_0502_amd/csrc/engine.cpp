@@ -156,6 +156,8 @@ struct Arnoldi {
     double2* Psave = nullptr;
     double* znorm = nullptr;
     double2* bcoef = nullptr;
+    int* reo = nullptr;         // per member: the block needs its second sweep pair
+    double reorth = 20;
     DiagList dlp{};
 
     void init(DMem& mem, gdr_op_s* op_, int m_, int nmem_, C* Vbuf, int64_t vms_) {
@@ -178,6 +180,7 @@ struct Arnoldi {
         Psave = mem.get<double2>((size_t)(MAXM + 1) * BLK_MAX * nmem);
         znorm = mem.get<double>((size_t)BLK_MAX * nmem);
         bcoef = mem.get<double2>((size_t)BLK_COEF_MS * nmem);
+        reo = mem.get<int>(nmem);
         G = mem.get<double2>((size_t)GMS * nmem);
         coef = mem.get<double2>((size_t)GS_COEF_MS * nmem);
         ref = mem.get<double>(nmem);
@@ -191,15 +194,21 @@ struct Arnoldi {
     }
 
     // Block size of the cycle: s-step blocks only for the FP32 basis
-    void set_block(int s) { sblk = (std::is_same<T, float>::value && s >= 2) ? std::min(s, BLK_MAX) : 0; }
+    void set_block(int s, double reorth_ = 20) {
+        sblk = (std::is_same<T, float>::value && s >= 2) ? std::min(s, BLK_MAX) : 0;
+        reorth = reorth_;
+    }
 
     // s-step cycle: from the orthonormal column j, sb = min(sblk, m - j) powers
-    // z_i = (A - c) z_{i-1} / r go straight into columns j+1..j+sb; two block
-    // Gram-Schmidt passes against columns 0..j (projection sweep, update sweep,
-    // each twice; the second projection also forms the block's Gram matrix)
-    // and the Cholesky factor of the twice-projected block give the new
-    // orthonormal columns, and H columns j..j+sb-1 follow from the change of
-    // basis (sstep_small). Four sweeps over the basis per block of sb steps.
+    // z_i = (A - c) z_{i-1} / r go straight into columns j+1..j+sb. One block
+    // projection sweep against columns 0..j (its basis range also takes in the
+    // block, giving the block's Gram matrix), the Cholesky factor of the
+    // Gram matrix with the projection removed, and one update sweep give the
+    // new orthonormal columns; a member whose projection cancelled more than
+    // the reorth ratio of a block vector takes a second projection and update
+    // sweep (kernels masked by reo). H columns j..j+sb-1 follow from the
+    // change of basis (sstep_small). Two sweeps over the basis per block of
+    // sb steps, four with the second pair.
     void blocks(int j0, const int* act, int nact) {
         const double cs = sizeof(C);
         const double dn = (double)n * nact;
@@ -236,19 +245,31 @@ struct Arnoldi {
             sa.theta = op->spec_c;
             sa.rho = op->spec_r;
             sa.brk = brk;
-            sa.act = act;
+            sa.reorth = reorth;
+            fill_int(reo, 0, nmem, st);
             for (int pass = 1; pass <= 2; ++pass) {
-                prof->begin(GDR_K_GS_PROJECT);
-                blk_dot<T>(V, n, vms, nc, Z, n, vms, sb, partial, nblk, n, nmem, st, act);
+                // the second pair only for the members mode 1 flagged; which
+                // ones is decided on the device, so its launches are timed in
+                // their own class without algorithmic bytes
+                const bool second = pass == 2;
+                const int* msk = second ? reo : act;
+                const int kp = second ? GDR_K_GS_CLOSE : GDR_K_GS_PROJECT;
+                const int ku = second ? GDR_K_GS_CLOSE : GDR_K_GS_UPDATE;
+                prof->begin(kp);
+                blk_dot<T>(V, n, vms, nc, Z, n, vms, sb, partial, nblk, n, nmem, st, msk, second);
                 // algorithmic bytes: columns 0..j and the block once each (the
                 // sweep reads the block twice, as basis columns and as inputs)
-                prof->end(GDR_K_GS_PROJECT, dn * nc * cs, dn * 16.0 * nc * sb);
-                reduce_cols(partial, nblk, sb * nc, Gb, BGS, nullptr, 0, nmem, st, act);
+                prof->end(kp, second ? 0.0 : dn * nc * cs, second ? 0.0 : dn * 16.0 * nc * sb);
+                reduce_cols(partial, nblk, sb * nc, Gb, BGS, nullptr, 0, nmem, st, msk);
                 sa.mode = pass;
+                sa.act = msk;
+                sa.reo = second ? nullptr : reo;
                 sstep_small(sa, nmem, st);
-                prof->begin(GDR_K_GS_UPDATE);
-                blk_update<T>(V, n, vms, j + 1, Z, n, vms, sb, bcoef, BLK_COEF_MS, n, nmem, st, act);
-                prof->end(GDR_K_GS_UPDATE, dn * (j + 1 + 2.0 * sb) * cs, dn * 16.0 * (j + 1 + sb) * sb);
+                prof->begin(ku);
+                blk_update<T>(V, n, vms, j + 1, Z, n, vms, sb, bcoef, BLK_COEF_MS, n, nmem, st, msk,
+                              second);
+                prof->end(ku, second ? 0.0 : dn * (j + 1 + 2.0 * sb) * cs,
+                          second ? 0.0 : dn * 16.0 * (j + 1 + sb) * sb);
             }
             j += sb;
         }
@@ -384,7 +405,7 @@ static int dr_run(gdr_op_s* op, int ns, const double2* sig_h, const double2* b_e
     Arnoldi<T> A;
     A.init(mem, op, m, 1, Va, 0);
     A.use_graph = p.use_graph != 0;
-    A.set_block(p.sstep);
+    A.set_block(p.sstep, p.sstep_reorth);
     A.prof = &S.prof;
     double2* Hn = mem.get<double2>((size_t)(m + 1) * m);
     double2* c0 = mem.get<double2>(m + 1);
@@ -602,7 +623,8 @@ static void proj_run(gdr_op_s* op, gdr_defl_s* defl, int nmem, int ns,
                      const std::vector<double2>& sig_h, const double2* Bm, double2* W,
                      const std::vector<double>& tol, const std::vector<double>& bnorm, int m,
                      int max_cycles, Stats& S, const std::vector<int>& phase, ProjResult& R,
-                     bool start = false, int kp = 0, bool graph = false, int sblk = 0) {
+                     bool start = false, int kp = 0, bool graph = false, int sblk = 0,
+                     double reorth = 20) {
     // kp > 0: project over the leading kp deflation vectors only (the
     // accurate-eigenvector variant, Table 4.1); otherwise over all k.
     // graph: replay the Arnoldi cycle from a captured HIP graph
@@ -621,7 +643,7 @@ static void proj_run(gdr_op_s* op, gdr_defl_s* defl, int nmem, int ns,
     Arnoldi<T> A;
     A.init(mem, op, m, nmem, Vb, vms);
     A.use_graph = graph;
-    A.set_block(sblk);
+    A.set_block(sblk, reorth);
     A.prof = &S.prof;
     double2* sig = mem.get<double2>((size_t)nmem * ns);
     double2* Cb = mem.get<double2>((size_t)80 * nmem);
@@ -995,7 +1017,7 @@ static int proj_batch(gdr_op_s* op, gdr_defl_s* d, int ns, const double2* sig_h,
                                    nsolved, ids, Bm, W, st);
         if (d->prec == GDR_PREC_MIXED)
             proj_run<float>(op, d, nmem, ns, sgm, Bm, W, tol, bnorm, m, p.max_cycles, S, phase, R,
-                            related, kp, p.use_graph != 0, p.sstep);
+                            related, kp, p.use_graph != 0, p.sstep, p.sstep_reorth);
         else
             proj_run<double>(op, d, nmem, ns, sgm, Bm, W, tol, bnorm, m, p.max_cycles, S, phase, R,
                              related, kp, p.use_graph != 0);
@@ -1175,7 +1197,7 @@ int cleanup(gdr_op_s* op, gdr_defl_s* defl, int ns, const double2* sig, int nrhs
                                  false, 0, p.use_graph != 0);
             else
                 proj_run<float>(op, defl, nmem, 1, sgm, Bm, W, tol, bnorm, mc, p.max_cycles, S, phase, Rr,
-                                false, 0, p.use_graph != 0, p.sstep);
+                                false, 0, p.use_graph != 0, p.sstep, p.sstep_reorth);
             for (int b = 0; b < nmem; ++b) {
                 const Pair& q = todo[pos + b];
                 axpy_dev(X_eo + ((int64_t)q.j * ns + q.i) * n, 0, W + (int64_t)b * 2 * n, 0,

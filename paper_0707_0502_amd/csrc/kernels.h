@@ -73,11 +73,13 @@ void gs_update(const typename CT<T>::t* V, int64_t ldv, int64_t v_ms, int nc,
 template <typename T>
 void blk_dot(const typename CT<T>::t* V, int64_t ldv, int64_t v_ms, int nc,
              const typename CT<T>::t* X, int64_t ldx, int64_t x_ms, int nx, double2* partial,
-             int nblk, int64_t n, int nmem, hipStream_t st, const int* act = nullptr);
+             int nblk, int64_t n, int nmem, hipStream_t st, const int* act = nullptr,
+             bool second = false);
 template <typename T>
 void blk_update(const typename CT<T>::t* V, int64_t ldv, int64_t v_ms, int nc,
                 typename CT<T>::t* X, int64_t ldx, int64_t x_ms, int nx, const double2* coef,
-                int64_t coef_ms, int64_t n, int nmem, hipStream_t st, const int* act = nullptr);
+                int64_t coef_ms, int64_t n, int nmem, hipStream_t st, const int* act = nullptr,
+                bool second = false);
 // DCGS2 bookkeeping of step j (see blas.hip): H corrections, next H column and
 // the update coefficients, breakdown flag.
 void dcgs_coef(const double2* G, int64_t g_ms, int j, int nx, int first, double2* H, int64_t ldh,

@@ -69,12 +69,16 @@ struct ProjArgs {
 // (columns j+1..j+sb) holds z_i = (A - theta) z_{i-1} / rho with z_0 = v_j.
 // G holds the reduced sums [V_{0..j}, Z]^H Z of the sweep just made (value
 // a*nc + c, nc = j+1+sb).
-//   mode 1 (after the first projection): keep P1 = V_{0..j}^H Z and the raw
-//     norms ||z_a||^2; coefficients of Z' = Z - V_{0..j} P1.
-//   mode 2 (after the second projection, Z'): P2 = V_{0..j}^H Z', the Cholesky
-//     factor R of Z'^H Z' - P2^H P2 (Z'' = Q R); coefficients of
-//     Q = (Z' - V_{0..j} P2) R^{-1}; H columns j..j+sb-1 from
-//     A Zhat = Z diag(rho) + Zhat diag(theta) in the basis [V_{0..j}, Q].
+//   mode 1 (after the first projection): P1 = V_{0..j}^H Z, the raw norms
+//     ||z_a||^2 and the Gram matrix Z^H Z - P1^H P1 of Z - V P1. If every
+//     pivot keeps more than 1/reorth of its raw norm (reorth > 0), this sweep
+//     suffices: as mode 2 with P2 = P1 and Z' = Z, reo[b] = 0. Otherwise the
+//     coefficients of Z' = Z - V_{0..j} P1 and reo[b] = 1.
+//   mode 2 (after the second projection, Z'; members with reo set): P2 =
+//     V_{0..j}^H Z', the Cholesky factor R of Z'^H Z' - P2^H P2 (Z'' = Q R);
+//     coefficients of Q = (Z' - V_{0..j} P2) R^{-1}; H columns j..j+sb-1 from
+//     A Zhat = Z diag(rho) + Zhat diag(theta) in the basis [V_{0..j}, Q]
+//     with C-hat = P1 + P2.
 // A pivot below 1e-10 of the raw ||z_a||^2 is a breakdown (the Krylov space
 // is invariant): brk = j + a, the later block vectors are zero.
 struct SstepArgs {
@@ -92,6 +96,8 @@ struct SstepArgs {
     double rho;
     int* brk;
     const int* act;
+    double reorth;    // cancellation ratio above which a block gets a second sweep pair
+    int* reo;         // per member: second sweep pair needed (mode 1 writes it)
 };
 void sstep_small(const SstepArgs& a, int nmem, hipStream_t st);
 

@@ -644,36 +644,32 @@ __global__ __launch_bounds__(64) void k_sstep_small(SstepArgs a) {
     double* zn = a.znorm + b * BLK_MAX;
     double2* coef = a.coef + b * a.coef_ms;
     double2* beta = coef + BLK_MAX * (MAXM + 1);
-    if (a.mode == 1) {
-        for (int t = lane; t < (j + 1) * sb; t += 64) {
-            const int c = t / sb, q = t % sb;
-            const double2 p = G[q * nc + c];
-            Ps[c * BLK_MAX + q] = p;
-            coef[q * (MAXM + 1) + c] = p;
-        }
-        if (lane < sb) zn[lane] = G[lane * nc + j + 1 + lane].x;
-        if (lane < BLK_MAX * BLK_MAX) beta[lane] = mk((lane / BLK_MAX) == (lane % BLK_MAX) ? 1.0 : 0.0, 0);
-        return;
-    }
-    __shared__ double2 P2[(MAXM + 1) * BLK_MAX];
-    __shared__ double2 Ch[(MAXM + 1) * BLK_MAX];
+    __shared__ double2 Pc[(MAXM + 1) * BLK_MAX];  // projection of this sweep
+    __shared__ double2 Ch[(MAXM + 1) * BLK_MAX];  // total projection C-hat
     __shared__ double2 G2[BLK_MAX * BLK_MAX];
     __shared__ double2 R[BLK_MAX * BLK_MAX];      // R[l*BLK_MAX + c], upper
     __shared__ double2 Ri[BLK_MAX * BLK_MAX];     // inverse of the leading nq x nq block
-    __shared__ int sh_fi;
+    __shared__ int sh_fi, sh_two;
     for (int t = lane; t < (j + 1) * BLK_MAX; t += 64) {
         const int c = t / BLK_MAX, q = t % BLK_MAX;
         const double2 p = q < sb ? G[q * nc + c] : mk(0, 0);
-        P2[t] = p;
-        Ch[t] = q < sb ? cadd(Ps[t], p) : mk(0, 0);
+        Pc[t] = p;
+        if (a.mode == 1) {
+            Ps[t] = p;
+            Ch[t] = p;
+        } else {
+            Ch[t] = q < sb ? cadd(Ps[t], p) : mk(0, 0);
+        }
     }
+    if (a.mode == 1 && lane < sb) zn[lane] = G[lane * nc + j + 1 + lane].x;
     __syncthreads();
-    // G2 = Z'^H Z' - P2^H P2
+    // Gram of the block with the V components of this sweep removed:
+    // G2 = X^H X - Pc^H Pc (X = Z after the first sweep, Z' after the second)
     for (int e = 0; e < sb * sb; ++e) {
-        const int r = e / sb, q = e % sb;   // G2[r][q] = z'_r^H z'_q - sum_c conj(P2[c][r]) P2[c][q]
+        const int r = e / sb, q = e % sb;
         double sx = 0, sy = 0;
         for (int c = lane; c <= j; c += 64) {
-            const double2 v = cjmul(P2[c * BLK_MAX + r], P2[c * BLK_MAX + q]);
+            const double2 v = cjmul(Pc[c * BLK_MAX + r], Pc[c * BLK_MAX + q]);
             sx += v.x;
             sy += v.y;
         }
@@ -682,6 +678,30 @@ __global__ __launch_bounds__(64) void k_sstep_small(SstepArgs a) {
         if (lane == 0) G2[r * BLK_MAX + q] = csub(G[q * nc + j + 1 + r], mk(sx, sy));
     }
     __syncthreads();
+    if (lane == 0) {
+        // one sweep suffices unless the projection cancelled much of a block
+        // vector (its stored FP32 rounding then leaves V components behind)
+        int two = 0;
+        if (a.mode == 1) {
+            for (int i = 0; i < sb; ++i) {
+                const double g = G2[i * BLK_MAX + i].x;
+                if (!(g > 0) || !(g * a.reorth > zn[i])) two = 1;
+            }
+            if (a.reorth <= 0) two = 1;
+        }
+        sh_two = two;
+        if (a.reo) a.reo[b] = two;
+    }
+    __syncthreads();
+    if (sh_two) {
+        // intermediate update Z' = Z - V_{0..j} P1; the second sweep finishes
+        for (int t = lane; t < (j + 1) * sb; t += 64) {
+            const int c = t / sb, q = t % sb;
+            coef[q * (MAXM + 1) + c] = Pc[c * BLK_MAX + q];
+        }
+        if (lane < BLK_MAX * BLK_MAX) beta[lane] = mk((lane / BLK_MAX) == (lane % BLK_MAX) ? 1.0 : 0.0, 0);
+        return;
+    }
     if (lane == 0) {
         int fi = -1;
         for (int t = 0; t < BLK_MAX * BLK_MAX; ++t) {
@@ -726,7 +746,7 @@ __global__ __launch_bounds__(64) void k_sstep_small(SstepArgs a) {
     const int fi = sh_fi;
     const int nq = fi >= 0 ? fi : sb;           // new orthonormal columns
     const int bs = fi >= 0 ? fi + 1 : sb;       // H columns produced by this block
-    // final update: q_o = sum_a z'_a Ri[a][o] - sum_c v_c (P2 Ri)[c][o]
+    // final update: q_o = sum_a x_a Ri[a][o] - sum_c v_c (Pc Ri)[c][o]
     for (int t = lane; t < BLK_MAX * BLK_MAX; t += 64) {
         const int o = t / BLK_MAX, q = t % BLK_MAX;
         beta[t] = (o < nq && q < nq) ? Ri[q * BLK_MAX + o] : mk(0, 0);
@@ -735,7 +755,7 @@ __global__ __launch_bounds__(64) void k_sstep_small(SstepArgs a) {
         const int c = t / BLK_MAX, o = t % BLK_MAX;
         double2 v = mk(0, 0);
         if (o < nq)
-            for (int q = 0; q <= o; ++q) v = cadd(v, cmul(P2[c * BLK_MAX + q], Ri[q * BLK_MAX + o]));
+            for (int q = 0; q <= o; ++q) v = cadd(v, cmul(Pc[c * BLK_MAX + q], Ri[q * BLK_MAX + o]));
         coef[o * (MAXM + 1) + c] = v;
     }
     // H columns j..j+bs-1 (rows 0..m), by rows across the lanes

@@ -37,8 +37,9 @@ def relation(gdr, op, defl, mv_host, n):
     return rel, orth
 
 
+@pytest.mark.parametrize("reorth", [20.0, 0.0])
 @pytest.mark.parametrize("sstep", [1, 2, 3, 4])
-def test_arnoldi_relation_bidiagonal(sstep):
+def test_arnoldi_relation_bidiagonal(sstep, reorth):
     from paper_0707_0502_amd import gdr
     op, mv = bidiag_op()
     b = np.random.default_rng(5).standard_normal(1000) + 0j
@@ -46,9 +47,9 @@ def test_arnoldi_relation_bidiagonal(sstep):
     x = empty(3 * 1000)
     st = gdr.Stats(1, 3)
     p = gdr.gdr_params_default(m_dr=25, k=10, tol=1e-6, max_cycles=2, precision=gdr.GDR_PREC_MIXED,
-                               sstep=sstep)
+                               sstep=sstep, sstep_reorth=reorth)
     rc, defl = gdr.gdr_solve_dr_sh(op, sig, dev(b), x, p, st)
-    say("sstep", sstep, "rc", rc, "hist", st.hist[:, 3])
+    say("sstep", sstep, "reorth", reorth, "rc", rc, "hist", st.hist[:, 3])
     assert defl is not None
     rel, orth = relation(gdr, op, defl, mv, 1000)
     say("  A V_k - V_{k+1} H_k rel %.3e, orthonormality %.3e" % (rel, orth))
@@ -57,8 +58,9 @@ def test_arnoldi_relation_bidiagonal(sstep):
     gdr.gdr_op_destroy(op)
 
 
+@pytest.mark.parametrize("reorth", [20.0, 0.0])
 @pytest.mark.parametrize("sstep", [1, 4])
-def test_arnoldi_relation_wilson(sstep):
+def test_arnoldi_relation_wilson(sstep, reorth):
     from paper_0707_0502_amd import gdr
     cfg, links, kappa, B = config_data("C1")
     A = wilson.WilsonOperator(links, kappa)
@@ -68,9 +70,9 @@ def test_arnoldi_relation_wilson(sstep):
     x = empty(len(sig) * n)
     st = gdr.Stats(1, len(sig))
     p = gdr.gdr_params_default(m_dr=cfg["m_dr"], k=cfg["k"], tol=1e-6, max_cycles=2,
-                               precision=gdr.GDR_PREC_MIXED, sstep=sstep)
+                               precision=gdr.GDR_PREC_MIXED, sstep=sstep, sstep_reorth=reorth)
     rc, defl = gdr.gdr_solve_dr_sh(op, sig, dev(B[0]), x, p, st)
-    say("sstep", sstep, "rc", rc, "hist", st.hist[:, 3])
+    say("sstep", sstep, "reorth", reorth, "rc", rc, "hist", st.hist[:, 3])
     assert defl is not None
     rel, orth = relation(gdr, op, defl, A, n)
     say("  A V_k - V_{k+1} H_k rel %.3e, orthonormality %.3e" % (rel, orth))
