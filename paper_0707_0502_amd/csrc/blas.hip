@@ -449,8 +449,8 @@ void blk_dot(const typename CT<T>::t* V, int64_t ldv, int64_t v_ms, int nc,
             hipLaunchKernelGGL((k_blk_dot<T, NX, R, false>), grid, blk, 0, st, V, ldv, v_ms, nc, \
                                X, ldx, x_ms, partial, nblk, n, act);                            \
     } while (0)
-#define BLK_DOT_R(R)          \
-    switch (nx) {             \
+#define BLK_DOT_R(R)                  \
+    switch (nx) {                     \
         case 1: BLK_DOT(1, R); break; \
         case 2: BLK_DOT(2, R); break; \
         case 3: BLK_DOT(3, R); break; \
@@ -481,8 +481,8 @@ void blk_update(const typename CT<T>::t* V, int64_t ldv, int64_t v_ms, int nc,
             hipLaunchKernelGGL((k_blk_update<T, NB, R, false>), grid, blk, 0, st, V, ldv, v_ms, \
                                nc, X, ldx, x_ms, coef, coef_ms, n, act);                       \
     } while (0)
-#define BLK_UPD_R(R)          \
-    switch (nx) {             \
+#define BLK_UPD_R(R)                  \
+    switch (nx) {                     \
         case 1: BLK_UPD(1, R); break; \
         case 2: BLK_UPD(2, R); break; \
         case 3: BLK_UPD(3, R); break; \
@@ -499,15 +499,10 @@ void blk_update(const typename CT<T>::t* V, int64_t ldv, int64_t v_ms, int nc,
 
 template void blk_dot<float>(const float2*, int64_t, int64_t, int, const float2*, int64_t, int64_t,
                              int, double2*, int, int64_t, int, hipStream_t, const int*, bool);
-template void blk_dot<double>(const double2*, int64_t, int64_t, int, const double2*, int64_t,
-                              int64_t, int, double2*, int, int64_t, int, hipStream_t, const int*,
-                              bool);
 template void blk_update<float>(const float2*, int64_t, int64_t, int, float2*, int64_t, int64_t,
                                 int, const double2*, int64_t, int64_t, int, hipStream_t,
                                 const int*, bool);
-template void blk_update<double>(const double2*, int64_t, int64_t, int, double2*, int64_t,
-                                 int64_t, int, const double2*, int64_t, int64_t, int, hipStream_t,
-                                 const int*, bool);
+
 
 template void gs_dot<float, float>(const float2*, int64_t, int64_t, int, const float2*, int64_t,
                                    const float2*, int64_t, double2*, int, int64_t, int,

@@ -319,9 +319,11 @@ struct Arnoldi {
 
     void body(int j0, const int* act, int nact) {
         fill_int(brk, -1, nmem, st);
-        if (sblk >= 2) {
-            blocks(j0, act, nact);
-            return;
+        if constexpr (std::is_same<T, float>::value) {
+            if (sblk >= 2) {
+                blocks(j0, act, nact);
+                return;
+            }
         }
         for (int j = j0; j < m; ++j) step(j, j0, act, nact);
         close(act, nact);
