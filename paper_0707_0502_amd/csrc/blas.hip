@@ -741,13 +741,15 @@ void fill_int(int* p, int v, int n, hipStream_t st) {
 // out_s = keep_s * out_s + sum_l V_l coef[l + s*ldc]
 constexpr int VC_MAXOUT = MAXNS + 2;
 
-template <typename T>
+template <typename T, int R, int MO>
 __global__ __launch_bounds__(256) void k_vcombine(const typename CT<T>::t* __restrict__ V,
                                                   int64_t ldv, int64_t v_ms, int ncols,
                                                   const double2* __restrict__ coef, int ldc,
                                                   int64_t c_ms, int nout, double2* __restrict__ out,
                                                   int64_t o_stride, int64_t o_ms, unsigned keep,
                                                   int64_t n, const int* __restrict__ act) {
+    using IO = RowIO<T, R>;
+    constexpr int CH = 8;   // basis columns loaded per batch (loads in flight per lane)
     const int b = blockIdx.y;
     if (act && !act[b]) return;
     V += b * v_ms;
@@ -759,23 +761,40 @@ __global__ __launch_bounds__(256) void k_vcombine(const typename CT<T>::t* __res
         cs[t] = coef[l + s * ldc];
     }
     __syncthreads();
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        double2 acc[VC_MAXOUT];
+    for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * R; i < n;
+         i += (int64_t)gridDim.x * blockDim.x * R) {
+        double2 acc[MO][R];
 #pragma unroll
-        for (int s = 0; s < VC_MAXOUT; ++s) acc[s] = mk(0, 0);
-        for (int l = 0; l < ncols; ++l) {
-            double2 v = to_d(V[l * ldv + i]);
+        for (int s = 0; s < MO; ++s)
 #pragma unroll
-            for (int s = 0; s < VC_MAXOUT; ++s)
-                if (s < nout) acc[s] = cadd(acc[s], cmul(v, cs[l + s * ncols]));
+            for (int r = 0; r < R; ++r) acc[s][r] = mk(0, 0);
+        for (int l0 = 0; l0 < ncols; l0 += CH) {
+            typename IO::V vr[CH];
+#pragma unroll
+            for (int c = 0; c < CH; ++c)
+                if (l0 + c < ncols) vr[c] = IO::ldnt(V + (int64_t)(l0 + c) * ldv + i);
+#pragma unroll
+            for (int c = 0; c < CH; ++c)
+                if (l0 + c < ncols) {
+                    double2 v[R];
+                    IO::get(vr[c], v);
+#pragma unroll
+                    for (int s = 0; s < MO; ++s)
+                        if (s < nout) {
+                            const double2 w = cs[l0 + c + s * ncols];
+#pragma unroll
+                            for (int r = 0; r < R; ++r) acc[s][r] = cadd(acc[s][r], cmul(v[r], w));
+                        }
+                }
         }
 #pragma unroll
-        for (int s = 0; s < VC_MAXOUT; ++s)
-            if (s < nout) {
-                double2* o = out + s * o_stride + i;
-                *o = ((keep >> s) & 1u) ? cadd(*o, acc[s]) : acc[s];
-            }
+        for (int s = 0; s < MO; ++s)
+            if (s < nout)
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    double2* o = out + s * o_stride + i + r;
+                    *o = ((keep >> s) & 1u) ? cadd(*o, acc[s][r]) : acc[s][r];
+                }
     }
 }
 
@@ -784,10 +803,25 @@ void vcombine(const typename CT<T>::t* V, int64_t ldv, int64_t v_mstride, int nc
               const double2* coef, int ldc, int64_t c_mstride, int nout, double2* out,
               int64_t o_stride, int64_t o_mstride, unsigned keep_mask, int64_t n, int nmem,
               hipStream_t st, const int* act) {
-    hipLaunchKernelGGL(k_vcombine<T>, dim3(vec_grid(n), nmem), dim3(256), 0, st, V, ldv,
-                       v_mstride, ncols, coef, ldc, c_mstride, nout, out, o_stride, o_mstride,
-                       keep_mask, n, act);
+    constexpr bool f32 = std::is_same<T, float>::value;
+    const bool r2 = f32 && pairable(n, {ldv, v_mstride}, {V});
+    const dim3 grid(vec_grid(n), nmem), blk(256);
+#define VCOMB(R, MO)                                                                            \
+    hipLaunchKernelGGL((k_vcombine<T, R, MO>), grid, blk, 0, st, V, ldv, v_mstride, ncols, coef, \
+                       ldc, c_mstride, nout, out, o_stride, o_mstride, keep_mask, n, act)
+    // accumulators sized for the outputs at hand (r = V s and up to 16 shifts)
+    if (r2) {
+        if (nout <= 4) VCOMB(f32 ? 2 : 1, 4);
+        else if (nout <= 8) VCOMB(f32 ? 2 : 1, 8);
+        else VCOMB(1, VC_MAXOUT);
+    } else {
+        if (nout <= 4) VCOMB(1, 4);
+        else if (nout <= 8) VCOMB(1, 8);
+        else VCOMB(1, VC_MAXOUT);
+    }
+#undef VCOMB
 }
+
 template void vcombine<double>(const double2*, int64_t, int64_t, int, const double2*, int, int64_t,
                                int, double2*, int64_t, int64_t, unsigned, int64_t, int,
                                hipStream_t, const int*);
