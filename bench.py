@@ -171,6 +171,92 @@ def operator_timings(a, gdr, synth, ctx, op, dims, kappa, links, n):
     return dsl
 
 
+def uneven_batch(a, gdr, synth, torch, np):
+    """The uneven mixed batch: one 32^3x64 lattice with FP16-stored links
+    (8 shifts, 4 Z4 RHS) solved concurrently with six 12^4 and four 16^4
+    lattices (4 shifts, 2 RHS), each lattice on its own context and stream
+    and a host thread of its own, Arnoldi cycles replayed from HIP graphs.
+    value: wall time of the whole batch divided by its 24 right-hand sides;
+    the same batch in plain FP64 (also concurrent) is timed first."""
+    import threading
+    runs = []
+    for name in synth.C5_GROUP:
+        cfg = synth.CONFIGS[name]
+        links = synth.gauge_links(cfg["dims"], cfg["eps"], cfg["seed"])
+        B = np.stack([synth.make_rhs(cfg, kd, sd).ravel() for kd, sd in cfg["rhs"]])
+        stream = torch.cuda.Stream()
+        ctx = gdr.gdr_ctx_create(0, stream.cuda_stream)
+        lst = gdr.GDR_LINKS_F16 if cfg.get("links") == "f16" else gdr.GDR_LINKS_F32
+        op = gdr.gdr_wilson_create(ctx, cfg["dims"], (1, 1, 1, -1), synth.kappa(name), links, lst)
+        with torch.cuda.stream(stream):
+            Bd = torch.from_numpy(B.ravel()).cuda()
+            X = torch.zeros(len(cfg["rhs"]) * len(cfg["sigmas"]) * op.n, dtype=torch.complex128,
+                            device="cuda")
+        stream.synchronize()
+        runs.append(dict(name=name, cfg=cfg, op=op, ctx=ctx, stream=stream, Bd=Bd, X=X))
+        log("bench: ready", name, cfg["dims"])
+
+    def batch(prec):
+        def solve(r):
+            cfg = r["cfg"]
+            p = gdr.gdr_params_default(m_dr=cfg["m_dr"], k=cfg["k"], m_proj=cfg["m_proj"],
+                                       tol=cfg["tol"], tol_extra=cfg["tol_extra"], precision=prec,
+                                       use_graph=1)
+            st = gdr.Stats(len(cfg["rhs"]), len(cfg["sigmas"]))
+            t0 = time.perf_counter()
+            r["rc"] = gdr.gdr_solve(r["op"], cfg["sigmas"], r["Bd"], r["X"], p, st)
+            r["sec"] = time.perf_counter() - t0
+            r["st"] = st
+        threads = [threading.Thread(target=solve, args=(r,)) for r in runs]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    nrhs = sum(len(r["cfg"]["rhs"]) for r in runs)
+    fp64 = None
+    if not a.no_fp64:
+        for w in range(a.warmup):
+            batch(gdr.GDR_PREC_F64)
+        wall64 = batch(gdr.GDR_PREC_F64)
+        fp64 = dict(sec_per_all_shift_solve=wall64 / nrhs, wall=wall64,
+                    max_true_resid=max(float(r["st"].resid.max()) for r in runs),
+                    rc=[r["rc"] for r in runs])
+        log("bench: fp64 batch", fp64)
+    for w in range(a.warmup):
+        batch(gdr.GDR_PREC_MIXED)
+    walls = [batch(gdr.GDR_PREC_MIXED) for _ in range(a.steps)]
+    wall = sum(walls) / len(walls)
+    per = {r["name"]: dict(sec=r["sec"], rc=r["rc"], **{k: v for k, v in r["st"].as_dict().items()
+                                                      if k.startswith(("mvp", "cycles"))},
+                           max_true_resid=float(r["st"].resid.max())) for r in runs}
+    if fp64 is not None:
+        fp64["speedup_mixed_vs_fp64"] = fp64["wall"] / wall
+    out = {
+        "metric": METRIC, "value": wall / nrhs, "unit": "s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": wall * 1e3, "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "uneven mixed batch, solved concurrently: 32x32x32x64 Wilson-Dirac "
+                               "(n=25165824, FP16-stored links) 4 Z4 RHS x 8 shifts, GMRES-DR(60,20)-Sh + "
+                               "GMRES(40)-Proj(20)-Sh; six 12^4 and four 16^4 lattices, 2 Z4 RHS x 4 "
+                               "shifts, DR(40,15) + Proj(40,15); tol 1e-8; one context and stream per "
+                               "lattice, Arnoldi cycles replayed from HIP graphs",
+                   "name": "C5", "nrhs": nrhs, "global_batch": nrhs, "parallelism": "1 GPU",
+                   "precision": "mixed: FP32 matvec/Gram-Schmidt/basis, FP64 small problems, "
+                                "accumulation and refinement"},
+        "roofline": None, "fp64": fp64, "cpu_baseline": None,
+        "max_true_resid": max(v["max_true_resid"] for v in per.values()), "lattices": per,
+    }
+    print(json.dumps(out), flush=True)
+    for r in runs:
+        gdr.gdr_op_destroy(r["op"])
+        gdr.gdr_ctx_destroy(r["ctx"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -203,6 +289,10 @@ def main():
     import synth
     from paper_0707_0502_amd import gdr
 
+    if a.workload == "C5":
+        torch.cuda.init()
+        uneven_batch(a, gdr, synth, torch, np)
+        return
     cfg = synth.CONFIGS[a.workload]
     dims = cfg["dims"]
     log("bench: workload", a.workload, describe(a.workload, cfg))
