@@ -175,7 +175,8 @@ typedef struct {
 } gdr_params;
 
 /* kernel classes of the profiler (gdr_params.profile bit i = class i) */
-#define GDR_K_DSLASH 0      /* Wilson operator launches (solver and residuals) */
+#define GDR_K_DSLASH 0      /* Wilson operator launches of the Krylov space (FP32 in the mixed path,
+                               FP64 in the FP64 path) */
 #define GDR_K_GS_PROJECT 1  /* Gram-Schmidt projection sweep V^H [r_j, A r_j] */
 #define GDR_K_GS_UPDATE 2   /* Gram-Schmidt update sweep (finishes q_j, forms r_{j+1}) */
 #define GDR_K_GS_CLOSE 3    /* second Gram-Schmidt passes: the closing pass of the last basis
@@ -184,7 +185,7 @@ typedef struct {
 #define GDR_K_SMALL 4       /* device small dense problems */
 #define GDR_K_COMBINE 5     /* x_i += V d_i, r = V s */
 #define GDR_K_RECOMBINE 6   /* V_{k+1} = V_{m+1} P */
-#define GDR_K_OTHER 7       /* reductions, scaling, conversions */
+#define GDR_K_OTHER 7       /* FP64 true residuals of the mixed path, reductions, scaling */
 
 /* Fill defaults: m_dr 40, k 15, m_proj 40, tol 1e-8, tol_extra sqrt(tol),
  * max_cycles 1000, FP64, batch 1, related 0, max_refine 8, profile 0, m_clean 0,

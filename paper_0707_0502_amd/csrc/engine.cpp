@@ -506,10 +506,12 @@ static int dr_run(gdr_op_s* op, int ns, const double2* sig_h, const double2* b_e
             DiagList dl{};
             dl.d[0] = z(1.0 - sig_h[0].x, -sig_h[0].y);
             dl.alpha[0] = -1;
-            S.prof.begin(GDR_K_DSLASH);
+            // FP64 true residual: its own class (the operator class holds the
+            // FP32 operator of the Krylov space only)
+            S.prof.begin(GDR_K_OTHER);
             op_apply<double>(op, X, 0, rtrue, 0, b_eo, 0, dl, 1,
                            st);
-            S.prof.end(GDR_K_DSLASH, dslash_bytes<double>(op, 1, true), dslash_flops(op, 1));
+            S.prof.end(GDR_K_OTHER, dslash_bytes<double>(op, 1, true), dslash_flops(op, 1));
             if (S.st) S.st->mvp_fp64 += 1;
         }
         HIPCHK(hipStreamWaitEvent(st, cx_->ev_join, 0));
@@ -773,11 +775,11 @@ static void proj_run(gdr_op_s* op, gdr_defl_s* defl, int nmem, int ns,
                     dl.alpha[v] = -1;
                 }
                 const int na = std::min(nb, nact0 - std::min(nact0, b0));
-                S.prof.begin(GDR_K_DSLASH);
+                S.prof.begin(GDR_K_OTHER);   // FP64 true residuals
                 op_apply<double>(op, W + b0 * wms, wms, W + b0 * wms + (int64_t)ns * n, wms,
                                Bm + b0 * n, n, dl, nb,
                                st, act + b0);
-                S.prof.end(GDR_K_DSLASH, dslash_bytes<double>(op, na, true), dslash_flops(op, na));
+                S.prof.end(GDR_K_OTHER, dslash_bytes<double>(op, na, true), dslash_flops(op, na));
                 if (S.st) S.st->mvp_fp64 += na;
             }
             gs_dot<double, double>(nullptr, 0, 0, 0, W + (int64_t)ns * n, wms, nullptr, 0,
