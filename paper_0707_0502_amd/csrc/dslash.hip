@@ -13,6 +13,8 @@
 // range of tiles, keeping the cross-face reuse in its own L2.
 #include "kernels.h"
 
+#include <type_traits>
+
 namespace gdr {
 
 template <typename R>
@@ -51,6 +53,74 @@ __device__ __forceinline__ const X* at(const X* base, unsigned off) {
     return (const X*)((const char*)base + off);
 }
 
+// c q for c = CR + i CI with CR, CI in {-1, 0, 1} (one of them zero): a
+// swap and sign changes, no multiplications
+template <int CR, int CI, typename R>
+__device__ __forceinline__ Z<R> mulc(Z<R> q) {
+    if constexpr (CR == 0) {
+        if constexpr (CI == 1) return {-q.y, q.x};
+        else return {q.y, -q.x};
+    } else {
+        if constexpr (CR == 1) return q;
+        else return {-q.x, -q.y};
+    }
+}
+
+// One hop with its direction fixed at compile time. Spin projection of hop
+// MU with sign sg (-1: forward with 1 - g_mu, +1: backward with 1 + g_mu) in
+// the chiral basis:
+//   h0 = psi0 + c0 psi_{p0},  h1 = psi1 + c1 psi_{p1},
+//   out rows 0,1 += U h0, U h1;  row p0 += conj(c0) U h0;  row p1 += conj(c1) U h1
+// with (p0, p1) = (3, 2) for mu = x, y and (2, 3) for mu = z, t, and
+//   mu=x: c0 = c1 = i sg;   mu=y: c0 = -sg, c1 = sg;
+//   mu=z: c0 = i sg, c1 = -i sg;   mu=t: c0 = c1 = sg.
+// Forward hops multiply by U_mu(x), backward hops by U_mu(x - mu)^H.
+template <int MU, int DIR, typename R>
+__device__ __forceinline__ void hop_acc(Z<R> (&acc)[4][3], const Z<R> (&ps)[4][3],
+                                        const Z<R> (&u)[3][3]) {
+    constexpr int sg = DIR == 0 ? -1 : 1;
+    constexpr int C0R = MU == 1 ? -sg : MU == 3 ? sg : 0;
+    constexpr int C0I = MU == 0 || MU == 2 ? sg : 0;
+    constexpr int C1R = MU == 1 || MU == 3 ? sg : 0;
+    constexpr int C1I = MU == 0 ? sg : MU == 2 ? -sg : 0;
+    constexpr bool low = MU < 2;   // (p0, p1) = (3, 2)
+    Z<R> h0[3], h1[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        h0[a] = zadd(ps[0][a], mulc<C0R, C0I>(low ? ps[3][a] : ps[2][a]));
+        h1[a] = zadd(ps[1][a], mulc<C1R, C1I>(low ? ps[2][a] : ps[3][a]));
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        // (U h)_a; the first term starts the sum (an added zero would not be
+        // folded away under IEEE rules)
+        Z<R> s0, s1;
+#pragma unroll
+        for (int bb = 0; bb < 3; ++bb) {
+            const Z<R> m = DIR == 0 ? u[a][bb] : Z<R>{u[bb][a].x, -u[bb][a].y};
+            const Z<R> t0 = {m.x * h0[bb].x - m.y * h0[bb].y, m.x * h0[bb].y + m.y * h0[bb].x};
+            const Z<R> t1 = {m.x * h1[bb].x - m.y * h1[bb].y, m.x * h1[bb].y + m.y * h1[bb].x};
+            s0 = bb == 0 ? t0 : zadd(s0, t0);
+            s1 = bb == 0 ? t1 : zadd(s1, t1);
+        }
+        acc[0][a] = zadd(acc[0][a], s0);
+        acc[1][a] = zadd(acc[1][a], s1);
+        const Z<R> e0 = mulc<C0R, -C0I>(s0);   // conj(c0) U h0
+        const Z<R> e1 = mulc<C1R, -C1I>(s1);
+        acc[2][a] = zadd(acc[2][a], low ? e1 : e0);
+        acc[3][a] = zadd(acc[3][a], low ? e0 : e1);
+    }
+}
+
+// An empty asm that claims to change x: the compiler must have x ready at
+// this point and cannot compute anything derived from the new value earlier.
+// Used to keep the eight hops in sequence (otherwise the straight-line code
+// is reordered so that all loads come first and the registers spill).
+template <typename X>
+__device__ __forceinline__ void pin(X& x) {
+    asm volatile("" : "+v"(x));
+}
+
 template <typename TS, typename TL, typename R>
 struct DslashK {
     using C = typename CT<TS>::t;
@@ -67,29 +137,37 @@ struct DslashK {
         const int lbv = (nb % 8 == 0) ? ((b % 8) * (nb / 8) + b / 8) : b;
         const int v = lbv % nvec;
         const int lb = lbv / nvec;
-        if (act && !act[v]) return;   // uniform over the block
+        const bool active = !act || act[v];   // uniform over the block
         const int local = threadIdx.x;
-        const int site = lb * 256 + local;
+        const int site0 = lb * 256 + local;
         const int vol = g.vol;
-        const bool valid = site < vol;   // blocks hold whole tiles: a tile is all valid or all not
+        const bool valid = site0 < vol;   // blocks hold whole tiles: a tile is all valid or all not
         const int64_t V = vol;
         const C* inv = in + v * in_stride;
+        // all twelve loads in flight at once: sites past the volume read
+        // site 0 (in bounds) and stage zeros
+        const int ss = valid ? site0 : 0;
+        C st[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) st[c] = inv[c * V + ss];
+        if (!active) return;
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
-            C z;
-            z.x = 0;
-            z.y = 0;
-            sp[c * 256 + local] = valid ? inv[c * V + site] : z;
+            if (!valid) {
+                st[c].x = 0;
+                st[c].y = 0;
+            }
+            sp[c * 256 + local] = st[c];
         }
         __syncthreads();
         if (!valid) return;
         const int ltv = g.ltv;
-        const int T = site >> ltv;
-        const int w = site & ((1 << ltv) - 1);
+        const int T0 = site0 >> ltv;
+        const int w0 = site0 & ((1 << ltv) - 1);
         const int slot = local & ~((1 << ltv) - 1);   // first LDS slot of this tile
         int tc[4];
         {
-            int r = T;
+            int r = T0;
             tc[0] = r % g.nt[0];
             r /= g.nt[0];
             tc[1] = r % g.nt[1];
@@ -105,121 +183,106 @@ struct DslashK {
 #pragma unroll
             for (int a = 0; a < 3; ++a) acc[sp_][a] = {0, 0};
 
-        // Spin projection of hop mu with sign sg (-1: forward with 1 - g_mu,
-        // +1: backward with 1 + g_mu) in the chiral basis:
-        //   h0 = psi0 + c0 psi_{p0},  h1 = psi1 + c1 psi_{p1},
-        //   out rows 0,1 += U h0, U h1;  row p0 += conj(c0) U h0;  row p1 += conj(c1) U h1
-        // with (p0, p1) = (3, 2) for mu = x, y and (2, 3) for mu = z, t, and
-        //   mu=x: c0 = c1 = i sg;   mu=y: c0 = -sg, c1 = sg;
-        //   mu=z: c0 = i sg, c1 = -i sg;   mu=t: c0 = c1 = sg.
-#pragma unroll 1
-        for (int mu = 0; mu < 4; ++mu) {
+        // the eight hops, each with its projection constants fixed at
+        // compile time; a hop inside the tile reads LDS, across a face global
+        // memory (the neighbouring tile, periodic wrap)
+        auto hop = [&](auto muc, auto dirc) {
+            constexpr int mu = decltype(muc)::value;
+            constexpr int dir = decltype(dirc)::value;
+            int w = w0, T = T0, site = site0;
+            pin(w);
+            pin(T);
+            pin(site);
             const int offm = g.off[mu];
             const int bm = 1 << g.lb[mu];
             const int cm = (w >> offm) & (bm - 1);
             const int ntm = g.nt[mu];
-            const int tcm = mu == 0 ? tc[0] : mu == 1 ? tc[1] : mu == 2 ? tc[2] : tc[3];
-            const int stm = mu == 0 ? tst[0] : mu == 1 ? tst[1] : mu == 2 ? tst[2] : tst[3];
-            const bool low = mu < 2;   // (p0, p1) = (3, 2)
-            const TL* lk = links + (int64_t)mu * 9 * V;
-#pragma unroll
-            for (int dir = 0; dir < 2; ++dir) {
-                const bool inside = dir == 0 ? cm < bm - 1 : cm > 0;
-                int wn, Tn;
-                if (dir == 0) {
-                    wn = inside ? w + (1 << offm) : w - ((bm - 1) << offm);
-                    Tn = inside ? T : (tcm == ntm - 1 ? T - (ntm - 1) * stm : T + stm);
-                } else {
-                    wn = inside ? w - (1 << offm) : w + ((bm - 1) << offm);
-                    Tn = inside ? T : (tcm == 0 ? T + (ntm - 1) * stm : T - stm);
-                }
-                const int sn = (Tn << ltv) | wn;
-                const R sg = dir == 0 ? R(-1) : R(1);
-                R c0r, c0i, c1r, c1i;
-                if (mu == 0) { c0r = 0; c0i = sg; c1r = 0; c1i = sg; }
-                else if (mu == 1) { c0r = -sg; c0i = 0; c1r = sg; c1i = 0; }
-                else if (mu == 2) { c0r = 0; c0i = sg; c1r = 0; c1i = -sg; }
-                else { c0r = sg; c0i = 0; c1r = sg; c1i = 0; }
-                Z<R> ps[4][3];
-                if (inside) {
-                    const int li = slot + wn;
-#pragma unroll
-                    for (int s_ = 0; s_ < 4; ++s_)
-#pragma unroll
-                        for (int a = 0; a < 3; ++a) ps[s_][a] = ld<R>(&sp[(s_ * 3 + a) * 256 + li]);
-                } else {
-#pragma unroll
-                    for (int s_ = 0; s_ < 4; ++s_)
-#pragma unroll
-                        for (int a = 0; a < 3; ++a)
-                            ps[s_][a] = ld<R>(at(inv + (s_ * 3 + a) * V, (unsigned)sn * (unsigned)sizeof(C)));
-                }
-                const int ls = dir == 0 ? site : sn;
-                Z<R> u[3][3];
-#pragma unroll
-                for (int a = 0; a < 3; ++a)
-#pragma unroll
-                    for (int bb = 0; bb < 3; ++bb)
-                        u[a][bb] = ld<R>(at(lk + (a * 3 + bb) * V, (unsigned)ls * (unsigned)sizeof(TL)));
-                Z<R> h0[3], h1[3];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    const Z<R> q0 = low ? ps[3][a] : ps[2][a];
-                    const Z<R> q1 = low ? ps[2][a] : ps[3][a];
-                    h0[a] = {ps[0][a].x + c0r * q0.x - c0i * q0.y, ps[0][a].y + c0r * q0.y + c0i * q0.x};
-                    h1[a] = {ps[1][a].x + c1r * q1.x - c1i * q1.y, ps[1][a].y + c1r * q1.y + c1i * q1.x};
-                }
-                Z<R> g0[3], g1[3];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    Z<R> s0 = {0, 0}, s1 = {0, 0};
-#pragma unroll
-                    for (int bb = 0; bb < 3; ++bb) {
-                        // forward: U[a][bb]; backward: conj(U[bb][a])
-                        const Z<R> m = dir == 0 ? u[a][bb] : Z<R>{u[bb][a].x, -u[bb][a].y};
-                        s0.x += m.x * h0[bb].x - m.y * h0[bb].y;
-                        s0.y += m.x * h0[bb].y + m.y * h0[bb].x;
-                        s1.x += m.x * h1[bb].x - m.y * h1[bb].y;
-                        s1.y += m.x * h1[bb].y + m.y * h1[bb].x;
-                    }
-                    g0[a] = s0;
-                    g1[a] = s1;
-                }
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    acc[0][a] = zadd(acc[0][a], g0[a]);
-                    acc[1][a] = zadd(acc[1][a], g1[a]);
-                    // conj(c0) g0 and conj(c1) g1
-                    const Z<R> e0 = {c0r * g0[a].x + c0i * g0[a].y, c0r * g0[a].y - c0i * g0[a].x};
-                    const Z<R> e1 = {c1r * g1[a].x + c1i * g1[a].y, c1r * g1[a].y - c1i * g1[a].x};
-                    acc[2][a] = zadd(acc[2][a], low ? e1 : e0);
-                    acc[3][a] = zadd(acc[3][a], low ? e0 : e1);
-                }
+            const int tcm = tc[mu];
+            const int stm = tst[mu];
+            const bool inside = dir == 0 ? cm < bm - 1 : cm > 0;
+            int wn, Tn;
+            if (dir == 0) {
+                wn = inside ? w + (1 << offm) : w - ((bm - 1) << offm);
+                Tn = inside ? T : (tcm == ntm - 1 ? T - (ntm - 1) * stm : T + stm);
+            } else {
+                wn = inside ? w - (1 << offm) : w + ((bm - 1) << offm);
+                Tn = inside ? T : (tcm == 0 ? T + (ntm - 1) * stm : T - stm);
             }
-        }
+            const int sn = (Tn << ltv) | wn;
+            Z<R> ps[4][3];
+            if (inside) {
+                const int li = slot + wn;
+#pragma unroll
+                for (int s_ = 0; s_ < 4; ++s_)
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) ps[s_][a] = ld<R>(&sp[(s_ * 3 + a) * 256 + li]);
+            } else {
+#pragma unroll
+                for (int s_ = 0; s_ < 4; ++s_)
+#pragma unroll
+                    for (int a = 0; a < 3; ++a)
+                        ps[s_][a] = ld<R>(at(inv + (s_ * 3 + a) * V, (unsigned)sn * (unsigned)sizeof(C)));
+            }
+            const TL* lk = links + (int64_t)mu * 9 * V;
+            const int ls = dir == 0 ? site : sn;
+            Z<R> u[3][3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int bb = 0; bb < 3; ++bb)
+                    u[a][bb] = ld<R>(at(lk + (a * 3 + bb) * V, (unsigned)ls * (unsigned)sizeof(TL)));
+            hop_acc<mu, dir>(acc, ps, u);
+#pragma unroll
+            for (int s_ = 0; s_ < 4; ++s_)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    pin(acc[s_][a].x);
+                    pin(acc[s_][a].y);
+                }
+        };
+        using I0 = std::integral_constant<int, 0>;
+        using I1 = std::integral_constant<int, 1>;
+        using I2 = std::integral_constant<int, 2>;
+        using I3 = std::integral_constant<int, 3>;
+        hop(I0{}, I0{});
+        hop(I0{}, I1{});
+        hop(I1{}, I0{});
+        hop(I1{}, I1{});
+        hop(I2{}, I0{});
+        hop(I2{}, I1{});
+        hop(I3{}, I0{});
+        hop(I3{}, I1{});
+
+        int site = site0, lsl = local;
+        pin(site);
+        pin(lsl);
         C* o = out + v * out_stride + site;
         const C* ad = add ? add + v * add_stride + site : nullptr;
         const R dre = (R)dl.d[v].x, dim = (R)dl.d[v].y, al = (R)dl.alpha[v];
+        auto fin = [&](auto with_add) {
 #pragma unroll
-        for (int s_ = 0; s_ < 4; ++s_)
+            for (int s_ = 0; s_ < 4; ++s_)
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const int comp = s_ * 3 + a;
-                Z<R> xi = ld<R>(&sp[comp * 256 + local]);
-                R re = dre * xi.x - dim * xi.y - kappa * acc[s_][a].x;
-                R im = dre * xi.y + dim * xi.x - kappa * acc[s_][a].y;
-                re *= al;
-                im *= al;
-                if (ad) {
-                    Z<R> av = ld<R>(ad + comp * V);
-                    re += av.x;
-                    im += av.y;
+                for (int a = 0; a < 3; ++a) {
+                    const int comp = s_ * 3 + a;
+                    Z<R> xi = ld<R>(&sp[comp * 256 + lsl]);
+                    R re = dre * xi.x - dim * xi.y - kappa * acc[s_][a].x;
+                    R im = dre * xi.y + dim * xi.x - kappa * acc[s_][a].y;
+                    re *= al;
+                    im *= al;
+                    if constexpr (decltype(with_add)::value) {
+                        Z<R> av = ld<R>(ad + comp * V);
+                        re += av.x;
+                        im += av.y;
+                    }
+                    C wv;
+                    wv.x = re;
+                    wv.y = im;
+                    o[comp * V] = wv;
                 }
-                C wv;
-                wv.x = re;
-                wv.y = im;
-                o[comp * V] = wv;
-            }
+        };
+        if (ad) fin(std::true_type{});
+        else fin(std::false_type{});
     }
 };
 
