@@ -75,21 +75,32 @@ __device__ __forceinline__ Z<R> mulc(Z<R> q) {
 //   mu=x: c0 = c1 = i sg;   mu=y: c0 = -sg, c1 = sg;
 //   mu=z: c0 = i sg, c1 = -i sg;   mu=t: c0 = c1 = sg.
 // Forward hops multiply by U_mu(x), backward hops by U_mu(x - mu)^H.
+template <int MU, int DIR>
+struct HopC {
+    static constexpr int sg = DIR == 0 ? -1 : 1;
+    static constexpr int c0r = MU == 1 ? -sg : MU == 3 ? sg : 0;
+    static constexpr int c0i = MU == 0 || MU == 2 ? sg : 0;
+    static constexpr int c1r = MU == 1 || MU == 3 ? sg : 0;
+    static constexpr int c1i = MU == 0 ? sg : MU == 2 ? -sg : 0;
+    static constexpr bool low = MU < 2;   // (p0, p1) = (3, 2)
+};
+
+// spin projection of a full spinor for hop (MU, DIR): the half spinor (h0, h1)
 template <int MU, int DIR, typename R>
-__device__ __forceinline__ void hop_acc(Z<R> (&acc)[4][3], const Z<R> (&ps)[4][3],
-                                        const Z<R> (&u)[3][3]) {
-    constexpr int sg = DIR == 0 ? -1 : 1;
-    constexpr int C0R = MU == 1 ? -sg : MU == 3 ? sg : 0;
-    constexpr int C0I = MU == 0 || MU == 2 ? sg : 0;
-    constexpr int C1R = MU == 1 || MU == 3 ? sg : 0;
-    constexpr int C1I = MU == 0 ? sg : MU == 2 ? -sg : 0;
-    constexpr bool low = MU < 2;   // (p0, p1) = (3, 2)
-    Z<R> h0[3], h1[3];
+__device__ __forceinline__ void proj(const Z<R> (&ps)[4][3], Z<R> (&h0)[3], Z<R> (&h1)[3]) {
+    using H = HopC<MU, DIR>;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        h0[a] = zadd(ps[0][a], mulc<C0R, C0I>(low ? ps[3][a] : ps[2][a]));
-        h1[a] = zadd(ps[1][a], mulc<C1R, C1I>(low ? ps[2][a] : ps[3][a]));
+        h0[a] = zadd(ps[0][a], mulc<H::c0r, H::c0i>(H::low ? ps[3][a] : ps[2][a]));
+        h1[a] = zadd(ps[1][a], mulc<H::c1r, H::c1i>(H::low ? ps[2][a] : ps[3][a]));
     }
+}
+
+// link times half spinor, reconstructed into the four spin rows of acc
+template <int MU, int DIR, typename R>
+__device__ __forceinline__ void mulrec(Z<R> (&acc)[4][3], const Z<R> (&h0)[3], const Z<R> (&h1)[3],
+                                       const Z<R> (&u)[3][3]) {
+    using H = HopC<MU, DIR>;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         // (U h)_a; the first term starts the sum (an added zero would not be
@@ -105,10 +116,10 @@ __device__ __forceinline__ void hop_acc(Z<R> (&acc)[4][3], const Z<R> (&ps)[4][3
         }
         acc[0][a] = zadd(acc[0][a], s0);
         acc[1][a] = zadd(acc[1][a], s1);
-        const Z<R> e0 = mulc<C0R, -C0I>(s0);   // conj(c0) U h0
-        const Z<R> e1 = mulc<C1R, -C1I>(s1);
-        acc[2][a] = zadd(acc[2][a], low ? e1 : e0);
-        acc[3][a] = zadd(acc[3][a], low ? e0 : e1);
+        const Z<R> e0 = mulc<H::c0r, -H::c0i>(s0);   // conj(c0) U h0
+        const Z<R> e1 = mulc<H::c1r, -H::c1i>(s1);
+        acc[2][a] = zadd(acc[2][a], H::low ? e1 : e0);
+        acc[3][a] = zadd(acc[3][a], H::low ? e0 : e1);
     }
 }
 
@@ -231,7 +242,9 @@ struct DslashK {
 #pragma unroll
                 for (int bb = 0; bb < 3; ++bb)
                     u[a][bb] = ld<R>(at(lk + (a * 3 + bb) * V, (unsigned)ls * (unsigned)sizeof(TL)));
-            hop_acc<mu, dir>(acc, ps, u);
+            Z<R> h0[3], h1[3];
+            proj<mu, dir>(ps, h0, h1);
+            mulrec<mu, dir>(acc, h0, h1, u);
 #pragma unroll
             for (int s_ = 0; s_ < 4; ++s_)
 #pragma unroll
@@ -286,6 +299,211 @@ struct DslashK {
     }
 };
 
+// FP32 operator for lattices cut into 4^4 tiles (every extent a multiple of
+// 4): a block of 256 threads is one tile. Before any hop it stages, with all
+// loads in flight together, its own tile and the spin-projected halo: for
+// each of the eight faces the 64 neighbouring sites across that face,
+// projected with that hop's (1 -/+ g_mu) to half spinors (6 complex). Every
+// hop then reads spinors from LDS only (inside the tile the full neighbour,
+// projected in the hop; across a face the staged half spinor), so no hop
+// waits on a scattered global read; the links still come from global
+// memory. LDS 48 KB per block (3 blocks per CU).
+template <typename TL>
+struct DslashHaloK {
+    using C = float2;
+    using R = float;
+
+    __device__ static void run(const C* __restrict__ in, int64_t in_stride, C* __restrict__ out,
+                               int64_t out_stride, const C* __restrict__ add, int64_t add_stride,
+                               const TL* __restrict__ links, const Geom& g, R kappa,
+                               const DiagList& dl, const int* __restrict__ act, int nvec) {
+        __shared__ C sp[12 * 256];        // own tile, [component][site]
+        __shared__ C hl[8 * 6 * 64];      // halo, [face = 2 mu + dir][half-spinor component][face site]
+        const int nb = gridDim.x;
+        const int b = blockIdx.x;
+        const int lbv = (nb % 8 == 0) ? ((b % 8) * (nb / 8) + b / 8) : b;
+        const int v = lbv % nvec;
+        const int T = lbv / nvec;   // tile
+        const bool active = !act || act[v];   // uniform over the block
+        const int local = threadIdx.x;
+        const int site0 = (T << 8) | local;
+        const int64_t V = g.vol;
+        const C* inv = in + v * in_stride;
+        int tc[4];
+        {
+            int r = T;
+            tc[0] = r % g.nt[0];
+            r /= g.nt[0];
+            tc[1] = r % g.nt[1];
+            r /= g.nt[1];
+            tc[2] = r % g.nt[2];
+            tc[3] = r / g.nt[2];
+        }
+        const int tst[4] = {1, g.nt[0], g.nt[0] * g.nt[1], g.nt[0] * g.nt[1] * g.nt[2]};
+        // neighbouring tile along mu (forward or backward, periodic)
+        auto ntile = [&](int mu, int dir) {
+            const int ntm = mu == 0 ? g.nt[0] : mu == 1 ? g.nt[1] : mu == 2 ? g.nt[2] : g.nt[3];
+            const int tcm = mu == 0 ? tc[0] : mu == 1 ? tc[1] : mu == 2 ? tc[2] : tc[3];
+            const int stm = mu == 0 ? tst[0] : mu == 1 ? tst[1] : mu == 2 ? tst[2] : tst[3];
+            return dir == 0 ? (tcm == ntm - 1 ? T - (ntm - 1) * stm : T + stm)
+                            : (tcm == 0 ? T + (ntm - 1) * stm : T - stm);
+        };
+
+        // ---- staging: own site, and halo entries e = local and local + 256
+        // (face f = e / 64 is uniform over a wavefront, j = e % 64 the face site)
+        C st[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) st[c] = inv[c * V + site0];
+        C hs[2][12];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int e = local + 256 * h;
+            const int f = e >> 6, j = e & 63;
+            const int mu = f >> 1, dir = f & 1;
+            const int sh = 2 * mu;
+            // the neighbour across face (mu, dir): coordinate mu is 0 in the
+            // next tile (forward) or 3 in the previous one (backward), the
+            // other three are those of face site j
+            const int cn = dir == 0 ? 0 : 3;
+            const int wn = (j & ((1 << sh) - 1)) | (cn << sh) | ((j >> sh) << (sh + 2));
+            const int sn = (ntile(mu, dir) << 8) | wn;
+#pragma unroll
+            for (int c = 0; c < 12; ++c) hs[h][c] = *at(inv + c * V, (unsigned)sn * (unsigned)sizeof(C));
+        }
+        if (!active) return;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) sp[c * 256 + local] = st[c];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int e = local + 256 * h;
+            const int f = e >> 6, j = e & 63;
+            Z<R> ps[4][3], h0[3], h1[3];
+#pragma unroll
+            for (int s_ = 0; s_ < 4; ++s_)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) ps[s_][a] = {hs[h][s_ * 3 + a].x, hs[h][s_ * 3 + a].y};
+            switch (f) {
+                case 0: proj<0, 0>(ps, h0, h1); break;
+                case 1: proj<0, 1>(ps, h0, h1); break;
+                case 2: proj<1, 0>(ps, h0, h1); break;
+                case 3: proj<1, 1>(ps, h0, h1); break;
+                case 4: proj<2, 0>(ps, h0, h1); break;
+                case 5: proj<2, 1>(ps, h0, h1); break;
+                case 6: proj<3, 0>(ps, h0, h1); break;
+                default: proj<3, 1>(ps, h0, h1); break;
+            }
+            C* hp = hl + f * 6 * 64 + j;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                hp[a * 64] = make_float2(h0[a].x, h0[a].y);
+                hp[(3 + a) * 64] = make_float2(h1[a].x, h1[a].y);
+            }
+        }
+        __syncthreads();
+
+        Z<R> acc[4][3];
+#pragma unroll
+        for (int s_ = 0; s_ < 4; ++s_)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) acc[s_][a] = {0, 0};
+        auto hop = [&](auto muc, auto dirc) {
+            constexpr int mu = decltype(muc)::value;
+            constexpr int dir = decltype(dirc)::value;
+            constexpr int sh = 2 * mu;
+            int w = local, site = site0;
+            pin(w);
+            pin(site);
+            const int cm = (w >> sh) & 3;
+            const bool inside = dir == 0 ? cm < 3 : cm > 0;
+            const int wn = dir == 0 ? (inside ? w + (1 << sh) : w - (3 << sh))
+                                    : (inside ? w - (1 << sh) : w + (3 << sh));
+            Z<R> h0[3], h1[3];
+            if (inside) {
+                Z<R> ps[4][3];
+#pragma unroll
+                for (int s_ = 0; s_ < 4; ++s_)
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) ps[s_][a] = ld<R>(&sp[(s_ * 3 + a) * 256 + wn]);
+                proj<mu, dir>(ps, h0, h1);
+            } else {
+                const int j = (w & ((1 << sh) - 1)) | ((w >> (sh + 2)) << sh);
+                const C* hp = hl + (2 * mu + dir) * 6 * 64 + j;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    h0[a] = ld<R>(&hp[a * 64]);
+                    h1[a] = ld<R>(&hp[(3 + a) * 64]);
+                }
+            }
+            // forward: U_mu(x) at this site; backward: U_mu(x - mu) at the
+            // neighbour, in the previous tile for face sites
+            int ls = site;
+            if (dir == 1) ls = ((inside ? T : ntile(mu, 1)) << 8) | wn;
+            const TL* lk = links + (int64_t)mu * 9 * V;
+            Z<R> u[3][3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int bb = 0; bb < 3; ++bb)
+                    u[a][bb] = ld<R>(at(lk + (a * 3 + bb) * V, (unsigned)ls * (unsigned)sizeof(TL)));
+            mulrec<mu, dir>(acc, h0, h1, u);
+#pragma unroll
+            for (int s_ = 0; s_ < 4; ++s_)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    pin(acc[s_][a].x);
+                    pin(acc[s_][a].y);
+                }
+        };
+        using I0 = std::integral_constant<int, 0>;
+        using I1 = std::integral_constant<int, 1>;
+        using I2 = std::integral_constant<int, 2>;
+        using I3 = std::integral_constant<int, 3>;
+        hop(I0{}, I0{});
+        hop(I0{}, I1{});
+        hop(I1{}, I0{});
+        hop(I1{}, I1{});
+        hop(I2{}, I0{});
+        hop(I2{}, I1{});
+        hop(I3{}, I0{});
+        hop(I3{}, I1{});
+
+        int site = site0, lsl = local;
+        pin(site);
+        pin(lsl);
+        C* o = out + v * out_stride + site;
+        const C* ad = add ? add + v * add_stride + site : nullptr;
+        const R dre = (R)dl.d[v].x, dim = (R)dl.d[v].y, al = (R)dl.alpha[v];
+        auto fin = [&](auto with_add) {
+#pragma unroll
+            for (int s_ = 0; s_ < 4; ++s_)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const int comp = s_ * 3 + a;
+                    Z<R> xi = ld<R>(&sp[comp * 256 + lsl]);
+                    R re = al * (dre * xi.x - dim * xi.y - kappa * acc[s_][a].x);
+                    R im = al * (dre * xi.y + dim * xi.x - kappa * acc[s_][a].y);
+                    if constexpr (decltype(with_add)::value) {
+                        Z<R> av = ld<R>(ad + comp * V);
+                        re += av.x;
+                        im += av.y;
+                    }
+                    o[comp * V] = make_float2(re, im);
+                }
+        };
+        if (ad) fin(std::true_type{});
+        else fin(std::false_type{});
+    }
+};
+
+template <typename TL>
+__global__ __launch_bounds__(256, 3) void k_dslash_halo(const float2* __restrict__ in, int64_t in_stride,
+                                                        float2* __restrict__ out, int64_t out_stride,
+                                                        const float2* __restrict__ add, int64_t add_stride,
+                                                        const TL* __restrict__ links, Geom g, float kappa,
+                                                        DiagList dl, const int* __restrict__ act, int nvec) {
+    DslashHaloK<TL>::run(in, in_stride, out, out_stride, add, add_stride, links, g, kappa, dl, act, nvec);
+}
+
 template <typename TS> struct DslashOcc { static constexpr int waves = 4; };
 template <> struct DslashOcc<double> { static constexpr int waves = 2; };
 
@@ -311,6 +529,16 @@ void dslash(const typename CT<TS>::t* in, int64_t in_stride, typename CT<TS>::t*
         hipLaunchKernelGGL((k_dslash<double, double2, double>), grid, dim3(256), 0, st, in,
                            in_stride, out, out_stride, add, add_stride, (const double2*)links, g,
                            kappa, dl, act, nvec);
+    } else if (g.ltv == 8) {   // 4^4 tiles: halo-staged kernel
+        if (link_storage == 2) {
+            hipLaunchKernelGGL((k_dslash_halo<__half2>), grid, dim3(256), 0, st, in, in_stride, out,
+                               out_stride, add, add_stride, (const __half2*)links, g, (float)kappa,
+                               dl, act, nvec);
+        } else {
+            hipLaunchKernelGGL((k_dslash_halo<float2>), grid, dim3(256), 0, st, in, in_stride, out,
+                               out_stride, add, add_stride, (const float2*)links, g, (float)kappa,
+                               dl, act, nvec);
+        }
     } else {
         if (link_storage == 2) {
             hipLaunchKernelGGL((k_dslash<float, __half2, float>), grid, dim3(256), 0, st, in,

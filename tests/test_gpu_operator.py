@@ -65,13 +65,15 @@ def test_apply_many_vectors_and_empty():
     gdr.gdr_op_destroy(op)
 
 
+@pytest.mark.parametrize("dims", [(4, 2, 6, 4), (8, 4, 8, 12)])
 @pytest.mark.parametrize("nv", [1, 2, 5, 16, 19])
-def test_apply_fp32_batches_against_oracle(nv):
-    """FP32 launches take two vectors per thread for batches (an odd batch
-    leaves the last pair half used); every vector of every batch size matches
-    the oracle to FP32 rounding, with FP32 and FP16-stored links."""
+def test_apply_fp32_batches_against_oracle(dims, nv):
+    """FP32 launches over batches of vectors: every vector of every batch size
+    matches the oracle to FP32 rounding, with FP32 and FP16-stored links, on
+    a lattice with 2-site tile extents (plain kernel) and on one cut into
+    2x1x2x3 tiles of 4^4 (halo-staged kernel: faces across tiles, and the
+    periodic wrap onto the tile itself in y)."""
     from paper_0707_0502_amd import gdr
-    dims = (4, 2, 6, 4)
     links = synth.gauge_links(dims, 0.4, 7)
     kappa = 0.13
     X = np.stack([synth.rhs_gaussian(dims, 40 + v).ravel() for v in range(nv)])
