@@ -177,31 +177,51 @@ def uneven_batch(a, gdr, synth, torch, np):
     lattices (4 shifts, 2 RHS), each lattice on its own context and stream
     and a host thread of its own, Arnoldi cycles replayed from HIP graphs.
     value: wall time of the whole batch divided by its 24 right-hand sides;
-    the same batch in plain FP64 (also concurrent) is timed first."""
+    the same batch in plain FP64 (also concurrent, on contexts of its own) is
+    timed first."""
     import threading
-    runs = []
+    inputs = []
     for name in synth.C5_GROUP:
         cfg = synth.CONFIGS[name]
         links = synth.gauge_links(cfg["dims"], cfg["eps"], cfg["seed"])
         B = np.stack([synth.make_rhs(cfg, kd, sd).ravel() for kd, sd in cfg["rhs"]])
-        stream = torch.cuda.Stream()
-        ctx = gdr.gdr_ctx_create(0, stream.cuda_stream)
-        lst = gdr.GDR_LINKS_F16 if cfg.get("links") == "f16" else gdr.GDR_LINKS_F32
-        op = gdr.gdr_wilson_create(ctx, cfg["dims"], (1, 1, 1, -1), synth.kappa(name), links, lst)
-        with torch.cuda.stream(stream):
-            Bd = torch.from_numpy(B.ravel()).cuda()
-            X = torch.zeros(len(cfg["rhs"]) * len(cfg["sigmas"]) * op.n, dtype=torch.complex128,
-                            device="cuda")
-        stream.synchronize()
-        runs.append(dict(name=name, cfg=cfg, op=op, ctx=ctx, stream=stream, Bd=Bd, X=X))
-        log("bench: ready", name, cfg["dims"])
+        inputs.append((name, cfg, links, B))
+        log("bench: inputs", name, cfg["dims"])
+
+    def make_runs():
+        # one context, stream and operator per lattice; each context keeps
+        # its own device-memory cache, so the FP64 and the mixed batch get
+        # fresh contexts (the FP64 batch's cached buffers would otherwise
+        # crowd the mixed one into allocating inside its timed region)
+        out = []
+        for name, cfg, links, B in inputs:
+            stream = torch.cuda.Stream()
+            ctx = gdr.gdr_ctx_create(0, stream.cuda_stream)
+            lst = gdr.GDR_LINKS_F16 if cfg.get("links") == "f16" else gdr.GDR_LINKS_F32
+            op = gdr.gdr_wilson_create(ctx, cfg["dims"], (1, 1, 1, -1), synth.kappa(name), links,
+                                       lst)
+            with torch.cuda.stream(stream):
+                Bd = torch.from_numpy(B.ravel()).cuda()
+                X = torch.zeros(len(cfg["rhs"]) * len(cfg["sigmas"]) * op.n,
+                                dtype=torch.complex128, device="cuda")
+            stream.synchronize()
+            out.append(dict(name=name, cfg=cfg, op=op, ctx=ctx, stream=stream, Bd=Bd, X=X))
+        return out
+
+    def drop(rs):
+        torch.cuda.synchronize()
+        for r in rs:
+            gdr.gdr_op_destroy(r["op"])
+            gdr.gdr_ctx_destroy(r["ctx"])
+        rs.clear()
+        torch.cuda.empty_cache()
 
     def batch(prec):
         def solve(r):
             cfg = r["cfg"]
             p = gdr.gdr_params_default(m_dr=cfg["m_dr"], k=cfg["k"], m_proj=cfg["m_proj"],
                                        tol=cfg["tol"], tol_extra=cfg["tol_extra"], precision=prec,
-                                       use_graph=1)
+                                       use_graph=1, refine_floor=a.refine_floor)
             st = gdr.Stats(len(cfg["rhs"]), len(cfg["sigmas"]))
             t0 = time.perf_counter()
             r["rc"] = gdr.gdr_solve(r["op"], cfg["sigmas"], r["Bd"], r["X"], p, st)
@@ -217,9 +237,11 @@ def uneven_batch(a, gdr, synth, torch, np):
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
-    nrhs = sum(len(r["cfg"]["rhs"]) for r in runs)
+    nrhs = sum(len(cfg["rhs"]) for _, cfg, _, _ in inputs)
     fp64 = None
+    runs = []
     if not a.no_fp64:
+        runs += make_runs()
         for w in range(a.warmup):
             batch(gdr.GDR_PREC_F64)
         wall64 = batch(gdr.GDR_PREC_F64)
@@ -227,6 +249,8 @@ def uneven_batch(a, gdr, synth, torch, np):
                     max_true_resid=max(float(r["st"].resid.max()) for r in runs),
                     rc=[r["rc"] for r in runs])
         log("bench: fp64 batch", fp64)
+        drop(runs)
+    runs += make_runs()
     for w in range(a.warmup):
         batch(gdr.GDR_PREC_MIXED)
     walls = [batch(gdr.GDR_PREC_MIXED) for _ in range(a.steps)]
@@ -252,9 +276,7 @@ def uneven_batch(a, gdr, synth, torch, np):
         "max_true_resid": max(v["max_true_resid"] for v in per.values()), "lattices": per,
     }
     print(json.dumps(out), flush=True)
-    for r in runs:
-        gdr.gdr_op_destroy(r["op"])
-        gdr.gdr_ctx_destroy(r["ctx"])
+    drop(runs)
 
 
 def main():
@@ -275,6 +297,8 @@ def main():
                     help="block size of the FP32 Arnoldi cycle (default: the library's)")
     ap.add_argument("--m-clean", type=int, default=0,
                     help="cycle length of the mixed-precision cleanup (0: library default)")
+    ap.add_argument("--refine-floor", type=float, default=0.0,
+                    help="inner tolerance floor of the cleanup's refinement rounds (0: library default)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="end with a 256 MiB device copy (calibrates hardware byte counters)")
     a = ap.parse_args()
@@ -317,7 +341,7 @@ def main():
         p = gdr.gdr_params_default(m_dr=cfg["m_dr"], k=cfg["k"], m_proj=cfg["m_proj"],
                                    tol=cfg["tol"], tol_extra=cfg["tol_extra"],
                                    precision=prec, batch=1, profile=profile,
-                                   m_clean=a.m_clean)
+                                   m_clean=a.m_clean, refine_floor=a.refine_floor)
         if a.sstep is not None:
             p.sstep = a.sstep
         return p

@@ -172,6 +172,9 @@ typedef struct {
                           the projection removed more than this ratio of a block vector's norm
                           squared (its FP32 rounding would then leave components along the
                           basis): then a second pair. 0: always two pairs. Default 20. */
+    double refine_floor; /* mixed precision: each refinement round of the cleanup solves the
+                          residual system in FP32 to relative tolerance max(0.3 tol / res,
+                          refine_floor). 0: 1e-5. Must be in [0, 0.5]. */
 } gdr_params;
 
 /* kernel classes of the profiler (gdr_params.profile bit i = class i) */
@@ -189,7 +192,7 @@ typedef struct {
 
 /* Fill defaults: m_dr 40, k 15, m_proj 40, tol 1e-8, tol_extra sqrt(tol),
  * max_cycles 1000, FP64, batch 1, related 0, max_refine 8, profile 0, m_clean 0,
- * proj_k 0, use_graph 0, galerkin 0, sstep 4, sstep_reorth 20. */
+ * proj_k 0, use_graph 0, galerkin 0, sstep 4, sstep_reorth 20, refine_floor 0. */
 void gdr_params_default(gdr_params* p);
 
 typedef struct {

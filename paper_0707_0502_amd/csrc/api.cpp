@@ -44,6 +44,10 @@ bool check_params(gdr_ctx_s* c, const gdr_params* p, int ns, bool need_dr) {
         c->err = "need 0 <= m_clean <= 64";
         return false;
     }
+    if (!(p->refine_floor >= 0 && p->refine_floor <= 0.5)) {
+        c->err = "need 0 <= refine_floor <= 0.5";
+        return false;
+    }
     if (p->proj_k < 0 || p->proj_k > p->k) {
         c->err = "need 0 <= proj_k <= k";
         return false;
@@ -206,6 +210,7 @@ void gdr_params_default(gdr_params* p) {
     p->galerkin = 0;
     p->sstep = 4;
     p->sstep_reorth = 20;
+    p->refine_floor = 0;
 }
 
 int gdr_wilson_create(gdr_ctx c, const int dims[4], const int bc[4], double kappa,

@@ -1161,6 +1161,10 @@ int cleanup(gdr_op_s* op, gdr_defl_s* defl, int ns, const double2* sig, int nrhs
     // (8 measured fastest on the 24^3x48 twelve-RHS workload: 16 and 24 cost
     // 1.7x and 6x more cleanup time for the same final residuals)
     const int mc = p.m_clean > 0 ? p.m_clean : std::min(p.m_proj, 8);
+    // inner tolerance floor of a round: what an FP32 solve reliably reaches
+    // (with FP16-stored links a floor of 1e-2 saved 5 % of the cleanup
+    // products on the 32^3x64 lattice and no time, so one default serves both)
+    const double floor_tol = p.refine_floor > 0 ? p.refine_floor : 1e-5;
     for (int round = 0; round <= p.max_refine && !done; ++round) {
         // pairs above tolerance
         struct Pair { int j, i; double res; };
@@ -1192,7 +1196,7 @@ int cleanup(gdr_op_s* op, gdr_defl_s* defl, int ns, const double2* sig, int nrhs
                 residual_vectors(op, 1, sig + q.i, B_eo + (int64_t)q.j * n,
                                  X_eo + ((int64_t)q.j * ns + q.i) * n, Bm + b * n);
                 bnorm[b] = q.res * bn[q.j];
-                tol[b] = std::min(0.5, std::max(0.3 * p.tol / q.res, 1e-5));
+                tol[b] = std::min(0.5, std::max(0.3 * p.tol / q.res, floor_tol));
                 sgm[b] = sig[q.i];
             }
             ProjResult Rr;

@@ -50,7 +50,8 @@ class gdr_params(ctypes.Structure):
                 ("max_refine", ctypes.c_int), ("profile", ctypes.c_int),
                 ("m_clean", ctypes.c_int), ("proj_k", ctypes.c_int),
                 ("use_graph", ctypes.c_int), ("galerkin", ctypes.c_int),
-                ("sstep", ctypes.c_int), ("sstep_reorth", ctypes.c_double)]
+                ("sstep", ctypes.c_int), ("sstep_reorth", ctypes.c_double),
+                ("refine_floor", ctypes.c_double)]
 
 
 class gdr_stats(ctypes.Structure):

@@ -41,8 +41,9 @@ def test_struct_layouts_match_header(tmp_path):
 #include <stddef.h>
 #include "gdr.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(gdr_params), sizeof(gdr_stats),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(gdr_params), sizeof(gdr_stats),
          offsetof(gdr_params, tol), offsetof(gdr_params, max_refine), offsetof(gdr_params, galerkin), offsetof(gdr_params, sstep), offsetof(gdr_params, sstep_reorth),
+         offsetof(gdr_params, refine_floor),
          offsetof(gdr_stats, mvp_dr), offsetof(gdr_stats, t_phase),
          offsetof(gdr_stats, resid), offsetof(gdr_stats, theta_len),
          offsetof(gdr_stats, k_ms), offsetof(gdr_stats, k_launches));
@@ -54,6 +55,7 @@ int main(void) {
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     P, S = gdr.gdr_params, gdr.gdr_stats
     want = [ctypes.sizeof(P), ctypes.sizeof(S), P.tol.offset, P.max_refine.offset, P.galerkin.offset, P.sstep.offset, P.sstep_reorth.offset,
+            P.refine_floor.offset,
             S.mvp_dr.offset, S.t_phase.offset, S.resid.offset, S.theta_len.offset,
             S.k_ms.offset, S.k_launches.offset]
     assert got == want
@@ -65,6 +67,7 @@ def test_params_default_host_only():
     assert (p.m_dr, p.k, p.m_proj, p.precision, p.batch, p.profile) == (40, 15, 40, gdr.GDR_PREC_F64, 1, 0)
     assert p.tol == 1e-8 and p.tol_extra == 0
     assert (p.proj_k, p.use_graph, p.galerkin, p.sstep, p.sstep_reorth) == (0, 0, 0, 4, 20.0)
+    assert p.refine_floor == 0.0
 
 
 def test_binding_rejects_missing_library(tmp_path):
