@@ -3,14 +3,19 @@
 //   D psi(x) = sum_mu (1 - g_mu) U_mu(x) psi(x+mu) + (1 + g_mu) U_mu(x-mu)^H psi(x-mu)
 // One thread per lattice site on the tile-blocked SoA layout (every
 // component load is a contiguous run across a wavefront). A block covers
-// 256 consecutive sites, i.e. whole tiles; it first stages its own input
-// tile in LDS, so the hops that stay inside a tile read LDS and only the
-// hops across a tile face read global memory. Each hop is spin-projected to
-// a 2-spinor, multiplied by the 3x3 link and reconstructed (the rank-2
-// projectors 1 -/+ g_mu of the chiral basis). The time-boundary factor is
-// folded into the links at pack time. Blocks are remapped so that each XCD
-// (blocks are dealt round-robin over the 8 XCDs) works on one contiguous
-// range of tiles, keeping the cross-face reuse in its own L2.
+// 256 consecutive sites, i.e. whole tiles. Two kernels:
+//  * k_dslash_halo (FP32 vectors, FP32 or FP16 links, 4^4 tiles): the block
+//    stages its tile and the spin-projected halo of its eight faces in LDS,
+//    so every hop reads its spinor from LDS;
+//  * k_dslash (FP64, and FP32 on lattices with a tile extent of 2): the block
+//    stages its own tile only; hops across a face read global memory.
+// Each hop is spin-projected to a 2-spinor, multiplied by the 3x3 link and
+// reconstructed (the rank-2 projectors 1 -/+ g_mu of the chiral basis). The
+// time-boundary factor is folded into the links at pack time. Blocks are
+// remapped so that each XCD (blocks are dealt round-robin over the 8 XCDs)
+// works on one contiguous range of tiles, keeping the cross-face reuse in its
+// own L2; a batched launch puts the blocks of one tile for all its vectors
+// next to each other, so they share the tile's links through L2.
 #include "kernels.h"
 
 #include <type_traits>
