@@ -167,9 +167,14 @@ int gdr_ctx_create(int device, void* hip_stream, gdr_ctx* out) {
         return GDR_ERR_HIP;
     }
     {
-        // keep at most a third of the device's memory idle in the cache
+        // keep at most half of the device's memory idle in the cache: enough
+        // for every phase of a 32^3x64 solve (about 130 GB) to find its
+        // buffers again in the next solve. A block released to the driver is
+        // expensive to get back: after large frees, hipMalloc of a multi-GB
+        // block has taken 0.3-0.9 s. An allocation that fails releases the
+        // whole idle cache and is retried once.
         size_t fr = 0, tot = 0;
-        if (hipMemGetInfo(&fr, &tot) == hipSuccess) c->pool.cap = tot / 3;
+        if (hipMemGetInfo(&fr, &tot) == hipSuccess) c->pool.cap = tot / 2;
     }
     *out = c;
     return GDR_OK;
