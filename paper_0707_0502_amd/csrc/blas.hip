@@ -11,6 +11,7 @@
 // every result is bitwise reproducible. All accumulation is FP64.
 #include <cstdint>
 #include <initializer_list>
+#include <stdexcept>
 
 #include "kernels.h"
 
@@ -200,6 +201,97 @@ __global__ __launch_bounds__(256) void k_gs_dot(
         if (lane == 0) pout[(int64_t)(NX * nc) * nblk] = mk(s2, 0);
     }
 }
+
+// k_shared_dot: gs_dot with one vector per member for members that all
+// project on the same basis V. A block takes the row range of gs_dot's block
+// for SHARED_MG members at once; its eight waves split the columns (at most 4
+// each, so that 4 columns x 4 members fill the 16 accumulators of one
+// reduce-scatter). Each basis row is read once per member group and each
+// vector row once per wave from the caches. Rows are visited per lane in the
+// same order and reduced by the same butterfly as in k_gs_dot, so the
+// partial sums are identical; member b's values go to b's place in gs_dot's
+// layout.
+template <typename T, typename TX>
+__global__ __launch_bounds__(512) void k_shared_dot(
+    const typename CT<T>::t* __restrict__ V, int64_t ldv, int nc,
+    const typename CT<TX>::t* __restrict__ x, int64_t x_ms, double2* __restrict__ partial,
+    int nblk, int64_t n, int nmem, const int* __restrict__ act) {
+    constexpr int MG = SHARED_MG;
+    constexpr int CW = 16 / MG;
+    using IV = RowIO<T, 1>;
+    using IX = RowIO<TX, 1>;
+    const int b0 = blockIdx.y * MG;
+    bool on[MG];
+    bool any = false;
+#pragma unroll
+    for (int m = 0; m < MG; ++m) {
+        on[m] = b0 + m < nmem && (!act || act[b0 + m]);
+        any = any || on[m];
+    }
+    if (!any) return;   // uniform over the block
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    constexpr int NW = 8;
+    const int64_t per = ((n + nblk - 1) / nblk + 63) / 64 * 64;
+    const int64_t r0 = (int64_t)blockIdx.x * per;
+    const int64_t r1 = r0 + per < n ? r0 + per : n;
+    const int nval = nc + 1;
+    const int g = (nc + NW - 1) / NW;   // <= CW
+    const int c0 = wv * g;
+    const int cnt = nc - c0 < g ? nc - c0 : g;
+    if (cnt > 0) {
+        double2 acc[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc[q] = mk(0, 0);
+        const typename CT<T>::t* vp = V + (int64_t)c0 * ldv;
+        for (int64_t i = r0 + lane; i < r1; i += 64) {
+            double2 xv[MG];
+#pragma unroll
+            for (int m = 0; m < MG; ++m) {
+                xv[m] = mk(0, 0);
+                if (on[m]) IX::get(IX::ld(x + (int64_t)(b0 + m) * x_ms + i), &xv[m]);
+            }
+#pragma unroll
+            for (int c = 0; c < CW; ++c)
+                if (c < cnt) {
+                    double2 v;
+                    IV::get(IV::ldnt(vp + (int64_t)c * ldv + i), &v);
+#pragma unroll
+                    for (int m = 0; m < MG; ++m) acc[m * CW + c] = cadd(acc[m * CW + c], cjmul(v, xv[m]));
+                }
+        }
+        const double2 sum = rs16(acc, lane);
+        if ((lane & 3) == 0) {
+            const int q = (lane >> 2) & 15;
+            const int m = q / CW, c = q % CW;
+            if (c < cnt && on[m])
+                partial[((int64_t)(b0 + m) * nval + c0 + c) * nblk + blockIdx.x] = sum;
+        }
+    }
+    // ||x_b||^2, one wave per member, as gs_dot's last wave computes it
+    if (wv < MG && on[wv]) {
+        const typename CT<TX>::t* xl = x + (int64_t)(b0 + wv) * x_ms;
+        double s2 = 0;
+        for (int64_t i = r0 + lane; i < r1; i += 64) s2 += cabs2(to_d(xl[i]));
+        s2 = wsum(s2);
+        if (lane == 0) partial[((int64_t)(b0 + wv) * nval + nc) * nblk + blockIdx.x] = mk(s2, 0);
+    }
+}
+
+template <typename T, typename TX>
+void shared_dot(const typename CT<T>::t* V, int64_t ldv, int nc, const typename CT<TX>::t* x,
+                int64_t x_ms, double2* partial, int nblk, int64_t n, int nmem, hipStream_t st,
+                const int* act) {
+    if (nc < 1 || nc > SHARED_NC_MAX) throw std::invalid_argument("shared_dot: nc out of range");
+    dim3 grid(nblk, (nmem + SHARED_MG - 1) / SHARED_MG), blk(512);
+    hipLaunchKernelGGL((k_shared_dot<T, TX>), grid, blk, 0, st, V, ldv, nc, x, x_ms, partial,
+                       nblk, n, nmem, act);
+}
+
+template void shared_dot<float, double>(const float2*, int64_t, int, const double2*, int64_t,
+                                        double2*, int, int64_t, int, hipStream_t, const int*);
+template void shared_dot<double, double>(const double2*, int64_t, int, const double2*, int64_t,
+                                         double2*, int, int64_t, int, hipStream_t, const int*);
 
 // k_gs_update: one sweep forms NO outputs
 //   y_o = sum_a beta[o][a] x_a - sum_{c<nc} V_c coef[o][c]

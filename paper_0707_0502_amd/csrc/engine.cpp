@@ -699,8 +699,13 @@ static void proj_run(gdr_op_s* op, gdr_defl_s* defl, int nmem, int ns,
         const double dn = (double)n * nact0;
         // ---- minres projection over V_k with v_{k+1} tracking
         if (k > 0) {
-            gs_dot<T, double>(Vd, n, 0, k + 1, W + (int64_t)ns * n, wms, nullptr, 0, A.partial,
-                              A.nblk, n, nmem, st, act);
+            // every member projects on the one deflation basis V_{k+1}
+            if (k + 1 <= SHARED_NC_MAX)
+                shared_dot<T, double>(Vd, n, k + 1, W + (int64_t)ns * n, wms, A.partial, A.nblk,
+                                      n, nmem, st, act);
+            else
+                gs_dot<T, double>(Vd, n, 0, k + 1, W + (int64_t)ns * n, wms, nullptr, 0,
+                                  A.partial, A.nblk, n, nmem, st, act);
             reduce_cols(A.partial, A.nblk, k + 2, Cb, 80, nullptr, 0, nmem, st, act);
             ProjArgs pa{};
             pa.Hk = defl->Hk;
@@ -918,10 +923,17 @@ static void related_start(gdr_op_s* op, int ns, const double2* Ball, const doubl
     double2* g = mem.get<double2>((size_t)(np + 1) * nmem);
     double2* dv = mem.get<double2>((size_t)np * nmem);
     double2* dn = mem.get<double2>((size_t)np * nmem);
-    // G column l = Bp^H b^l; g_b = Bp^H b_b (each with a norm slot, ignored)
-    gs_dot<double, double>(Bp, n, 0, np, Bp, n, nullptr, 0, part, nblk, n, np, st);
-    reduce_cols(part, nblk, np + 1, G, np + 1, nullptr, 0, np, st);
-    gs_dot<double, double>(Bp, n, 0, np, Bm, n, nullptr, 0, part, nblk, n, nmem, st);
+    // G column l = Bp^H b^l; g_b = Bp^H b_b (each with a norm slot, ignored);
+    // one shared basis Bp for all columns
+    if (np <= SHARED_NC_MAX) {
+        shared_dot<double, double>(Bp, n, np, Bp, n, part, nblk, n, np, st);
+        reduce_cols(part, nblk, np + 1, G, np + 1, nullptr, 0, np, st);
+        shared_dot<double, double>(Bp, n, np, Bm, n, part, nblk, n, nmem, st);
+    } else {
+        gs_dot<double, double>(Bp, n, 0, np, Bp, n, nullptr, 0, part, nblk, n, np, st);
+        reduce_cols(part, nblk, np + 1, G, np + 1, nullptr, 0, np, st);
+        gs_dot<double, double>(Bp, n, 0, np, Bm, n, nullptr, 0, part, nblk, n, nmem, st);
+    }
     reduce_cols(part, nblk, np + 1, g, np + 1, nullptr, 0, nmem, st);
     // compact G to ld np
     double2* Gc = mem.get<double2>((size_t)np * np);

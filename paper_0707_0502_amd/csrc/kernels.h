@@ -56,6 +56,16 @@ void gs_dot(const typename CT<T>::t* V, int64_t ldv, int64_t v_ms, int nc,
             const typename CT<TX>::t* x0, int64_t x0_ms, const typename CT<TX>::t* x1,
             int64_t x1_ms, double2* partial, int nblk, int64_t n, int nmem, hipStream_t st,
             const int* act = nullptr);
+// The same sums (one vector per member, nval = nc + 1, the same partials bit
+// for bit) when every member projects on one shared basis V: the basis is
+// read once per group of SHARED_MG members instead of once per member.
+// Needs nc <= SHARED_NC_MAX; V is the same for all members (no member stride).
+constexpr int SHARED_MG = 4;
+constexpr int SHARED_NC_MAX = 32;
+template <typename T, typename TX>
+void shared_dot(const typename CT<T>::t* V, int64_t ldv, int nc, const typename CT<TX>::t* x,
+                int64_t x_ms, double2* partial, int nblk, int64_t n, int nmem, hipStream_t st,
+                const int* act = nullptr);
 // y_o = sum_a beta[o][a] x_a - V_{0..nc-1} coef[o] (o < 1 or 2 outputs as inputs);
 // layout of coef per member: coef[o*(MAXM+1) + c], beta at 2*(MAXM+1) + 2*o + a.
 constexpr int GS_COEF_MS = 2 * (MAXM + 1) + 4;
