@@ -32,6 +32,11 @@
  *    HIP stream and the call waits for it. No caller pointer is retained.
  *  - Return codes: GDR_OK (0), GDR_NOT_CONVERGED (1, outputs valid and
  *    residuals filled), or a negative error; gdr_last_error() describes it.
+ *    A solve returns GDR_OK only if every final FP64 true residual
+ *    ||b - (A - sigma_i) x_i|| / ||b|| is at most tol (plain FP64 checks them
+ *    after the solve; mixed precision in its cleanup). In plain FP64 the
+ *    corrected non-base shifts of later right-hand sides are only as accurate
+ *    as the extra right-hand side's tolerance (Sec. 4) and can end above tol.
  *  - One context per host thread; calls on one context must not overlap.
  */
 #ifndef GDR_H

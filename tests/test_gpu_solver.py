@@ -122,6 +122,8 @@ def test_c2_full_fp64_parity(c2):
     rc = gdr.gdr_solve(op, sig, dev(B.ravel()), X, params(cfg, gdr.GDR_PREC_F64), st)
     d = st.as_dict()
     say("  rc", rc, d)
+    expect = gdr.GDR_OK if ref["resid"].max() <= cfg["tol"] else gdr.GDR_NOT_CONVERGED
+    assert rc == expect
     assert d["mvp_dr"] == ref["runs"][0]["mvps"]
     assert d["mvp_extra"] == ref["extra"]["mvps"]
     assert d["mvp_proj"] == sum(r["mvps"] for r in ref["runs"][1:])
@@ -183,7 +185,10 @@ def test_c2_related_rhs_fp64_parity(c2):
     rc = gdr.gdr_solve(op, sig, dev(B.ravel()), X, p, st)
     d = st.as_dict()
     say("  rc", rc, d, "oracle proj mvps", [r["mvps"] for r in ref["runs"][1:]])
-    assert rc == gdr.GDR_OK
+    # the corrected shifts end where the extra right-hand side's tolerance
+    # leaves them: the status follows the oracle's true residuals
+    expect = gdr.GDR_OK if ref["resid"].max() <= cfg["tol"] else gdr.GDR_NOT_CONVERGED
+    assert rc == expect
     assert d["mvp_proj"] == sum(r["mvps"] for r in ref["runs"][1:])
     Xh = host(X).reshape(nrhs, ns, n)
     worst = max(rel(Xh[j, i], ref["X"][j, i]) for j in range(nrhs) for i in range(ns))
@@ -318,7 +323,12 @@ def test_graph_replay_matches_eager(c2):
                 say("  prec", prec, "graph", graph, "rc", rc, "t", st.s.t_total)
         for prec in (gdr.GDR_PREC_F64, gdr.GDR_PREC_MIXED):
             e, g = out[(prec, 0)], out[(prec, 1)]
-            assert e[0] == g[0] == gdr.GDR_OK
+            # plain FP64 at tol 1e-10 ends with its corrected shifts where the
+            # extra right-hand side leaves them (the oracle's 2.4e-10 on C2)
+            expect = gdr.GDR_OK
+            if prec == gdr.GDR_PREC_F64 and ref["resid"].max() > cfg["tol"]:
+                expect = gdr.GDR_NOT_CONVERGED
+            assert e[0] == g[0] == expect
             for key in ("mvp_dr", "mvp_extra", "mvp_proj", "mvp_cleanup", "cycles_dr", "cycles_proj"):
                 assert e[1][key] == g[1][key]
             assert np.array_equal(e[2], g[2])
