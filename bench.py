@@ -297,6 +297,8 @@ def main():
                     help="block size of the FP32 Arnoldi cycle (default: the library's)")
     ap.add_argument("--m-clean", type=int, default=0,
                     help="cycle length of the mixed-precision cleanup (0: library default)")
+    ap.add_argument("--tol-extra", type=float, default=None,
+                    help="tolerance of the extra right-hand side (default: the workload's)")
     ap.add_argument("--refine-floor", type=float, default=0.0,
                     help="inner tolerance floor of the cleanup's refinement rounds (0: library default)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -339,7 +341,8 @@ def main():
 
     def params(prec, profile):
         p = gdr.gdr_params_default(m_dr=cfg["m_dr"], k=cfg["k"], m_proj=cfg["m_proj"],
-                                   tol=cfg["tol"], tol_extra=cfg["tol_extra"],
+                                   tol=cfg["tol"],
+                                   tol_extra=cfg["tol_extra"] if a.tol_extra is None else a.tol_extra,
                                    precision=prec, batch=1, profile=profile,
                                    m_clean=a.m_clean, refine_floor=a.refine_floor)
         if a.sstep is not None:
