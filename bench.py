@@ -305,7 +305,7 @@ def main():
                     help="end with a 256 MiB device copy (calibrates hardware byte counters)")
     a = ap.parse_args()
     if a.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(requested --gpus %d)" % a.gpus, file=sys.stderr)
         sys.exit(2)
 
