@@ -313,6 +313,8 @@ struct DslashK {
 // projected in the hop; across a face the staged half spinor), so no hop
 // waits on a scattered global read; the links still come from global
 // memory. LDS 48 KB per block (3 blocks per CU).
+typedef float f2o __attribute__((ext_vector_type(2)));
+
 template <typename TL>
 struct DslashHaloK {
     using C = float2;
@@ -492,7 +494,11 @@ struct DslashHaloK {
                         re += av.x;
                         im += av.y;
                     }
-                    o[comp * V] = make_float2(re, im);
+                    // the product is read by the next kernel from HBM in
+                    // any case: a non-temporal store keeps it from evicting
+                    // the links and neighbour tiles the other blocks still
+                    // read from L2
+                    __builtin_nontemporal_store(f2o{re, im}, (f2o*)&o[comp * V]);
                 }
         };
         if (ad) fin(std::true_type{});
