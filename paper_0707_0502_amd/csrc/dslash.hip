@@ -26,6 +26,18 @@ template <typename R>
 struct Z {
     R x, y;
 };
+
+// The operator's product is read by the next kernel from HBM in any case:
+// non-temporal stores keep it from evicting the links and neighbour tiles
+// that other blocks still read from L2.
+typedef float f2o __attribute__((ext_vector_type(2)));
+typedef double d2o __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void st_nt(float2* p, float re, float im) {
+    __builtin_nontemporal_store(f2o{re, im}, (f2o*)p);
+}
+__device__ __forceinline__ void st_nt(double2* p, double re, double im) {
+    __builtin_nontemporal_store(d2o{re, im}, (d2o*)p);
+}
 template <typename R>
 __device__ __forceinline__ Z<R> zadd(Z<R> a, Z<R> b) { return {a.x + b.x, a.y + b.y}; }
 template <typename R>
@@ -293,10 +305,7 @@ struct DslashK {
                         re += av.x;
                         im += av.y;
                     }
-                    C wv;
-                    wv.x = re;
-                    wv.y = im;
-                    o[comp * V] = wv;
+                    st_nt(&o[comp * V], re, im);
                 }
         };
         if (ad) fin(std::true_type{});
@@ -313,8 +322,6 @@ struct DslashK {
 // projected in the hop; across a face the staged half spinor), so no hop
 // waits on a scattered global read; the links still come from global
 // memory. LDS 48 KB per block (3 blocks per CU).
-typedef float f2o __attribute__((ext_vector_type(2)));
-
 template <typename TL>
 struct DslashHaloK {
     using C = float2;
@@ -494,11 +501,7 @@ struct DslashHaloK {
                         re += av.x;
                         im += av.y;
                     }
-                    // the product is read by the next kernel from HBM in
-                    // any case: a non-temporal store keeps it from evicting
-                    // the links and neighbour tiles the other blocks still
-                    // read from L2
-                    __builtin_nontemporal_store(f2o{re, im}, (f2o*)&o[comp * V]);
+                    st_nt(&o[comp * V], re, im);
                 }
         };
         if (ad) fin(std::true_type{});
