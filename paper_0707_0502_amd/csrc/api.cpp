@@ -94,6 +94,25 @@ void stats_reset(gdr_stats* st) {
     st->resid_main = 0;
 }
 
+bool finite_shifts(gdr_ctx_s* c, const gdr_c64* sigma, int ns) {
+    for (int i = 0; i < ns; ++i)
+        if (!std::isfinite(sigma[i].re) || !std::isfinite(sigma[i].im)) {
+            c->err = "shift " + std::to_string(i) + " is not finite";
+            return false;
+        }
+    return true;
+}
+
+// every right-hand side must have a finite norm (a NaN or Inf entry, or an
+// overflowing norm, is rejected before any solve starts)
+void check_rhs(gdr_op_s* op, const double2* Beo, int nrhs) {
+    const std::vector<double> r = norms_of(op, Beo, nrhs);
+    for (int j = 0; j < nrhs; ++j)
+        if (!std::isfinite(r[j]))
+            throw GdrError(GDR_ERR_ARG, "right-hand side " + std::to_string(j) +
+                                            " is not finite (||b|| = " + std::to_string(r[j]) + ")");
+}
+
 template <typename T>
 void dslash_bench_run(gdr_op op, int nvec, int nsets, int reps, double* ms_each) {
     using C = typename CT<T>::t;
@@ -148,6 +167,21 @@ void dslash_bench_run(gdr_op op, int nvec, int nsets, int reps, double* ms_each)
         return fail((c), GDR_ERR_HIP, e.what());                    \
     }
 
+namespace gdr {
+// A vector argument must be device memory of the context's device (or
+// managed memory): a host pointer handed to a kernel would fault the GPU.
+bool device_ptr(const void* p, int device) {
+    hipPointerAttribute_t a{};
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    if (a.type == hipMemoryTypeUnregistered || a.type == hipMemoryTypeHost) return false;
+    if (a.type == hipMemoryTypeDevice && a.device != device) return false;
+    return true;
+}
+}  // namespace gdr
+
 extern "C" {
 
 int gdr_ctx_create(int device, void* hip_stream, gdr_ctx* out) {
@@ -166,16 +200,7 @@ int gdr_ctx_create(int device, void* hip_stream, gdr_ctx* out) {
         gdr_ctx_destroy(c);
         return GDR_ERR_HIP;
     }
-    {
-        // keep at most half of the device's memory idle in the cache: enough
-        // for every phase of a 32^3x64 solve (about 130 GB) to find its
-        // buffers again in the next solve. A block released to the driver is
-        // expensive to get back: after large frees, hipMalloc of a multi-GB
-        // block has taken 0.3-0.9 s. An allocation that fails releases the
-        // whole idle cache and is retried once.
-        size_t fr = 0, tot = 0;
-        if (hipMemGetInfo(&fr, &tot) == hipSuccess) c->pool.cap = tot / 2;
-    }
+    c->pool.attach(device);
     *out = c;
     return GDR_OK;
 }
@@ -190,7 +215,7 @@ void gdr_ctx_destroy(gdr_ctx c) {
     if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
     (void)hipStreamSynchronize(c->st);
-    c->pool.release();
+    c->pool.detach();
     delete c;
 }
 
@@ -232,6 +257,10 @@ int gdr_wilson_create(gdr_ctx c, const int dims[4], const int bc[4], double kapp
     if (!std::isfinite(kappa)) return fail(c, GDR_ERR_ARG, "kappa not finite");
     const int64_t vol = (int64_t)dims[0] * dims[1] * dims[2] * dims[3];
     if (vol > (int64_t)1 << 30) return fail(c, GDR_ERR_ARG, "lattice too large");
+    if (links_on_device != 0 && links_on_device != 1)
+        return fail(c, GDR_ERR_ARG, "links_on_device must be 0 or 1");
+    if (links_on_device && !device_ptr(links, c->device))
+        return fail(c, GDR_ERR_ARG, "links_on_device = 1 but links is not device memory of the context's device");
     gdr_op_s* op = new gdr_op_s;
     API_TRY(c)
     HIPCHK(hipSetDevice(c->device));
@@ -343,6 +372,8 @@ int gdr_op_apply(gdr_op op, gdr_c64 sigma, const gdr_c64* x, gdr_c64* y, int nve
     if (precision != GDR_PREC_F64 && precision != GDR_PREC_F32)
         return fail(c, GDR_ERR_ARG, "precision must be F64 or F32");
     if (nvec == 0) return GDR_OK;
+    if (!device_ptr(x, c->device) || !device_ptr(y, c->device))
+        return fail(c, GDR_ERR_ARG, "x and y must be device memory of the context's device");
     API_TRY(c)
     HIPCHK(hipSetDevice(c->device));
     const int64_t n = op->n;
@@ -433,8 +464,10 @@ static double finish_stats(gdr_op op, gdr_stats* st, int ns, const double2* sig,
         Timer tv;
         std::vector<double> r;
         true_residuals(op, ns, sig, nrhs, Beo, Xeo, r);
+        // a NaN residual propagates (and fails every "<= tol" test)
         rmax = 0;
-        for (double v : r) rmax = std::max(rmax, v);
+        for (double v : r)
+            if (std::isnan(v) || v > rmax) rmax = v;
         if (st) {
             if (st->resid) std::memcpy(st->resid, r.data(), r.size() * sizeof(double));
             st->t_phase[5] += tv.sec();
@@ -445,13 +478,27 @@ static double finish_stats(gdr_op op, gdr_stats* st, int ns, const double2* sig,
     return rmax;
 }
 
+// vector arguments of the solvers: device memory of the context's device
+static bool solve_ptrs_ok(gdr_ctx_s* c, const void* b, const void* x) {
+    if (device_ptr(b, c->device) && device_ptr(x, c->device)) return true;
+    c->err = "right-hand sides and solutions must be device memory of the context's device";
+    return false;
+}
+
+// status of a finished solve: GDR_OK only if every final FP64 true residual
+// is at most tol (a NaN residual is not)
+static int final_status(int rc, double rmax, double tol) {
+    return (rc == GDR_OK && !(rmax <= tol)) ? GDR_NOT_CONVERGED : rc;
+}
+
 int gdr_solve_dr_sh(gdr_op op, int ns, const gdr_c64* sigma, const gdr_c64* b, gdr_c64* x,
                     const gdr_params* p, gdr_stats* st, gdr_defl* defl_out) {
     if (!op) return GDR_ERR_ARG;
     gdr_ctx_s* c = op->ctx;
     if (!sigma || !b || !x) return fail(c, GDR_ERR_ARG, "null argument");
     if (defl_out) *defl_out = nullptr;
-    if (!check_params(c, p, ns, true)) return GDR_ERR_ARG;
+    if (!check_params(c, p, ns, true) || !finite_shifts(c, sigma, ns) || !solve_ptrs_ok(c, b, x))
+        return GDR_ERR_ARG;
     stats_reset(st);
     API_TRY(c)
     HIPCHK(hipSetDevice(c->device));
@@ -461,8 +508,15 @@ int gdr_solve_dr_sh(gdr_op op, int ns, const gdr_c64* sigma, const gdr_c64* b, g
     double2* beo = mem.get<double2>(n);
     double2* Xeo = mem.get<double2>((size_t)ns * n);
     op_pack<double>(op, (const double2*)b, beo, n, 1, c->st);
+    check_rhs(op, beo, 1);
     Stats S(st, (unsigned)p->profile, c->st, &c->evpool);
     gdr_defl_s* d = nullptr;
+    // owns the deflation pair until it is handed to the caller (every error
+    // path below releases it)
+    struct Own {
+        gdr_defl_s*& d;
+        ~Own() { delete d; }
+    } own{d};
     bool conv = false;
     Timer tdr;
     int rc = solve_dr_sh(op, ns, (const double2*)sigma, beo, Xeo, *p, S, &d, &conv);
@@ -473,14 +527,16 @@ int gdr_solve_dr_sh(gdr_op op, int ns, const gdr_c64* sigma, const gdr_c64* b, g
         if (st) st->t_phase[4] += tc.sec();
     }
     S.flush();
-    if (finish_stats(op, st, ns, (const double2*)sigma, 1, beo, Xeo, t, p->precision) > p->tol &&
-        rc == GDR_OK)
-        rc = GDR_NOT_CONVERGED;
+    rc = final_status(rc, finish_stats(op, st, ns, (const double2*)sigma, 1, beo, Xeo, t,
+                                       p->precision),
+                      p->tol);
     op_unpack<double>(op, Xeo, n, (double2*)x, ns, c->st);
     HIPCHK(hipStreamSynchronize(c->st));
     if (st) st->t_total = t.sec();
-    if (defl_out) *defl_out = d;
-    else delete d;
+    if (defl_out) {
+        *defl_out = d;
+        d = nullptr;
+    }
     return rc;
     API_CATCH(c)
 }
@@ -491,7 +547,8 @@ int gdr_solve_proj_sh(gdr_op op, gdr_defl defl, int ns, const gdr_c64* sigma, in
     gdr_ctx_s* c = op->ctx;
     if (!defl || !sigma || !B || !X || nrhs < 1) return fail(c, GDR_ERR_ARG, "null argument or nrhs < 1");
     if (defl->op != op) return fail(c, GDR_ERR_STATE, "deflation handle belongs to another operator");
-    if (!check_params(c, p, ns, false)) return GDR_ERR_ARG;
+    if (!check_params(c, p, ns, false) || !finite_shifts(c, sigma, ns) || !solve_ptrs_ok(c, B, X))
+        return GDR_ERR_ARG;
     stats_reset(st);
     API_TRY(c)
     HIPCHK(hipSetDevice(c->device));
@@ -501,6 +558,7 @@ int gdr_solve_proj_sh(gdr_op op, gdr_defl defl, int ns, const gdr_c64* sigma, in
     double2* Beo = mem.get<double2>((size_t)nrhs * n);
     double2* Xeo = mem.get<double2>((size_t)nrhs * ns * n);
     op_pack<double>(op, (const double2*)B, Beo, n, nrhs, c->st);
+    check_rhs(op, Beo, nrhs);
     Stats S(st, (unsigned)p->profile, c->st, &c->evpool);
     int rc = solve_proj_batch(op, defl, ns, (const double2*)sigma, nrhs, Beo, Xeo, 0, *p, S);
     if (p->precision == GDR_PREC_MIXED) {
@@ -509,10 +567,9 @@ int gdr_solve_proj_sh(gdr_op op, gdr_defl defl, int ns, const gdr_c64* sigma, in
         if (st) st->t_phase[4] += tc.sec();
     }
     S.flush();
-    if (finish_stats(op, st, ns, (const double2*)sigma, nrhs, Beo, Xeo, t, p->precision) >
-            p->tol &&
-        rc == GDR_OK)
-        rc = GDR_NOT_CONVERGED;
+    rc = final_status(rc, finish_stats(op, st, ns, (const double2*)sigma, nrhs, Beo, Xeo, t,
+                                       p->precision),
+                      p->tol);
     op_unpack<double>(op, Xeo, n, (double2*)X, nrhs * ns, c->st);
     HIPCHK(hipStreamSynchronize(c->st));
     if (st) st->t_total = t.sec();
@@ -525,7 +582,8 @@ int gdr_solve(gdr_op op, int ns, const gdr_c64* sigma, int nrhs, const gdr_c64* 
     if (!op) return GDR_ERR_ARG;
     gdr_ctx_s* c = op->ctx;
     if (!sigma || !B || !X || nrhs < 1) return fail(c, GDR_ERR_ARG, "null argument or nrhs < 1");
-    if (!check_params(c, p, ns, true)) return GDR_ERR_ARG;
+    if (!check_params(c, p, ns, true) || !finite_shifts(c, sigma, ns) || !solve_ptrs_ok(c, B, X))
+        return GDR_ERR_ARG;
     stats_reset(st);
     API_TRY(c)
     HIPCHK(hipSetDevice(c->device));
@@ -535,17 +593,18 @@ int gdr_solve(gdr_op op, int ns, const gdr_c64* sigma, int nrhs, const gdr_c64* 
     double2* Beo = mem.get<double2>((size_t)nrhs * n);
     double2* Xeo = mem.get<double2>((size_t)nrhs * ns * n);
     op_pack<double>(op, (const double2*)B, Beo, n, nrhs, c->st);
+    check_rhs(op, Beo, nrhs);
     Stats S(st, (unsigned)p->profile, c->st, &c->evpool);
     gdr_defl_s* d = nullptr;
+    struct Own {
+        gdr_defl_s*& d;
+        ~Own() { delete d; }
+    } own{d};
     bool conv = false;
     Timer tdr;
     int rc = solve_dr_sh(op, ns, (const double2*)sigma, Beo, Xeo, *p, S, &d, &conv);
     HIPCHK(hipStreamSynchronize(c->st));
     if (st) st->t_phase[0] += tdr.sec();
-    struct Guard {
-        gdr_defl_s* d;
-        ~Guard() { delete d; }
-    } guard{d};
     if (nrhs > 1) {
         if (!d) throw GdrError(GDR_ERR_BREAKDOWN, "first solve ended in a lucky breakdown: no deflation space");
         int rc2 = solve_proj_batch(op, d, ns, (const double2*)sigma, nrhs - 1, Beo + n,
@@ -558,10 +617,9 @@ int gdr_solve(gdr_op op, int ns, const gdr_c64* sigma, int nrhs, const gdr_c64* 
         if (st) st->t_phase[4] += tc.sec();
     }
     S.flush();
-    if (finish_stats(op, st, ns, (const double2*)sigma, nrhs, Beo, Xeo, t, p->precision) >
-            p->tol &&
-        rc == GDR_OK)
-        rc = GDR_NOT_CONVERGED;
+    rc = final_status(rc, finish_stats(op, st, ns, (const double2*)sigma, nrhs, Beo, Xeo, t,
+                                       p->precision),
+                      p->tol);
     op_unpack<double>(op, Xeo, n, (double2*)X, nrhs * ns, c->st);
     HIPCHK(hipStreamSynchronize(c->st));
     if (st) st->t_total = t.sec();
@@ -575,6 +633,8 @@ int gdr_defl_export(gdr_defl d, gdr_c64* V, gdr_c64* Hbar) {
     if (!d) return GDR_ERR_ARG;
     gdr_op_s* op = d->op;
     gdr_ctx_s* c = op->ctx;
+    if (V && !device_ptr(V, c->device))
+        return fail(c, GDR_ERR_ARG, "V must be device memory of the context's device");
     API_TRY(c)
     HIPCHK(hipSetDevice(c->device));
     if (V) {
@@ -599,6 +659,11 @@ int gdr_defl_import(gdr_op op, int k, const gdr_c64* V, const gdr_c64* Hbar, int
     if (precision != GDR_PREC_F64 && precision != GDR_PREC_MIXED)
         return fail(c, GDR_ERR_ARG, "precision must be F64 or MIXED");
     *out = nullptr;
+    if (!device_ptr(V, c->device))
+        return fail(c, GDR_ERR_ARG, "V must be device memory of the context's device");
+    for (size_t i = 0; k > 0 && i < (size_t)(k + 1) * k; ++i)
+        if (!std::isfinite(Hbar[i].re) || !std::isfinite(Hbar[i].im))
+            return fail(c, GDR_ERR_ARG, "Hbar has a non-finite entry");
     gdr_defl_s* d = new gdr_defl_s;
     API_TRY(c)
     HIPCHK(hipSetDevice(c->device));

@@ -425,6 +425,7 @@ static int dr_run(gdr_op_s* op, int ns, const double2* sig_h, const double2* b_e
     HIPCHK(hipMemcpyAsync(sig, sig_h, ns * sizeof(double2), hipMemcpyHostToDevice, st));
 
     const double bnorm = vec_norm(op, b_eo);
+    if (!std::isfinite(bnorm)) throw GdrError(GDR_ERR_ARG, "right-hand side is not finite");
     HIPCHK(hipMemsetAsync(X, 0, (size_t)ns * n * sizeof(double2), st));
     if (!(bnorm > 0)) {
         *conv_out = true;
@@ -531,6 +532,8 @@ static int dr_run(gdr_op_s* op, int ns, const double2* sig_h, const double2* b_e
         for (int i = 1; i < ns; ++i) bmax = std::max(bmax, zabs(o.beta[i]));
         const double rmax = r1 * bmax;
         S.hist(0, cycles, mvps, o.snorm / bnorm, rmax);
+        if (!std::isfinite(rmax))
+            throw GdrError(GDR_ERR_BREAKDOWN, "GMRES-DR-Sh: non-finite residual norm");
         conv = rmax <= p.tol || brk >= 0;
         bool stop = conv;
         if (mixed && !conv) {
@@ -813,6 +816,8 @@ static void proj_run(gdr_op_s* op, gdr_defl_s* defl, int nmem, int ns,
             for (int i = 1; i < ns; ++i) bmax = std::max(bmax, zabs(oh[b].beta[i]));
             const double r1 = rn / bnorm[b];
             const double rmax = r1 * bmax;
+            if (!std::isfinite(rmax))
+                throw GdrError(GDR_ERR_BREAKDOWN, "GMRES-Proj-Sh: non-finite residual norm");
             worst = std::max(worst, rmax);
             worst_r1 = std::max(worst_r1, r1);
             for (int i = 0; i < ns; ++i) R.beta[(size_t)b * ns + i] = oh[b].beta[i];
@@ -1013,6 +1018,8 @@ static int proj_batch(gdr_op_s* op, gdr_defl_s* d, int ns, const double2* sig_h,
                 phase[b] = 2 + ids[b];
             }
             bnorm[b] = vec_norm(op, Bm + b * n);
+            if (!std::isfinite(bnorm[b]))
+                throw GdrError(GDR_ERR_ARG, "right-hand side is not finite");
             if (!(bnorm[b] > 0)) bnorm[b] = 1;
             for (int i = 0; i < ns; ++i) sgm[(size_t)b * ns + i] = sig_h[i];
         }
@@ -1129,7 +1136,7 @@ static void residual_vectors(gdr_op_s* op, int ns, const double2* sig, const dou
     }
 }
 
-static std::vector<double> norms(gdr_op_s* op, const double2* R, int nv) {
+std::vector<double> norms_of(gdr_op_s* op, const double2* R, int nv) {
     hipStream_t st = op->ctx->st;
     DMem mem;
     const int nblk = cgs_nblk(op->n);
@@ -1154,7 +1161,7 @@ void true_residuals(gdr_op_s* op, int ns, const double2* sig, int nrhs, const do
     for (int j = 0; j < nrhs; ++j) {
         const double bn = vec_norm(op, B_eo + (int64_t)j * n);
         residual_vectors(op, ns, sig, B_eo + (int64_t)j * n, X_eo + (int64_t)j * ns * n, R);
-        auto rn = norms(op, R, ns);
+        auto rn = norms_of(op, R, ns);
         for (int i = 0; i < ns; ++i) resid[(size_t)j * ns + i] = bn > 0 ? rn[i] / bn : rn[i];
     }
 }
@@ -1183,12 +1190,14 @@ int cleanup(gdr_op_s* op, gdr_defl_s* defl, int ns, const double2* sig, int nrhs
         std::vector<Pair> todo;
         for (int j = 0; j < nrhs; ++j) {
             residual_vectors(op, ns, sig, B_eo + (int64_t)j * n, X_eo + (int64_t)j * ns * n, R);
-            auto rn = norms(op, R, ns);
+            auto rn = norms_of(op, R, ns);
             if (S.st) S.st->mvp_fp64 += ns;
             for (int i = 0; i < ns; ++i) {
-                const double rel = bn[j] > 0 ? rn[i] / bn[j] : 0;
+                const double rel = bn[j] > 0 ? rn[i] / bn[j] : rn[i];
+                if (!std::isfinite(rel))
+                    throw GdrError(GDR_ERR_BREAKDOWN, "mixed-precision cleanup: non-finite true residual");
                 if (round == 0 && S.st) S.st->resid_main = std::max(S.st->resid_main, rel);
-                if (rel > p.tol) todo.push_back({j, i, rel});
+                if (!(rel <= p.tol)) todo.push_back({j, i, rel});
             }
         }
         if (todo.empty() || round == p.max_refine) {

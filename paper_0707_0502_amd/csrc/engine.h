@@ -3,6 +3,7 @@
 
 #include <list>
 #include <map>
+#include <mutex>
 #include <new>
 #include <stdexcept>
 #include <unordered_map>
@@ -30,81 +31,44 @@ namespace gdr {
 // Device memory cache of a context. Solves allocate their work buffers per
 // call; returning them here instead of to the driver lets the next call (or
 // the next batch of the same call) reuse them without mapping new memory.
-// Best fit within +25 % (sizes rounded up to 2 MiB); at most `cap` bytes stay
-// idle, the least recently returned blocks going back to the driver first; a
-// failed allocation releases every idle block and retries once. Blocks are
-// only reused in stream order on the context's stream.
+// Best fit within +25 % (sizes rounded up to 2 MiB). The idle blocks of all
+// contexts on one device together stay below half of the device's memory:
+// returning a block past that releases the returning context's least
+// recently returned blocks. An allocation that fails releases the context's
+// own idle blocks and retries, then the idle blocks of every other context
+// on the device and retries once more. Blocks are only reused in stream
+// order on the owning context's stream; hipFree, which releases an idle
+// block of another context, waits for the device. Thread safe: one mutex
+// per cache, and a registry of the live caches per process.
 struct DevPool {
     struct Idle {
         size_t sz;
         void* p;
     };
+    std::mutex mu;
     std::list<Idle> lru;   // idle blocks, least recently returned first
     std::multimap<size_t, std::list<Idle>::iterator> bysize;
     std::unordered_map<void*, size_t> used;
     size_t idle_bytes = 0;
-    size_t cap = 0;
+    int device = -1;
+    // join the registry of `dev` (the device must be current)
+    void attach(int dev);
+    // leave the registry and release every idle block
+    void detach();
+    void* get(size_t bytes);   // throws std::bad_alloc
+    void put(void* p);
+    size_t release();          // idle blocks back to the driver; returns their bytes
     static size_t round(size_t b) {
         const size_t g = b >= (1u << 20) ? (size_t)2 << 20 : (size_t)4 << 10;
         return (b + g - 1) / g * g;
     }
-    void drop(std::multimap<size_t, std::list<Idle>::iterator>::iterator it, bool to_driver) {
-        auto li = it->second;
-        idle_bytes -= li->sz;
-        if (to_driver) (void)hipFree(li->p);
-        lru.erase(li);
-        bysize.erase(it);
-    }
-    void* get(size_t bytes) {
-        bytes = round(bytes);
-        auto it = bysize.lower_bound(bytes);
-        if (it != bysize.end() && it->first <= bytes + bytes / 4) {
-            void* p = it->second->p;
-            used[p] = it->first;
-            drop(it, false);
-            return p;
-        }
-        void* p = nullptr;
-        if (hipMalloc(&p, bytes) != hipSuccess) {
-            (void)hipGetLastError();
-            release();
-            if (hipMalloc(&p, bytes) != hipSuccess) {
-                (void)hipGetLastError();
-                throw std::bad_alloc();
-            }
-        }
-        used[p] = bytes;
-        return p;
-    }
-    void put(void* p) {
-        auto u = used.find(p);
-        if (u == used.end()) return;
-        const size_t sz = u->second;
-        used.erase(u);
-        if (sz > cap) {
-            (void)hipFree(p);
-            return;
-        }
-        lru.push_back({sz, p});
-        bysize.emplace(sz, std::prev(lru.end()));
-        idle_bytes += sz;
-        while (idle_bytes > cap) {
-            auto oldest = lru.begin();
-            auto range = bysize.equal_range(oldest->sz);
-            for (auto it = range.first; it != range.second; ++it)
-                if (it->second == oldest) {
-                    drop(it, true);
-                    break;
-                }
-        }
-    }
-    void release() {
-        for (auto& b : lru) (void)hipFree(b.p);
-        lru.clear();
-        bysize.clear();
-        idle_bytes = 0;
-    }
+
+   private:
+    void drop_oldest();   // mu held
 };
+// idle bytes of every cache on `dev`, and their cap
+size_t pool_idle_bytes(int dev);
+size_t pool_idle_cap(int dev);
 }  // namespace gdr
 
 struct gdr_ctx_s {
@@ -339,6 +303,10 @@ void true_residuals(gdr_op_s* op, int ns, const double2* sig, int nrhs, const do
 // mixed-precision cleanup: FP64-refined single-shift GMRES(m)-Proj(k) per (shift, RHS)
 int cleanup(gdr_op_s* op, gdr_defl_s* defl, int ns, const double2* sig, int nrhs,
             const double2* B_eo, double2* X_eo, const gdr_params& p, Stats& S);
+// true if p is device (or managed) memory usable on `device`
+bool device_ptr(const void* p, int device);
 double vec_norm(gdr_op_s* op, const double2* x);
+// 2-norms of nv FP64 vectors stored n apart
+std::vector<double> norms_of(gdr_op_s* op, const double2* X, int nv);
 
 }  // namespace gdr

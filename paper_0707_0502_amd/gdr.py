@@ -135,6 +135,53 @@ def _ptr(t):
     raise TypeError(type(t))
 
 
+def _dev(t, name, numel):
+    """Address of a device vector argument, after the checks the C-ABI relies
+    on: a contiguous CUDA complex128 tensor of exactly `numel` entries (the
+    library reads and writes that many; a host buffer would fault the GPU)."""
+    if not (hasattr(t, "is_cuda") and t.is_cuda):
+        raise TypeError("%s must be a CUDA tensor (device memory), got %s" % (name, type(t).__name__))
+    if str(t.dtype) != "torch.complex128":
+        raise TypeError("%s must be complex128, got %s" % (name, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if numel is not None and t.numel() != numel:
+        raise ValueError("%s has %d entries, expected %d" % (name, t.numel(), numel))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _host(a, name, numel):
+    """Address of a host complex128 array argument of exactly `numel` entries."""
+    if not isinstance(a, np.ndarray):
+        raise TypeError("%s must be a numpy array (host memory), got %s" % (name, type(a).__name__))
+    if a.dtype != np.complex128:
+        raise TypeError("%s must be complex128, got %s" % (name, a.dtype))
+    if not a.flags["C_CONTIGUOUS"]:
+        raise ValueError("%s must be C-contiguous" % name)
+    if a.size != numel:
+        raise ValueError("%s has %d entries, expected %d" % (name, a.size, numel))
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _nrhs(B, n):
+    """Number of right-hand sides in the device tensor B (a positive multiple of n entries)."""
+    if not (hasattr(B, "is_cuda") and B.is_cuda):
+        raise TypeError("B must be a CUDA tensor (device memory), got %s" % type(B).__name__)
+    if B.numel() == 0 or B.numel() % n:
+        raise ValueError("B has %d entries, not a positive multiple of n = %d" % (B.numel(), n))
+    return B.numel() // n
+
+
+def _stats(stats, nrhs, ns):
+    """The gdr_stats pointer of a Stats object sized for nrhs x ns residuals."""
+    if stats is None:
+        return None
+    if stats.resid.shape != (nrhs, ns):
+        raise ValueError("Stats holds %s residuals, the solve writes (%d, %d)"
+                         % (stats.resid.shape, nrhs, ns))
+    return ctypes.byref(stats.s)
+
+
 def _sig(sigmas):
     arr = (gdr_c64 * len(sigmas))()
     for i, s in enumerate(sigmas):
@@ -230,11 +277,15 @@ def gdr_last_error(ctx):
 
 def gdr_wilson_create(ctx, dims, bc, kappa, links, link_storage=GDR_LINKS_F32):
     """links: numpy (host) or torch (device) complex128 [4][Lt][Lz][Ly][Lx][3][3]."""
+    if len(dims) != 4 or len(bc) != 4:
+        raise ValueError("dims and bc need 4 entries")
     d = (ctypes.c_int * 4)(*dims)
     b = (ctypes.c_int * 4)(*bc)
     on_dev = int(hasattr(links, "is_cuda") and links.is_cuda)
+    nl = 36 * int(np.prod(dims))
+    ptr = _dev(links, "links", nl) if on_dev else _host(links, "links", nl)
     h = ctypes.c_void_p()
-    ctx.check(lib().gdr_wilson_create(ctx.h, d, b, float(kappa), _ptr(links), on_dev,
+    ctx.check(lib().gdr_wilson_create(ctx.h, d, b, float(kappa), ptr, on_dev,
                                       link_storage, ctypes.byref(h)))
     return Op(ctx, h, dims)
 
@@ -259,8 +310,9 @@ def gdr_op_size(op):
 
 def gdr_op_apply(op, sigma, x, y, nvec=1, precision=GDR_PREC_F64):
     s = complex(sigma)
-    return op.ctx.check(lib().gdr_op_apply(op.h, gdr_c64(s.real, s.imag), _ptr(x), _ptr(y),
-                                           nvec, precision))
+    want = nvec * op.n if nvec > 0 else None   # nvec = 0 touches nothing
+    px, py = _dev(x, "x", want), _dev(y, "y", want)
+    return op.ctx.check(lib().gdr_op_apply(op.h, gdr_c64(s.real, s.imag), px, py, nvec, precision))
 
 
 def gdr_op_tables(op):
@@ -281,25 +333,32 @@ def gdr_op_dslash_bench(op, precision, nvec, nsets, reps):
 
 
 def gdr_solve_dr_sh(op, sigmas, b, x, params, stats=None, want_defl=True):
+    ns = len(sigmas)
+    pb, px = _dev(b, "b", op.n), _dev(x, "x", ns * op.n)
+    pst = _stats(stats, 1, ns)
     h = ctypes.c_void_p()
     rc = op.ctx.check(lib().gdr_solve_dr_sh(
-        op.h, len(sigmas), _sig(sigmas), _ptr(b), _ptr(x), ctypes.byref(params),
-        ctypes.byref(stats.s) if stats else None, ctypes.byref(h) if want_defl else None))
+        op.h, ns, _sig(sigmas), pb, px, ctypes.byref(params), pst,
+        ctypes.byref(h) if want_defl else None))
     return rc, (Defl(op, h) if want_defl and h.value else None)
 
 
 def gdr_solve_proj_sh(op, defl, sigmas, B, X, params, stats=None):
-    nrhs = B.numel() // op.n if hasattr(B, "numel") else B.size // op.n
+    ns = len(sigmas)
+    nrhs = _nrhs(B, op.n)
+    pB, pX = _dev(B, "B", nrhs * op.n), _dev(X, "X", nrhs * ns * op.n)
+    pst = _stats(stats, nrhs, ns)
     return op.ctx.check(lib().gdr_solve_proj_sh(
-        op.h, defl.h, len(sigmas), _sig(sigmas), nrhs, _ptr(B), _ptr(X), ctypes.byref(params),
-        ctypes.byref(stats.s) if stats else None))
+        op.h, defl.h, ns, _sig(sigmas), nrhs, pB, pX, ctypes.byref(params), pst))
 
 
 def gdr_solve(op, sigmas, B, X, params, stats=None):
-    nrhs = B.numel() // op.n if hasattr(B, "numel") else B.size // op.n
+    ns = len(sigmas)
+    nrhs = _nrhs(B, op.n)
+    pB, pX = _dev(B, "B", nrhs * op.n), _dev(X, "X", nrhs * ns * op.n)
+    pst = _stats(stats, nrhs, ns)
     return op.ctx.check(lib().gdr_solve(
-        op.h, len(sigmas), _sig(sigmas), nrhs, _ptr(B), _ptr(X), ctypes.byref(params),
-        ctypes.byref(stats.s) if stats else None))
+        op.h, ns, _sig(sigmas), nrhs, pB, pX, ctypes.byref(params), pst))
 
 
 def gdr_defl_k(defl):
@@ -307,13 +366,19 @@ def gdr_defl_k(defl):
 
 
 def gdr_defl_export(defl, V=None, Hbar=None):
-    return defl.op.ctx.check(lib().gdr_defl_export(
-        defl.h, _ptr(V) if V is not None else None, _ptr(Hbar) if Hbar is not None else None))
+    """V: device tensor of (k+1)*n entries; Hbar: host array of (k+1)*k entries
+    (column-major); either may be None."""
+    k = gdr_defl_k(defl)
+    pV = _dev(V, "V", (k + 1) * defl.op.n) if V is not None else None
+    pH = _host(Hbar, "Hbar", (k + 1) * k) if Hbar is not None else None
+    return defl.op.ctx.check(lib().gdr_defl_export(defl.h, pV, pH))
 
 
 def gdr_defl_import(op, k, V, Hbar, precision=GDR_PREC_F64):
+    pV = _dev(V, "V", (k + 1) * op.n)
+    pH = _host(Hbar, "Hbar", (k + 1) * k)
     h = ctypes.c_void_p()
-    op.ctx.check(lib().gdr_defl_import(op.h, k, _ptr(V), _ptr(Hbar), precision, ctypes.byref(h)))
+    op.ctx.check(lib().gdr_defl_import(op.h, k, pV, pH, precision, ctypes.byref(h)))
     return Defl(op, h)
 
 

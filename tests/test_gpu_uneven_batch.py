@@ -30,18 +30,27 @@ def _have_kappas():
     return True
 
 
-@pytest.mark.skipif(not _have_kappas(), reason="kappa_c of the batch's fields not in the manifest")
-def test_uneven_batch_concurrent():
-    from paper_0707_0502_amd import gdr
-    torch = torch_mod()
-    runs = []
+@pytest.fixture(scope="module")
+def inputs():
+    if not _have_kappas():
+        pytest.skip("kappa_c of the batch's fields not in the manifest")
+    out = []
     for name in synth.C5_GROUP:
         cfg = synth.CONFIGS[name]
         links = synth.gauge_links(cfg["dims"], cfg["eps"], cfg["seed"])
         B = np.stack([synth.make_rhs(cfg, k, s).ravel() for k, s in cfg["rhs"]])
-        runs.append(dict(name=name, cfg=cfg, links=links, B=B, kappa=synth.kappa(name)))
+        out.append(dict(name=name, cfg=cfg, links=links, B=B, kappa=synth.kappa(name)))
     say("inputs ready")
-    for r in runs:
+    return out
+
+
+def _make_runs(inputs, prec):
+    """One context, stream and operator per lattice, inputs on the device."""
+    from paper_0707_0502_amd import gdr
+    torch = torch_mod()
+    runs = []
+    for src in inputs:
+        r = dict(src)
         cfg = r["cfg"]
         r["stream"] = torch.cuda.Stream()
         r["ctx"] = gdr.gdr_ctx_create(0, r["stream"].cuda_stream)
@@ -56,11 +65,21 @@ def test_uneven_batch_concurrent():
         r["st"] = gdr.Stats(len(cfg["rhs"]), len(cfg["sigmas"]))
         r["p"] = gdr.gdr_params_default(m_dr=cfg["m_dr"], k=cfg["k"], m_proj=cfg["m_proj"],
                                         tol=cfg["tol"], tol_extra=cfg["tol_extra"],
-                                        precision=gdr.GDR_PREC_MIXED, use_graph=1)
+                                        precision=prec, use_graph=1)
+        runs.append(r)
+    return runs
+
+
+def _solve_concurrently(runs):
+    from paper_0707_0502_amd import gdr
 
     def solve(r):
         t0 = time.perf_counter()
-        r["rc"] = gdr.gdr_solve(r["op"], r["cfg"]["sigmas"], r["Bd"], r["X"], r["p"], r["st"])
+        try:
+            r["rc"] = gdr.gdr_solve(r["op"], r["cfg"]["sigmas"], r["Bd"], r["X"], r["p"], r["st"])
+        except gdr.GdrError as e:
+            r["rc"] = e.code
+            r["err"] = str(e)
         r["sec"] = time.perf_counter() - t0
 
     threads = [threading.Thread(target=solve, args=(r,)) for r in runs]
@@ -69,12 +88,27 @@ def test_uneven_batch_concurrent():
         t.start()
     for t in threads:
         t.join()
-    wall = time.perf_counter() - t0
+    return time.perf_counter() - t0
+
+
+def _drop(runs):
+    from paper_0707_0502_amd import gdr
+    torch_mod().cuda.synchronize()
+    for r in runs:
+        gdr.gdr_op_destroy(r["op"])
+        gdr.gdr_ctx_destroy(r["ctx"])
+
+
+def test_uneven_batch_concurrent(inputs):
+    from paper_0707_0502_amd import gdr
+    runs = _make_runs(inputs, gdr.GDR_PREC_MIXED)
+    wall = _solve_concurrently(runs)
     say("concurrent wall %.2f s; per solve" % wall,
         {r["name"]: round(r["sec"], 2) for r in runs})
     for r in runs:
         cfg = r["cfg"]
-        say(r["name"], "rc", r["rc"], "max resid %.2e" % r["st"].resid.max(), r["st"].as_dict())
+        say(r["name"], "rc", r["rc"], r.get("err", ""), "max resid %.2e" % r["st"].resid.max(),
+            r["st"].as_dict())
         assert r["rc"] == gdr.GDR_OK
         assert r["st"].resid.max() <= cfg["tol"]
         # independent check with the oracle's operator
@@ -88,6 +122,50 @@ def test_uneven_batch_concurrent():
             res = np.linalg.norm(gmres.true_residual(A, r["B"][j], X[j, i], cfg["sigmas"][i]))
             res /= np.linalg.norm(r["B"][j])
             assert res <= cfg["tol"] * 1.01, (r["name"], j, i, res)
-    for r in runs:
-        gdr.gdr_op_destroy(r["op"])
-        gdr.gdr_ctx_destroy(r["ctx"])
+    _drop(runs)
+
+
+def test_contexts_share_the_device_cache(inputs):
+    """Many live contexts on one device: three contexts solve the 16^3x32
+    workload in turn, then the whole batch runs in plain FP64 on eleven
+    contexts of its own, then in mixed precision on eleven more, every
+    context staying alive with its idle cache. The idle blocks of all
+    contexts share one cap, and an allocation that fails releases the other
+    contexts' idle blocks, so no solve runs out of device memory."""
+    from paper_0707_0502_amd import gdr
+    torch = torch_mod()
+    cfg = synth.CONFIGS["C3"]
+    links = synth.gauge_links(cfg["dims"], cfg["eps"], cfg["seed"])
+    b = synth.make_rhs(cfg, *cfg["rhs"][0]).ravel()
+    kappa = synth.kappa("C3")
+    first = []
+    for i in range(3):
+        c = gdr.gdr_ctx_create(0, torch.cuda.current_stream().cuda_stream)
+        op = gdr.gdr_wilson_create(c, cfg["dims"], (1, 1, 1, -1), kappa, links)
+        n, ns = op.n, len(cfg["sigmas"])
+        st = gdr.Stats(1, ns)
+        p = gdr.gdr_params_default(m_dr=cfg["m_dr"], k=cfg["k"], m_proj=cfg["m_proj"],
+                                   tol=cfg["tol"], precision=gdr.GDR_PREC_MIXED)
+        rc, d = gdr.gdr_solve_dr_sh(op, cfg["sigmas"], torch.from_numpy(b).cuda(),
+                                    torch.zeros(ns * n, dtype=torch.complex128, device="cuda"),
+                                    p, st, want_defl=False)
+        say("16^3x32 on context", i, "rc", rc, "max resid %.2e" % st.resid.max())
+        assert rc == gdr.GDR_OK
+        first.append((c, op))
+    say("device cache: idle bytes of the live contexts are capped device-wide")
+    runs64 = _make_runs(inputs, gdr.GDR_PREC_F64)
+    wall = _solve_concurrently(runs64)
+    say("FP64 batch wall %.2f s" % wall, {r["name"]: (r["rc"], r.get("err", "")) for r in runs64})
+    for r in runs64:
+        assert r["rc"] in (gdr.GDR_OK, gdr.GDR_NOT_CONVERGED), (r["name"], r.get("err"))
+    runs32 = _make_runs(inputs, gdr.GDR_PREC_MIXED)
+    wall = _solve_concurrently(runs32)
+    say("mixed batch wall %.2f s" % wall, {r["name"]: (r["rc"], r.get("err", "")) for r in runs32})
+    for r in runs32:
+        assert r["rc"] == gdr.GDR_OK, (r["name"], r.get("err"))
+        assert r["st"].resid.max() <= r["cfg"]["tol"]
+    _drop(runs32)
+    _drop(runs64)
+    for c, op in first:
+        gdr.gdr_op_destroy(op)
+        gdr.gdr_ctx_destroy(c)
