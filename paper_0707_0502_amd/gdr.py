@@ -176,7 +176,7 @@ def _stats(stats, nrhs, ns):
     """The gdr_stats pointer of a Stats object sized for nrhs x ns residuals."""
     if stats is None:
         return None
-    if stats.resid.shape != (nrhs, ns):
+    if ns > 0 and stats.resid.shape != (nrhs, ns):
         raise ValueError("Stats holds %s residuals, the solve writes (%d, %d)"
                          % (stats.resid.shape, nrhs, ns))
     return ctypes.byref(stats.s)
@@ -334,7 +334,8 @@ def gdr_op_dslash_bench(op, precision, nvec, nsets, reps):
 
 def gdr_solve_dr_sh(op, sigmas, b, x, params, stats=None, want_defl=True):
     ns = len(sigmas)
-    pb, px = _dev(b, "b", op.n), _dev(x, "x", ns * op.n)
+    # ns < 1 is the library's to reject (GDR_ERR_ARG); no size to check then
+    pb, px = _dev(b, "b", op.n), _dev(x, "x", ns * op.n if ns > 0 else None)
     pst = _stats(stats, 1, ns)
     h = ctypes.c_void_p()
     rc = op.ctx.check(lib().gdr_solve_dr_sh(
@@ -346,7 +347,7 @@ def gdr_solve_dr_sh(op, sigmas, b, x, params, stats=None, want_defl=True):
 def gdr_solve_proj_sh(op, defl, sigmas, B, X, params, stats=None):
     ns = len(sigmas)
     nrhs = _nrhs(B, op.n)
-    pB, pX = _dev(B, "B", nrhs * op.n), _dev(X, "X", nrhs * ns * op.n)
+    pB, pX = _dev(B, "B", nrhs * op.n), _dev(X, "X", nrhs * ns * op.n if ns > 0 else None)
     pst = _stats(stats, nrhs, ns)
     return op.ctx.check(lib().gdr_solve_proj_sh(
         op.h, defl.h, ns, _sig(sigmas), nrhs, pB, pX, ctypes.byref(params), pst))
@@ -355,7 +356,7 @@ def gdr_solve_proj_sh(op, defl, sigmas, B, X, params, stats=None):
 def gdr_solve(op, sigmas, B, X, params, stats=None):
     ns = len(sigmas)
     nrhs = _nrhs(B, op.n)
-    pB, pX = _dev(B, "B", nrhs * op.n), _dev(X, "X", nrhs * ns * op.n)
+    pB, pX = _dev(B, "B", nrhs * op.n), _dev(X, "X", nrhs * ns * op.n if ns > 0 else None)
     pst = _stats(stats, nrhs, ns)
     return op.ctx.check(lib().gdr_solve(
         op.h, ns, _sig(sigmas), nrhs, pB, pX, ctypes.byref(params), pst))
