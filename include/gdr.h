@@ -117,6 +117,20 @@ int64_t gdr_op_size(gdr_op op);
 int gdr_op_apply(gdr_op op, gdr_c64 sigma, const gdr_c64* x, gdr_c64* y, int nvec,
                  int precision);
 
+/* gdr_op_apply without any device allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same y_v = (A - sigma I) x_v, same
+ * layouts and arguments. Its internal-layout staging buffers live in one
+ * static 64 MiB device array per GPU (held until the process ends), so n is
+ * limited to 2^21 unknowns in FP64 (2^22 in FP32) - larger operators return
+ * GDR_ERR_ARG; more vectors than fit run in chunks. Every call on a GPU
+ * shares that GPU's array: calls that overlap on one GPU (from several
+ * threads or contexts) race and must be serialised by the caller. Nothing in
+ * the array needs to start cleared (each chunk is written before it is
+ * read). Errors: ARG, HIP. */
+int gdr_op_apply_noalloc(gdr_op op, gdr_c64 sigma, const gdr_c64* x, gdr_c64* y, int nvec,
+                         int precision);
+
 /* Test hook: the even-odd index of every lexicographic site
  * (eo = parity*V/2 + lex/2, lex = x + Lx(y + Ly(z + Lz t))), the neighbour
  * table nbr[eo][d] in even-odd positions for hops d = +x,+y,+z,+t,-x,-y,-z,-t

@@ -201,6 +201,11 @@ int gdr_ctx_create(int device, void* hip_stream, gdr_ctx* out) {
         return GDR_ERR_HIP;
     }
     c->pool.attach(device);
+    // the device address of gdr_op_apply_noalloc's static workspace
+    if (noalloc_setup(device) != GDR_OK) {
+        gdr_ctx_destroy(c);
+        return GDR_ERR_HIP;
+    }
     *out = c;
     return GDR_OK;
 }

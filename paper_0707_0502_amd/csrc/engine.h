@@ -303,6 +303,9 @@ void true_residuals(gdr_op_s* op, int ns, const double2* sig, int nrhs, const do
 // mixed-precision cleanup: FP64-refined single-shift GMRES(m)-Proj(k) per (shift, RHS)
 int cleanup(gdr_op_s* op, gdr_defl_s* defl, int ns, const double2* sig, int nrhs,
             const double2* B_eo, double2* X_eo, const gdr_params& p, Stats& S);
+// device address of gdr_op_apply_noalloc's static workspace on `device`,
+// looked up once per device (the device must be current); GDR_OK or GDR_ERR_HIP
+int noalloc_setup(int device);
 // true if p is device (or managed) memory usable on `device`
 bool device_ptr(const void* p, int device);
 double vec_norm(gdr_op_s* op, const double2* x);

@@ -31,7 +31,8 @@ K_CLASSES = ["dslash", "gs_project", "gs_update", "gs_close", "small", "combine"
 
 SYMBOLS = [
     "gdr_ctx_create", "gdr_ctx_destroy", "gdr_last_error", "gdr_wilson_create",
-    "gdr_op_destroy", "gdr_bidiag_create", "gdr_op_size", "gdr_op_apply", "gdr_op_tables", "gdr_op_dslash_bench",
+    "gdr_op_destroy", "gdr_bidiag_create", "gdr_op_size", "gdr_op_apply", "gdr_op_apply_noalloc",
+    "gdr_op_tables", "gdr_op_dslash_bench",
     "gdr_params_default",
     "gdr_solve_dr_sh", "gdr_solve_proj_sh", "gdr_solve", "gdr_defl_k", "gdr_defl_export",
     "gdr_defl_import", "gdr_defl_destroy",
@@ -93,6 +94,7 @@ def load(path=LIB_PATH):
     lib.gdr_op_size.argtypes = [vp]
     lib.gdr_op_size.restype = i64
     lib.gdr_op_apply.argtypes = [vp, gdr_c64, vp, vp, ip, ip]
+    lib.gdr_op_apply_noalloc.argtypes = [vp, gdr_c64, vp, vp, ip, ip]
     lib.gdr_op_tables.argtypes = [vp, vp, vp, vp]
     lib.gdr_op_dslash_bench.argtypes = [vp, ip, ip, ip, ip, vp]
     lib.gdr_params_default.argtypes = [ctypes.POINTER(gdr_params)]
@@ -313,6 +315,14 @@ def gdr_op_apply(op, sigma, x, y, nvec=1, precision=GDR_PREC_F64):
     want = nvec * op.n if nvec > 0 else None   # nvec = 0 touches nothing
     px, py = _dev(x, "x", want), _dev(y, "y", want)
     return op.ctx.check(lib().gdr_op_apply(op.h, gdr_c64(s.real, s.imag), px, py, nvec, precision))
+
+
+def gdr_op_apply_noalloc(op, sigma, x, y, nvec=1, precision=GDR_PREC_F64):
+    s = complex(sigma)
+    want = nvec * op.n if nvec > 0 else None
+    px, py = _dev(x, "x", want), _dev(y, "y", want)
+    return op.ctx.check(lib().gdr_op_apply_noalloc(op.h, gdr_c64(s.real, s.imag), px, py, nvec,
+                                                   precision))
 
 
 def gdr_op_tables(op):
