@@ -81,20 +81,27 @@ def dslash_standalone(gdr, ops, vol, reps=100, nsets=3):
     """The Wilson operator alone: median per-launch time over `reps` launches
     rotating over `nsets` buffer sets (so the 256 MB Infinity Cache cannot hold
     one set), batch sizes 1, 3, 11, 12. Algorithmic bytes per launch count each
-    link and spinor once (links amortised over the batch): FP32 links
-    (288 + 192 nb) B/site, FP16 links (144 + 192 nb), FP64 (576 + 384 nb)."""
+    link and spinor once (links amortised over the batch), the links as the
+    operator stores them (gdr_op_link_bytes: 192 B/site for special unitary
+    FP32 links kept as two rows, 288 for nine entries, 144 FP16, 576 FP64),
+    spinors 192 B/site/vector FP32, 384 FP64. `gbs_480` restates FP32 rates
+    on the nine-entry count (288 + 192 nb) for comparison with it."""
     import numpy as np
     rows = []
-    per_site = {"f32": (288.0, 192.0), "f16link": (144.0, 192.0), "f64": (576.0, 384.0)}
     for name, (op, prec) in ops.items():
+        lk = float(gdr.gdr_op_link_bytes(op, prec))
+        sp = 384.0 if prec == gdr.GDR_PREC_F64 else 192.0
         for nb in (1, 3, 11, 12):
             ms = gdr.gdr_op_dslash_bench(op, prec, nb, nsets, reps)
             med = float(np.median(ms))
-            lk, sp = per_site[name]
             gbs = (lk + sp * nb) * vol / (med * 1e-3) / 1e9
-            rows.append(dict(variant=name, nvec=nb, us_median=med * 1e3, gbs=gbs,
-                             frac=gbs / HBM_PEAK_GBS))
-            log("bench: dslash %s nb=%d %.1f us %.0f GB/s" % (name, nb, med * 1e3, gbs))
+            row = dict(variant=name, nvec=nb, us_median=med * 1e3, link_bytes_per_site=lk,
+                       gbs=gbs, frac=gbs / HBM_PEAK_GBS)
+            if prec != gdr.GDR_PREC_F64 and name == "f32":
+                row["gbs_480"] = (288.0 + sp * nb) * vol / (med * 1e-3) / 1e9
+            rows.append(row)
+            log("bench: dslash %s nb=%d %.1f us %.0f GB/s (links %d B/site)"
+                % (name, nb, med * 1e3, gbs, lk))
     return rows
 
 

@@ -110,6 +110,15 @@ int gdr_bidiag_create(gdr_ctx ctx, int64_t n, const gdr_c64* diag, const gdr_c64
 /* Number of complex unknowns n (12 * volume for the Wilson operator). */
 int64_t gdr_op_size(gdr_op op);
 
+/* Bytes of link storage per lattice site that one application of the
+ * operator reads at `precision` (GDR_PREC_F64: 576; GDR_PREC_F32: 288 for
+ * FP32 links, 144 for FP16-stored links, 192 when the links are special
+ * unitary and stored as their first two rows, the third being rebuilt as
+ * the conjugated cross product of the two - chosen by gdr_wilson_create for
+ * FP32 storage on lattices whose extents are multiples of 4). -1 for a
+ * non-lattice operator or an unknown precision. */
+int gdr_op_link_bytes(gdr_op op, int precision);
+
 /* y_v = (A - sigma I) x_v for v = 0..nvec-1 (eq. (1.1)), canonical layout,
  * device pointers, x and y each nvec*n complex128 (must not overlap).
  * precision GDR_PREC_F64 or GDR_PREC_F32 (FP32 arithmetic with the op's

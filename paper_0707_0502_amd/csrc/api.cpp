@@ -278,9 +278,10 @@ int gdr_wilson_create(gdr_ctx c, const int dims[4], const int bc[4], double kapp
     op->spec_r = 8 * std::fabs(kappa) > 0 ? 8 * std::fabs(kappa) : 1;
     op->n = 12 * vol;
     op->lst = link_storage == GDR_LINKS_F64 ? GDR_LINKS_F32 : link_storage;
+    for (int mu = 0; mu < 4; ++mu)
+        if (bc[mu] == -1) op->anti |= 1 << mu;
     const size_t nl = (size_t)36 * vol;
     HIPCHK(hipMalloc(&op->u64, nl * sizeof(double2)));
-    HIPCHK(hipMalloc(&op->ulo, nl * (op->lst == GDR_LINKS_F16 ? sizeof(__half2) : sizeof(float2))));
     const double2* src = (const double2*)links;
     double2* tmp = nullptr;
     if (!links_on_device) {
@@ -288,6 +289,23 @@ int gdr_wilson_create(gdr_ctx c, const int dims[4], const int bc[4], double kapp
         HIPCHK(hipMemcpyAsync(tmp, links, nl * sizeof(double2), hipMemcpyHostToDevice, c->st));
         src = tmp;
     }
+    if (op->lst == GDR_LINKS_F32 && op->g.ltv == 8) {
+        // special unitary links (to 1e-9) are stored for the FP32 operator as
+        // their first two rows; any other field keeps all nine entries
+        DMem mem;
+        unsigned long long* devb = mem.get<unsigned long long>(1);
+        HIPCHK(hipMemsetAsync(devb, 0, sizeof(unsigned long long), c->st));
+        su3_deviation(src, 4 * vol, devb, c->st);
+        unsigned long long bits = 0;
+        HIPCHK(hipMemcpyAsync(&bits, devb, sizeof(bits), hipMemcpyDeviceToHost, c->st));
+        HIPCHK(hipStreamSynchronize(c->st));
+        double dev;
+        std::memcpy(&dev, &bits, sizeof(dev));
+        op->su3_dev = dev;
+        if (dev <= 1e-9) op->lst = LINK_R12;
+    }
+    const size_t nlo = op->lst == LINK_R12 ? (size_t)24 * vol : nl;
+    HIPCHK(hipMalloc(&op->ulo, nlo * (op->lst == GDR_LINKS_F16 ? sizeof(__half2) : sizeof(float2))));
     pack_links(src, op->u64, GDR_LINKS_F64, op->g, bc, c->st);
     pack_links(src, op->ulo, op->lst, op->g, bc, c->st);
     HIPCHK(hipGetLastError());
@@ -369,6 +387,13 @@ int gdr_bidiag_create(gdr_ctx c, int64_t n, const gdr_c64* diag, const gdr_c64* 
 }
 
 int64_t gdr_op_size(gdr_op op) { return op ? op->n : 0; }
+
+int gdr_op_link_bytes(gdr_op op, int precision) {
+    if (!op || op->kind != 0) return -1;
+    if (precision == GDR_PREC_F64) return 4 * 9 * 16;
+    if (precision != GDR_PREC_F32) return -1;
+    return op->lst == LINK_R12 ? 4 * 6 * 8 : op->lst == GDR_LINKS_F16 ? 4 * 9 * 4 : 4 * 9 * 8;
+}
 
 int gdr_op_apply(gdr_op op, gdr_c64 sigma, const gdr_c64* x, gdr_c64* y, int nvec, int precision) {
     if (!op) return GDR_ERR_ARG;

@@ -18,6 +18,7 @@
 // next to each other, so they share the tile's links through L2.
 #include "kernels.h"
 
+#include <stdexcept>
 #include <type_traits>
 
 namespace gdr {
@@ -165,7 +166,7 @@ struct DslashK {
         const int lbv = (nb % 8 == 0) ? ((b % 8) * (nb / 8) + b / 8) : b;
         const int v = lbv % nvec;
         const int lb = lbv / nvec;
-        const bool active = !act || act[v];   // uniform over the block
+        if (act && !act[v]) return;   // inactive member: uniform over the block, nothing loaded
         const int local = threadIdx.x;
         const int site0 = lb * 256 + local;
         const int vol = g.vol;
@@ -178,7 +179,6 @@ struct DslashK {
         C st[12];
 #pragma unroll
         for (int c = 0; c < 12; ++c) st[c] = inv[c * V + ss];
-        if (!active) return;
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
             if (!valid) {
@@ -338,7 +338,7 @@ struct DslashHaloK {
         const int lbv = (nb % 8 == 0) ? ((b % 8) * (nb / 8) + b / 8) : b;
         const int v = lbv % nvec;
         const int T = lbv / nvec;   // tile
-        const bool active = !act || act[v];   // uniform over the block
+        if (act && !act[v]) return;   // inactive member: uniform over the block, nothing loaded
         const int local = threadIdx.x;
         const int site0 = (T << 8) | local;
         const int64_t V = g.vol;
@@ -384,7 +384,6 @@ struct DslashHaloK {
 #pragma unroll
             for (int c = 0; c < 12; ++c) hs[h][c] = *at(inv + c * V, (unsigned)sn * (unsigned)sizeof(C));
         }
-        if (!active) return;
 #pragma unroll
         for (int c = 0; c < 12; ++c) sp[c * 256 + local] = st[c];
 #pragma unroll
@@ -509,6 +508,401 @@ struct DslashHaloK {
     }
 };
 
+// ---------------------------------------------------------------------------
+// FP32 operator on special unitary links stored as their first two rows
+// (LINK_R12: 12 reals instead of 18 per link, a third less link traffic);
+// the third row is rebuilt as conj(row0 x row1), exact for det U = 1, and the
+// boundary factor bc[mu] = -1 is applied here on the last slice (the stored
+// links carry none, since -U is not special unitary). 4^4 tiles only.
+
+// link of one hop: rows 0 and 1 at site ls, row 2 rebuilt
+__device__ __forceinline__ void ld_r12(const float2* __restrict__ lk, int64_t V, int ls,
+                                       Z<float> (&u)[3][3]) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int bb = 0; bb < 3; ++bb) u[a][bb] = ld<float>(at(lk + (a * 3 + bb) * V, (unsigned)ls * 8u));
+#pragma unroll
+    for (int bb = 0; bb < 3; ++bb) {
+        const int b1 = (bb + 1) % 3, b2 = (bb + 2) % 3;
+        // conj(u0[b1] u1[b2] - u0[b2] u1[b1])
+        float re = u[0][b1].x * u[1][b2].x;
+        float im = u[0][b1].x * u[1][b2].y;
+        re = __builtin_fmaf(-u[0][b1].y, u[1][b2].y, re);
+        im = __builtin_fmaf(u[0][b1].y, u[1][b2].x, im);
+        re = __builtin_fmaf(-u[0][b2].x, u[1][b1].x, re);
+        im = __builtin_fmaf(-u[0][b2].x, u[1][b1].y, im);
+        re = __builtin_fmaf(u[0][b2].y, u[1][b1].y, re);
+        im = __builtin_fmaf(-u[0][b2].y, u[1][b1].x, im);
+        u[2][bb] = {re, -im};
+    }
+}
+
+// mulrec with explicit FMA chains and a sign sg = +-1 on the whole hop
+template <int MU, int DIR>
+__device__ __forceinline__ void mulrec_sg(Z<float> (&acc)[4][3], const Z<float> (&h0)[3],
+                                          const Z<float> (&h1)[3], const Z<float> (&u)[3][3],
+                                          float sg) {
+    using H = HopC<MU, DIR>;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float s0x, s0y, s1x, s1y;
+#pragma unroll
+        for (int bb = 0; bb < 3; ++bb) {
+            // m = u[a][bb] (forward) or conj(u[bb][a]) (backward)
+            const float mx = DIR == 0 ? u[a][bb].x : u[bb][a].x;
+            const float my = DIR == 0 ? u[a][bb].y : -u[bb][a].y;
+            if (bb == 0) {
+                s0x = mx * h0[0].x;
+                s0y = mx * h0[0].y;
+                s1x = mx * h1[0].x;
+                s1y = mx * h1[0].y;
+            } else {
+                s0x = __builtin_fmaf(mx, h0[bb].x, s0x);
+                s0y = __builtin_fmaf(mx, h0[bb].y, s0y);
+                s1x = __builtin_fmaf(mx, h1[bb].x, s1x);
+                s1y = __builtin_fmaf(mx, h1[bb].y, s1y);
+            }
+            s0x = __builtin_fmaf(-my, h0[bb].y, s0x);
+            s0y = __builtin_fmaf(my, h0[bb].x, s0y);
+            s1x = __builtin_fmaf(-my, h1[bb].y, s1x);
+            s1y = __builtin_fmaf(my, h1[bb].x, s1y);
+        }
+        const Z<float> s0{s0x, s0y}, s1{s1x, s1y};
+        const Z<float> e0 = mulc<H::c0r, -H::c0i>(s0);   // conj(c0) U h0
+        const Z<float> e1 = mulc<H::c1r, -H::c1i>(s1);
+        const Z<float> r2 = H::low ? e1 : e0, r3 = H::low ? e0 : e1;
+        acc[0][a] = {__builtin_fmaf(sg, s0.x, acc[0][a].x), __builtin_fmaf(sg, s0.y, acc[0][a].y)};
+        acc[1][a] = {__builtin_fmaf(sg, s1.x, acc[1][a].x), __builtin_fmaf(sg, s1.y, acc[1][a].y)};
+        acc[2][a] = {__builtin_fmaf(sg, r2.x, acc[2][a].x), __builtin_fmaf(sg, r2.y, acc[2][a].y)};
+        acc[3][a] = {__builtin_fmaf(sg, r3.x, acc[3][a].x), __builtin_fmaf(sg, r3.y, acc[3][a].y)};
+    }
+}
+
+// Geometry of one 4^4 tile T: tile coordinates and the neighbouring tile
+// across each face (periodic wrap). Scalar fields only: a per-direction
+// array indexed by a run-time direction would be placed in scratch memory.
+struct TileGeo {
+    int T;
+    int tc0, tc1, tc2, tc3;   // tile coordinates
+    int nt0, nt1, nt2, nt3;   // tiles per direction
+    int s1, s2, s3;           // tile index strides of y, z, t
+    __device__ __forceinline__ TileGeo(const Geom& gg, int T_) : T(T_) {
+        nt0 = gg.nt[0];
+        nt1 = gg.nt[1];
+        nt2 = gg.nt[2];
+        nt3 = gg.nt[3];
+        int r = T;
+        tc0 = r % nt0;
+        r /= nt0;
+        tc1 = r % nt1;
+        r /= nt1;
+        tc2 = r % nt2;
+        tc3 = r / nt2;
+        s1 = nt0;
+        s2 = nt0 * nt1;
+        s3 = s2 * nt2;
+    }
+    template <int MU>
+    __device__ __forceinline__ int tcoord() const {
+        return MU == 0 ? tc0 : MU == 1 ? tc1 : MU == 2 ? tc2 : tc3;
+    }
+    template <int MU>
+    __device__ __forceinline__ int ntiles() const {
+        return MU == 0 ? nt0 : MU == 1 ? nt1 : MU == 2 ? nt2 : nt3;
+    }
+    template <int MU>
+    __device__ __forceinline__ int nbr(int dir) const {
+        const int ntm = ntiles<MU>(), tcm = tcoord<MU>();
+        const int stm = MU == 0 ? 1 : MU == 1 ? s1 : MU == 2 ? s2 : s3;
+        return dir == 0 ? (tcm == ntm - 1 ? T - (ntm - 1) * stm : T + stm)
+                        : (tcm == 0 ? T + (ntm - 1) * stm : T - stm);
+    }
+    // run-time direction (uniform over a wavefront where it is used)
+    __device__ __forceinline__ int nbr(int mu, int dir) const {
+        if (mu == 0) return nbr<0>(dir);
+        if (mu == 1) return nbr<1>(dir);
+        if (mu == 2) return nbr<2>(dir);
+        return nbr<3>(dir);
+    }
+};
+
+// storage index of face entry e (0..511) of tile geometry tg: face f = e / 64
+// (2 mu + dir), site j = e % 64 across that face in the neighbouring tile
+__device__ __forceinline__ int halo_source(const TileGeo tg, int e) {
+    const int f = __builtin_amdgcn_readfirstlane(e >> 6), j = e & 63;   // f: one face per wavefront
+    const int mu = f >> 1, dir = f & 1;
+    const int sh = 2 * mu;
+    const int cn = dir == 0 ? 0 : 3;
+    const int wn = (j & ((1 << sh) - 1)) | (cn << sh) | ((j >> sh) << (sh + 2));
+    return (tg.nbr(mu, dir) << 8) | wn;
+}
+
+// Load this thread's own site and its two halo entries of vector `inv` and
+// stage them into LDS: the tile in sp[component][site], the spin-projected
+// halo in hl[face][half-spinor component][face site]. SPLIT: in two rounds of
+// loads (own site and first halo entry, then the second halo entry) instead
+// of all 36 at once, for kernels that also hold the links in registers.
+template <bool SPLIT>
+__device__ __forceinline__ void stage_r12(const float2* __restrict__ inv, int64_t V, int site0,
+                                          int local, const int (&hsrc)[2], float2* sp, float2* hl) {
+    float2 st[12], hs[2][12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) st[c] = inv[c * V + site0];
+#pragma unroll
+    for (int h = 0; h < (SPLIT ? 1 : 2); ++h)
+#pragma unroll
+        for (int c = 0; c < 12; ++c) hs[h][c] = *at(inv + c * V, (unsigned)hsrc[h] * 8u);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) sp[c * 256 + local] = st[c];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        if (SPLIT && h == 1) {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) hs[1][c] = *at(inv + c * V, (unsigned)hsrc[1] * 8u);
+        }
+        const int e = local + 256 * h;
+        const int f = e >> 6, j = e & 63;
+        Z<float> ps[4][3], h0[3], h1[3];
+#pragma unroll
+        for (int s_ = 0; s_ < 4; ++s_)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) ps[s_][a] = {hs[h][s_ * 3 + a].x, hs[h][s_ * 3 + a].y};
+        switch (f) {
+            case 0: proj<0, 0>(ps, h0, h1); break;
+            case 1: proj<0, 1>(ps, h0, h1); break;
+            case 2: proj<1, 0>(ps, h0, h1); break;
+            case 3: proj<1, 1>(ps, h0, h1); break;
+            case 4: proj<2, 0>(ps, h0, h1); break;
+            case 5: proj<2, 1>(ps, h0, h1); break;
+            case 6: proj<3, 0>(ps, h0, h1); break;
+            default: proj<3, 1>(ps, h0, h1); break;
+        }
+        float2* hp = hl + f * 6 * 64 + j;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            hp[a * 64] = make_float2(h0[a].x, h0[a].y);
+            hp[(3 + a) * 64] = make_float2(h1[a].x, h1[a].y);
+        }
+    }
+}
+
+// The spin-projected half spinor of hop (MU, DIR) at in-tile site w: from the
+// staged tile (projected here) or the staged halo.
+template <int MU, int DIR>
+__device__ __forceinline__ void hop_input(const float2* sp, const float2* hl, int w, Z<float> (&h0)[3],
+                                          Z<float> (&h1)[3]) {
+    constexpr int sh = 2 * MU;
+    const int cm = (w >> sh) & 3;
+    const bool inside = DIR == 0 ? cm < 3 : cm > 0;
+    if (inside) {
+        const int wn = DIR == 0 ? w + (1 << sh) : w - (1 << sh);
+        Z<float> ps[4][3];
+#pragma unroll
+        for (int s_ = 0; s_ < 4; ++s_)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) ps[s_][a] = ld<float>(&sp[(s_ * 3 + a) * 256 + wn]);
+        proj<MU, DIR>(ps, h0, h1);
+    } else {
+        const int j = (w & ((1 << sh) - 1)) | ((w >> (sh + 2)) << sh);
+        const float2* hp = hl + (2 * MU + DIR) * 6 * 64 + j;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            h0[a] = ld<float>(&hp[a * 64]);
+            h1[a] = ld<float>(&hp[(3 + a) * 64]);
+        }
+    }
+}
+
+// link site and boundary sign of hop (MU, DIR) at in-tile site w of tile tg
+template <int MU, int DIR>
+__device__ __forceinline__ void hop_link(const TileGeo tg, int w, int anti, int& ls, float& sg) {
+    constexpr int sh = 2 * MU;
+    const int cm = (w >> sh) & 3;
+    const int ntm = tg.ntiles<MU>();
+    if (DIR == 0) {
+        ls = (tg.T << 8) | w;   // U_mu(x)
+        sg = ((anti >> MU) & 1) && cm == 3 && tg.tcoord<MU>() == ntm - 1 ? -1.f : 1.f;
+    } else {
+        const bool inside = cm > 0;
+        const int wn = inside ? w - (1 << sh) : w + (3 << sh);
+        ls = ((inside ? tg.T : tg.nbr<MU>(1)) << 8) | wn;   // U_mu(x - mu)
+        sg = ((anti >> MU) & 1) && cm == 0 && tg.tcoord<MU>() == 0 ? -1.f : 1.f;
+    }
+}
+
+// out = alpha ((1 - sigma) in - kappa acc) [+ add], non-temporal stores
+__device__ __forceinline__ void finish_r12(const Z<float> (&acc)[4][3], const float2* sp, int local,
+                                           float2* o, const float2* ad, int64_t V, float dre, float dim,
+                                           float al, float kappa) {
+#pragma unroll
+    for (int s_ = 0; s_ < 4; ++s_)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int comp = s_ * 3 + a;
+            const Z<float> xi = ld<float>(&sp[comp * 256 + local]);
+            float re = al * (dre * xi.x - dim * xi.y - kappa * acc[s_][a].x);
+            float im = al * (dre * xi.y + dim * xi.x - kappa * acc[s_][a].y);
+            if (ad) {
+                const Z<float> av = ld<float>(ad + comp * V);
+                re += av.x;
+                im += av.y;
+            }
+            st_nt(&o[comp * V], re, im);
+        }
+}
+
+// One block per (tile, vector): the halo kernel's staging with LINK_R12 links.
+__global__ __launch_bounds__(256, 3) void k_dslash_r12(const float2* __restrict__ in, int64_t in_stride,
+                                                      float2* __restrict__ out, int64_t out_stride,
+                                                      const float2* __restrict__ add, int64_t add_stride,
+                                                      const float2* __restrict__ links, Geom g, float kappa,
+                                                      DiagList dl, const int* __restrict__ act, int nvec,
+                                                      int anti) {
+    __shared__ float2 sp[12 * 256];
+    __shared__ float2 hl[8 * 6 * 64];
+    const int nb = gridDim.x;
+    const int b = blockIdx.x;
+    const int lbv = (nb % 8 == 0) ? ((b % 8) * (nb / 8) + b / 8) : b;
+    const int v = lbv % nvec;
+    if (act && !act[v]) return;   // inactive member: uniform over the block, nothing loaded
+    const TileGeo tg(g, lbv / nvec);
+    const int local = threadIdx.x;
+    const int site0 = (tg.T << 8) | local;
+    const int64_t V = g.vol;
+    const int hsrc[2] = {halo_source(tg, local), halo_source(tg, local + 256)};
+    stage_r12<false>(in + v * in_stride, V, site0, local, hsrc, sp, hl);
+    __syncthreads();
+    Z<float> acc[4][3];
+#pragma unroll
+    for (int s_ = 0; s_ < 4; ++s_)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) acc[s_][a] = {0, 0};
+    auto hop = [&](auto muc, auto dirc) {
+        constexpr int mu = decltype(muc)::value;
+        constexpr int dir = decltype(dirc)::value;
+        int w = local;
+        pin(w);
+        Z<float> h0[3], h1[3];
+        hop_input<mu, dir>(sp, hl, w, h0, h1);
+        int ls;
+        float sg;
+        hop_link<mu, dir>(tg, w, anti, ls, sg);
+        Z<float> u[3][3];
+        ld_r12(links + (int64_t)mu * 6 * V, V, ls, u);
+        mulrec_sg<mu, dir>(acc, h0, h1, u, sg);
+#pragma unroll
+        for (int s_ = 0; s_ < 4; ++s_)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                pin(acc[s_][a].x);
+                pin(acc[s_][a].y);
+            }
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I3 = std::integral_constant<int, 3>;
+    hop(I0{}, I0{});
+    hop(I0{}, I1{});
+    hop(I1{}, I0{});
+    hop(I1{}, I1{});
+    hop(I2{}, I0{});
+    hop(I2{}, I1{});
+    hop(I3{}, I0{});
+    hop(I3{}, I1{});
+    finish_r12(acc, sp, local, out + v * out_stride + site0,
+               add ? add + v * add_stride + site0 : nullptr, V, (float)dl.d[v].x, (float)dl.d[v].y,
+               (float)dl.alpha[v], kappa);
+}
+
+// Several vectors per launch: one block per tile loops over the vectors. The
+// links of the tile's eight hops (each link once, third row rebuilt once,
+// boundary sign folded in) stay in registers for every vector; each vector
+// is staged and applied as in k_dslash_r12 (no added vector: launches with
+// one go to k_dslash_r12). Inactive members are skipped.
+__global__ __launch_bounds__(256, 2) void k_dslash_r12v(const float2* __restrict__ in, int64_t in_stride,
+                                                       float2* __restrict__ out, int64_t out_stride,
+                                                       const float2* __restrict__ links, Geom g, float kappa,
+                                                       DiagList dl, const int* __restrict__ act, int nvec,
+                                                       int anti) {
+    __shared__ float2 sp[12 * 256];
+    __shared__ float2 hl[8 * 6 * 64];
+    const int nb = gridDim.x;
+    const int b = blockIdx.x;
+    const TileGeo tg(g, (nb % 8 == 0) ? ((b % 8) * (nb / 8) + b / 8) : b);
+    const int local = threadIdx.x;
+    const int site0 = (tg.T << 8) | local;
+    const int64_t V = g.vol;
+    Z<float> ul[8][3][3];
+    auto ldh = [&](auto muc, auto dirc) {
+        constexpr int mu = decltype(muc)::value;
+        constexpr int dir = decltype(dirc)::value;
+        int ls;
+        float sg;
+        hop_link<mu, dir>(tg, local, anti, ls, sg);
+        Z<float>(&u)[3][3] = ul[2 * mu + dir];
+        ld_r12(links + (int64_t)mu * 6 * V, V, ls, u);
+        // the boundary sign folded into the register copy of the link
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int bb = 0; bb < 3; ++bb) u[a][bb] = {sg * u[a][bb].x, sg * u[a][bb].y};
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I3 = std::integral_constant<int, 3>;
+    ldh(I0{}, I0{});
+    ldh(I0{}, I1{});
+    ldh(I1{}, I0{});
+    ldh(I1{}, I1{});
+    ldh(I2{}, I0{});
+    ldh(I2{}, I1{});
+    ldh(I3{}, I0{});
+    ldh(I3{}, I1{});
+    bool first = true;
+    for (int v = 0; v < nvec; ++v) {
+        if (act && !act[v]) continue;   // uniform over the block
+        if (!first) __syncthreads();   // the previous vector's LDS reads are done
+        first = false;
+        const int hsrc[2] = {halo_source(tg, local), halo_source(tg, local + 256)};
+        stage_r12<true>(in + v * in_stride, V, site0, local, hsrc, sp, hl);
+        __syncthreads();
+        Z<float> acc[4][3];
+#pragma unroll
+        for (int s_ = 0; s_ < 4; ++s_)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) acc[s_][a] = {0, 0};
+        auto hop = [&](auto muc, auto dirc) {
+            constexpr int mu = decltype(muc)::value;
+            constexpr int dir = decltype(dirc)::value;
+            int w = local;
+            pin(w);
+            Z<float> h0[3], h1[3];
+            hop_input<mu, dir>(sp, hl, w, h0, h1);
+            mulrec_sg<mu, dir>(acc, h0, h1, ul[2 * mu + dir], 1.f);
+#pragma unroll
+            for (int s_ = 0; s_ < 4; ++s_)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    pin(acc[s_][a].x);
+                    pin(acc[s_][a].y);
+                }
+        };
+        hop(I0{}, I0{});
+        hop(I0{}, I1{});
+        hop(I1{}, I0{});
+        hop(I1{}, I1{});
+        hop(I2{}, I0{});
+        hop(I2{}, I1{});
+        hop(I3{}, I0{});
+        hop(I3{}, I1{});
+        finish_r12(acc, sp, local, out + v * out_stride + site0, nullptr, V, (float)dl.d[v].x,
+                   (float)dl.d[v].y, (float)dl.alpha[v], kappa);
+    }
+}
+
 template <typename TL>
 __global__ __launch_bounds__(256, 3) void k_dslash_halo(const float2* __restrict__ in, int64_t in_stride,
                                                         float2* __restrict__ out, int64_t out_stride,
@@ -537,8 +931,22 @@ template <typename TS>
 void dslash(const typename CT<TS>::t* in, int64_t in_stride, typename CT<TS>::t* out,
             int64_t out_stride, const typename CT<TS>::t* add, int64_t add_stride,
             const void* links, int link_storage, const Geom& g, double kappa, const DiagList& dl,
-            int nvec, hipStream_t st, const int* act) {
+            int nvec, hipStream_t st, const int* act, int anti) {
     dim3 grid(((g.vol + 255) / 256) * nvec);
+    if constexpr (std::is_same<TS, float>::value) {
+        if (link_storage == LINK_R12) {
+            if (g.ltv != 8) throw std::invalid_argument("dslash: LINK_R12 needs 4^4 tiles");
+            if (nvec >= DSLASH_VLOOP_MIN && !add)
+                hipLaunchKernelGGL(k_dslash_r12v, dim3(g.vol >> 8), dim3(256), 0, st, in, in_stride,
+                                   out, out_stride, (const float2*)links, g, (float)kappa, dl, act,
+                                   nvec, anti);
+            else
+                hipLaunchKernelGGL(k_dslash_r12, grid, dim3(256), 0, st, in, in_stride, out,
+                                   out_stride, add, add_stride, (const float2*)links, g,
+                                   (float)kappa, dl, act, nvec, anti);
+            return;
+        }
+    }
     if constexpr (std::is_same<TS, double>::value) {
         hipLaunchKernelGGL((k_dslash<double, double2, double>), grid, dim3(256), 0, st, in,
                            in_stride, out, out_stride, add, add_stride, (const double2*)links, g,
@@ -568,9 +976,9 @@ void dslash(const typename CT<TS>::t* in, int64_t in_stride, typename CT<TS>::t*
 
 template void dslash<double>(const double2*, int64_t, double2*, int64_t, const double2*, int64_t,
                              const void*, int, const Geom&, double, const DiagList&, int,
-                             hipStream_t, const int*);
+                             hipStream_t, const int*, int);
 template void dslash<float>(const float2*, int64_t, float2*, int64_t, const float2*, int64_t,
                             const void*, int, const Geom&, double, const DiagList&, int,
-                            hipStream_t, const int*);
+                            hipStream_t, const int*, int);
 
 }  // namespace gdr

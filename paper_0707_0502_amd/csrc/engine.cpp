@@ -45,8 +45,11 @@ static double dslash_bytes(gdr_op_s* op, int nvec, bool add) {
     if (op->kind == 1)   // bidiagonal: 2n matrix entries, in, out (, add) per vector
         return (double)op->n * cs * (2 + nvec * (2 + (add ? 1 : 0)));
     const double vol = op->g.vol;
-    double link = std::is_same<T, double>::value ? 16 : (op->lst == GDR_LINKS_F16 ? 4 : 8);
-    return vol * (36 * link + nvec * (12 * cs * 2 + (add ? 12 * cs : 0)));
+    double link = std::is_same<T, double>::value ? 16 * 36
+                  : op->lst == LINK_R12         ? 8 * 24
+                  : op->lst == GDR_LINKS_F16    ? 4 * 36
+                                                : 8 * 36;
+    return vol * (link + nvec * (12 * cs * 2 + (add ? 12 * cs : 0)));
 }
 static double dslash_flops(gdr_op_s* op, int nvec) {
     if (op->kind == 1) return (double)op->n * nvec * 16.0;
@@ -66,7 +69,7 @@ void op_apply(gdr_op_s* op, const typename CT<T>::t* in, int64_t in_stride,
         return;
     }
     dslash<T>(in, in_stride, out, out_stride, add, add_stride, links_for<T>(op), lst_for<T>(op),
-              op->g, op->kappa, dl, nvec, st, act);
+              op->g, op->kappa, dl, nvec, st, act, op->anti);
 }
 template <typename T>
 void op_pack(gdr_op_s* op, const double2* canon, typename CT<T>::t* dst, int64_t stride, int nvec,

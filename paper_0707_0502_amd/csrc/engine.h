@@ -91,8 +91,10 @@ struct gdr_op_s {
     double kappa = 0;
     int64_t n = 0;          // 12 * volume
     double2* u64 = nullptr; // FP64 links (internal layout)
-    void* ulo = nullptr;    // FP32 or FP16 links
+    void* ulo = nullptr;    // FP32, FP16 or FP32 two-row (LINK_R12) links
     int lst = GDR_LINKS_F32;
+    int anti = 0;           // bit mu: direction mu antiperiodic (bc[mu] = -1)
+    double su3_dev = -1;    // largest deviation of the links from SU(3) (-1: not checked)
     int kind = 0;             // 0: Wilson-Dirac lattice operator, 1: bidiagonal matrix
     double2* bd64 = nullptr;  // bidiagonal: diagonal (n) then superdiagonal (n), FP64
     float2* bd32 = nullptr;   //   and the FP32 copy

@@ -14,9 +14,15 @@ void pack_spinor(const double2* canon, typename CT<T>::t* dst, int64_t stride, c
 template <typename T>
 void unpack_spinor(const typename CT<T>::t* src, int64_t stride, double2* canon, const Geom& g,
                    int nvec, hipStream_t st);
-// storage: 0 FP64 (double2), 1 FP32 (float2), 2 FP16 (__half2 per complex)
+// storage: 0 FP64 (double2), 1 FP32 (float2), 2 FP16 (__half2 per complex),
+// 3 FP32 rows 0 and 1 of special unitary links (LINK_R12; bc not folded)
+constexpr int LINK_R12 = 3;
 void pack_links(const double2* canon, void* out, int storage, const Geom& g, const int bc[4],
                 hipStream_t st);
+// largest deviation of nlinks canonical 3x3 links from SU(3) (see layout.hip);
+// *dev_bits must be zeroed first, read it back as a double
+void su3_deviation(const double2* canon, int64_t nlinks, unsigned long long* dev_bits,
+                   hipStream_t st);
 void build_tables(int32_t* eo_of_lex, int32_t* nbr, int8_t* sign, const Geom& g, int bc_t,
                   hipStream_t st);
 
@@ -28,11 +34,16 @@ struct DiagList {
 };
 // out_v = alpha_v * ((1 - sigma_v) in_v - kappa D in_v) [+ add_v]   for v < nvec
 // TS spinor type; link storage per `link_storage`; compute in TS.
+// anti: bit mu set when direction mu is antiperiodic (used with LINK_R12,
+// whose links carry no boundary factor). Members with act[v] == 0 are skipped.
 template <typename TS>
 void dslash(const typename CT<TS>::t* in, int64_t in_stride, typename CT<TS>::t* out,
             int64_t out_stride, const typename CT<TS>::t* add, int64_t add_stride,
             const void* links, int link_storage, const Geom& g, double kappa, const DiagList& dl,
-            int nvec, hipStream_t st, const int* act = nullptr);
+            int nvec, hipStream_t st, const int* act = nullptr, int anti = 0);
+// vectors per launch from which the FP32 LINK_R12 operator runs the vector-loop
+// kernel (links held in registers across the vectors of one tile)
+constexpr int DSLASH_VLOOP_MIN = 2;
 
 // ------------------------------------------------------------ bidiagonal operator (bidiag.hip)
 // out_v = alpha_v * (M in_v - sigma_v in_v) [+ add_v], sigma_v = 1 - dl.d[v];

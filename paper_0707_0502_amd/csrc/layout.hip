@@ -72,7 +72,10 @@ struct BC4 {
 };
 
 // links internal: [mu][e = a*3+b][vol] in tile order, bc[mu] folded into
-// U_mu(x) at x_mu = L_mu - 1
+// U_mu(x) at x_mu = L_mu - 1. Storage 3 (FP32, special unitary links): rows
+// 0 and 1 only, [mu][e = a*3+b, a < 2][vol], boundary factors not folded (the
+// third row is rebuilt as conj(row0 x row1), which holds for det U = 1 only;
+// the operator applies bc[mu] itself)
 __global__ void k_pack_links(const double2* __restrict__ canon, void* __restrict__ out, int storage,
                              Geom g, BC4 bc) {
     int lex = blockIdx.x * blockDim.x + threadIdx.x;
@@ -80,6 +83,15 @@ __global__ void k_pack_links(const double2* __restrict__ canon, void* __restrict
     int c[4];
     lex_coords(g, lex, c[0], c[1], c[2], c[3]);
     const int s = site_of(g, c);
+    if (storage == 3) {
+        for (int mu = 0; mu < 4; ++mu) {
+            const double2* src = canon + ((int64_t)mu * g.vol + lex) * 9;
+            for (int e = 0; e < 6; ++e)
+                ((float2*)out)[((int64_t)mu * 6 + e) * g.vol + s] =
+                    make_float2((float)src[e].x, (float)src[e].y);
+        }
+        return;
+    }
     for (int mu = 0; mu < 4; ++mu) {
         double f = (c[mu] == g.L[mu] - 1) ? (double)bc.v[mu] : 1.0;
         const double2* src = canon + ((int64_t)mu * g.vol + lex) * 9;
@@ -96,6 +108,37 @@ __global__ void k_pack_links(const double2* __restrict__ canon, void* __restrict
             }
         }
     }
+}
+
+// Largest deviation of the canonical links from SU(3) over the lattice:
+// max(|U U^H - I|_max, |det U - 1|) per link, as the bit pattern of a
+// non-negative double (monotone as an unsigned integer) in *dev_bits.
+__global__ void k_su3_dev(const double2* __restrict__ canon, int64_t nlinks,
+                          unsigned long long* __restrict__ dev_bits) {
+    double worst = 0;
+    for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < nlinks;
+         l += (int64_t)gridDim.x * blockDim.x) {
+        const double2* u = canon + l * 9;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                double2 acc = mk(i == j ? -1.0 : 0.0, 0);
+                for (int k = 0; k < 3; ++k) acc = cadd(acc, cmul(u[i * 3 + k], cconj(u[j * 3 + k])));
+                worst = fmax(worst, cabs(acc));
+            }
+        // det by the first row's cofactors
+        const double2 c0 = csub(cmul(u[4], u[8]), cmul(u[5], u[7]));
+        const double2 c1 = csub(cmul(u[5], u[6]), cmul(u[3], u[8]));
+        const double2 c2 = csub(cmul(u[3], u[7]), cmul(u[4], u[6]));
+        const double2 det = cadd(cadd(cmul(u[0], c0), cmul(u[1], c1)), cmul(u[2], c2));
+        worst = fmax(worst, cabs(csub(det, mk(1, 0))));
+        if (!(worst == worst)) worst = 1e300;   // NaN entries count as far from SU(3)
+    }
+    atomicMax(dev_bits, (unsigned long long)__double_as_longlong(worst));
+}
+
+void su3_deviation(const double2* canon, int64_t nlinks, unsigned long long* dev_bits,
+                   hipStream_t st) {
+    hipLaunchKernelGGL(k_su3_dev, dim3(1024), dim3(256), 0, st, canon, nlinks, dev_bits);
 }
 
 void pack_links(const double2* canon, void* out, int storage, const Geom& g, const int bc[4],

@@ -31,7 +31,8 @@ K_CLASSES = ["dslash", "gs_project", "gs_update", "gs_close", "small", "combine"
 
 SYMBOLS = [
     "gdr_ctx_create", "gdr_ctx_destroy", "gdr_last_error", "gdr_wilson_create",
-    "gdr_op_destroy", "gdr_bidiag_create", "gdr_op_size", "gdr_op_apply", "gdr_op_apply_noalloc",
+    "gdr_op_destroy", "gdr_bidiag_create", "gdr_op_size", "gdr_op_link_bytes", "gdr_op_apply",
+    "gdr_op_apply_noalloc",
     "gdr_op_tables", "gdr_op_dslash_bench",
     "gdr_params_default",
     "gdr_solve_dr_sh", "gdr_solve_proj_sh", "gdr_solve", "gdr_defl_k", "gdr_defl_export",
@@ -93,6 +94,7 @@ def load(path=LIB_PATH):
     lib.gdr_bidiag_create.argtypes = [vp, i64, vp, vp, ctypes.POINTER(vp)]
     lib.gdr_op_size.argtypes = [vp]
     lib.gdr_op_size.restype = i64
+    lib.gdr_op_link_bytes.argtypes = [vp, ip]
     lib.gdr_op_apply.argtypes = [vp, gdr_c64, vp, vp, ip, ip]
     lib.gdr_op_apply_noalloc.argtypes = [vp, gdr_c64, vp, vp, ip, ip]
     lib.gdr_op_tables.argtypes = [vp, vp, vp, vp]
@@ -308,6 +310,10 @@ def gdr_op_destroy(op):
 
 def gdr_op_size(op):
     return lib().gdr_op_size(op.h)
+
+
+def gdr_op_link_bytes(op, precision):
+    return lib().gdr_op_link_bytes(op.h, precision)
 
 
 def gdr_op_apply(op, sigma, x, y, nvec=1, precision=GDR_PREC_F64):

@@ -24,7 +24,8 @@ def test_tables_bit_exact(dims):
 
 
 @pytest.mark.parametrize("dims,bc", [((4, 4, 4, 4), (1, 1, 1, -1)), ((2, 4, 6, 8), (1, 1, 1, -1)),
-                                     ((6, 4, 2, 4), (1, -1, 1, 1))])
+                                     ((6, 4, 2, 4), (1, -1, 1, 1)),
+                                     ((4, 8, 4, 8), (-1, 1, -1, -1)), ((8, 4, 4, 4), (1, -1, 1, -1))])
 def test_apply_matches_oracle(dims, bc):
     from paper_0707_0502_amd import gdr
     say("apply", dims, bc)
@@ -122,3 +123,36 @@ def test_bad_operator_arguments():
     with pytest.raises(gdr.GdrError) as e:
         gdr.gdr_wilson_create(ctx(), (2, 2, 2, 2), (1, 1, 1, -1), 0.1, links, 7)
     assert e.value.code == gdr.GDR_ERR_ARG
+
+
+@pytest.mark.parametrize("nv", [1, 3, 12])
+def test_fp32_link_storage_choice(nv):
+    """FP32 storage of special unitary links on 4^4 tiles keeps two rows per
+    link (192 B/site) and rebuilds the third in the operator, with the
+    antiperiodic factors applied there; a field that is not special unitary
+    keeps all nine entries (288 B/site). Both match the oracle to FP32
+    rounding, one vector or several per launch, with every direction
+    antiperiodic."""
+    from paper_0707_0502_amd import gdr
+    dims, bc = (8, 4, 4, 8), (-1, -1, -1, -1)
+    kappa, sig = 0.124, 0.07 - 0.02j
+    su3 = synth.gauge_links(dims, 0.6, 11)
+    rng = np.random.default_rng(12)
+    general = su3 * (1.0 + 0.05 * rng.standard_normal(su3.shape[:-2])[..., None, None])
+    X = np.stack([synth.rhs_gaussian(dims, 60 + v).ravel() for v in range(nv)])
+    for links, want in ((su3, 192), (general, 288)):
+        ref = np.stack([wilson.apply_A(links, kappa, x.reshape(dims[::-1] + (4, 3)), sig, bc).ravel()
+                        for x in X])
+        op = make_op(links, kappa, bc, gdr.GDR_LINKS_F32)
+        assert gdr.gdr_op_link_bytes(op, gdr.GDR_PREC_F32) == want
+        assert gdr.gdr_op_link_bytes(op, gdr.GDR_PREC_F64) == 576
+        y = empty(X.size)
+        gdr.gdr_op_apply(op, sig, dev(X.ravel()), y, nv, gdr.GDR_PREC_F32)
+        got = host(y).reshape(X.shape)
+        err = max(np.abs(got[v] - ref[v]).max() / np.abs(ref[v]).max() for v in range(nv))
+        say("  link bytes", want, "nv", nv, "max rel err", err)
+        assert err <= 1e-6
+        gdr.gdr_op_destroy(op)
+    op = make_op(su3, kappa, bc, gdr.GDR_LINKS_F16)
+    assert gdr.gdr_op_link_bytes(op, gdr.GDR_PREC_F32) == 144
+    gdr.gdr_op_destroy(op)
