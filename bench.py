@@ -77,6 +77,30 @@ def cpu_baseline(cfg, links, kappa, b, sec_budget, gpu_steps):
                 seconds=time.perf_counter() - t_start, threads=int(threads))
 
 
+def host_info():
+    """CPU model, logical CPUs visible to this process, and the BLAS/OpenMP
+    thread settings the oracle runs with."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    env = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS",
+                                          "MKL_NUM_THREADS") if os.environ.get(k)}
+    blas = None
+    try:
+        import numpy as np
+        cfg = np.show_config(mode="dicts")
+        blas = cfg.get("Build Dependencies", {}).get("blas", {}).get("name")
+    except Exception:
+        pass
+    return {"cpu_model": model, "nproc": len(os.sched_getaffinity(0)), "os_cpu_count": os.cpu_count(),
+            "thread_env": env, "numpy_blas": blas}
+
+
 def dslash_standalone(gdr, ops, vol, reps=100, nsets=3):
     """The Wilson operator alone: median per-launch time over `reps` launches
     rotating over `nsets` buffer sets (so the 256 MB Infinity Cache cannot hold
@@ -205,6 +229,8 @@ def uneven_batch(a, gdr, synth, torch, np):
             stream = torch.cuda.Stream()
             ctx = gdr.gdr_ctx_create(0, stream.cuda_stream)
             lst = gdr.GDR_LINKS_F16 if cfg.get("links") == "f16" else gdr.GDR_LINKS_F32
+            if a.c5_links == "f32":
+                lst = gdr.GDR_LINKS_F32
             op = gdr.gdr_wilson_create(ctx, cfg["dims"], (1, 1, 1, -1), synth.kappa(name), links,
                                        lst)
             with torch.cuda.stream(stream):
@@ -223,12 +249,17 @@ def uneven_batch(a, gdr, synth, torch, np):
         rs.clear()
         torch.cuda.empty_cache()
 
-    def batch(prec):
+    def batch(prec, profile_big=False):
         def solve(r):
             cfg = r["cfg"]
             p = gdr.gdr_params_default(m_dr=cfg["m_dr"], k=cfg["k"], m_proj=cfg["m_proj"],
                                        tol=cfg["tol"], tol_extra=cfg["tol_extra"], precision=prec,
-                                       use_graph=1, refine_floor=a.refine_floor)
+                                       use_graph=1, refine_floor=a.refine_floor, m_clean=a.m_clean)
+            if profile_big and r["name"] == "C5":
+                # kernel classes of the critical path (the 32^3x64 lattice)
+                # timed with HIP events on its stream; the small lattices keep
+                # their graph replays (profiling runs a context's cycles eagerly)
+                p.profile = 0xFF
             st = gdr.Stats(len(cfg["rhs"]), len(cfg["sigmas"]))
             t0 = time.perf_counter()
             r["rc"] = gdr.gdr_solve(r["op"], cfg["sigmas"], r["Bd"], r["X"], p, st)
@@ -260,13 +291,58 @@ def uneven_batch(a, gdr, synth, torch, np):
     runs += make_runs()
     for w in range(a.warmup):
         batch(gdr.GDR_PREC_MIXED)
-    walls = [batch(gdr.GDR_PREC_MIXED) for _ in range(a.steps)]
+    walls = []
+    kern = {}
+    for _ in range(a.steps):
+        walls.append(batch(gdr.GDR_PREC_MIXED, profile_big=True))
+        big = next(r for r in runs if r["name"] == "C5")
+        for name, d in big["st"].kernels().items():
+            e = kern.setdefault(name, dict(ms=0.0, bytes=0.0, flops=0.0, launches=0))
+            for key in e:
+                e[key] += d[key]
     wall = sum(walls) / len(walls)
     per = {r["name"]: dict(sec=r["sec"], rc=r["rc"], **{k: v for k, v in r["st"].as_dict().items()
-                                                      if k.startswith(("mvp", "cycles"))},
+                                                      if k.startswith(("mvp", "cycles", "t_phase"))},
                            max_true_resid=float(r["st"].resid.max())) for r in runs}
     if fp64 is not None:
         fp64["speedup_mixed_vs_fp64"] = fp64["wall"] / wall
+    dom = max((k for k in kern if kern[k]["bytes"] > 0), key=lambda k: kern[k]["ms"])
+    kd = kern[dom]
+    achieved = kd["bytes"] / (kd["ms"] * 1e-3) / 1e9
+    total_ms = sum(v["ms"] for v in kern.values())
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                "traffic": counter_traffic(dom, "C5"),
+                "algorithmic_bytes_per_launch": kd["bytes"] / kd["launches"] if kd["launches"] else None,
+                "scope": "the 32x32x32x64 lattice's kernels (the critical path), timed with HIP events "
+                         "on its stream while the ten small lattices run concurrently",
+                "kernel_share_of_timed_kernel_ms": kd["ms"] / total_ms if total_ms else None}
+    cpu = None
+    if not a.no_cpu:
+        # the oracle's Arnoldi steps on one lattice of each size (bounded
+        # samples), each lattice's own Arnoldi step count from its solve
+        cost = 0.0
+        samples = []
+        budget = {"C5": 0.6 * a.cpu_seconds, "C5a": 0.2 * a.cpu_seconds, "C5b": 0.2 * a.cpu_seconds}
+        fits = {}
+        for name, cfg, links, B in inputs:
+            group = name if name == "C5" else name[:3]
+            if group not in fits:
+                c = cpu_baseline(cfg, links, synth.kappa(name), B[0], budget[group], [])
+                fits[group] = c
+                samples.append("%d steps on %s in %.1f s (t = %.3f s + (j+1) * %.4f s)"
+                               % (c["steps"], "x".join(map(str, cfg["dims"])), c["seconds"],
+                                  c["t_mv"], c["t_col"]))
+            c = fits[group]
+            r = next(x for x in runs if x["name"] == name)
+            steps = arnoldi_columns(r["st"], cfg, len(cfg["rhs"]))
+            cost += sum(c["t_mv"] + (j + 1) * c["t_col"] for j in steps)
+        cpu = dict(value=cost / nrhs, unit="s", cores=fits["C5"]["threads"], kind="oracle",
+                   host=host_info(),
+                   sample="oracle GMRES-DR-Sh Arnoldi steps (matvec + CGS2): " + "; ".join(samples)
+                          + "; scaled to each lattice's own Arnoldi steps in the GPU solve, summed, "
+                            "per RHS (extrapolated; the oracle solves the lattices one after another)")
+        log("bench: cpu", cpu)
     out = {
         "metric": METRIC, "value": wall / nrhs, "unit": "s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": wall * 1e3, "higher_is_better": False,
@@ -279,7 +355,7 @@ def uneven_batch(a, gdr, synth, torch, np):
                    "name": "C5", "nrhs": nrhs, "global_batch": nrhs, "parallelism": "1 GPU",
                    "precision": "mixed: FP32 matvec/Gram-Schmidt/basis, FP64 small problems, "
                                 "accumulation and refinement"},
-        "roofline": None, "fp64": fp64, "cpu_baseline": None,
+        "roofline": roofline, "fp64": fp64, "cpu_baseline": cpu, "kernels_big_lattice": kern,
         "max_true_resid": max(v["max_true_resid"] for v in per.values()), "lattices": per,
     }
     print(json.dumps(out), flush=True)
@@ -308,6 +384,9 @@ def main():
                     help="tolerance of the extra right-hand side (default: the workload's)")
     ap.add_argument("--refine-floor", type=float, default=0.0,
                     help="inner tolerance floor of the cleanup's refinement rounds (0: library default)")
+    ap.add_argument("--c5-links", choices=["f16", "f32"], default="f16",
+                    help="link storage of the uneven batch's 32^3x64 lattice (default: the "
+                         "workload's FP16)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="end with a 256 MiB device copy (calibrates hardware byte counters)")
     a = ap.parse_args()
@@ -418,6 +497,7 @@ def main():
         steps = arnoldi_columns(st, cfg, nrhs)
         c = cpu_baseline(cfg, links, kappa, b0, a.cpu_seconds, steps)
         cpu = dict(value=c["cost"] / nrhs, unit="s", cores=c["threads"], kind="oracle",
+                   host=host_info(),
                    sample="%d oracle GMRES-DR-Sh Arnoldi steps (matvec + CGS2) on RHS 1 of the "
                           "same workload in %.1f s; fit t = %.3f s + (j+1) * %.4f s, scaled to the "
                           "%d Arnoldi steps the GPU solve took, per RHS (extrapolated)"

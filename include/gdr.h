@@ -90,7 +90,10 @@ const char* gdr_last_error(gdr_ctx ctx);
  * >= 2. bc[mu] is +1 (periodic) or -1 (antiperiodic). `links` is host memory
  * (links_on_device = 0) or device memory (1) in the canonical link layout;
  * it is copied into internal tile-blocked layouts (FP64 always, plus FP32
- * or FP16 per link_storage for the FP32 operator) and not retained.
+ * or FP16 per link_storage for the FP32 operator; with FP16 storage also an
+ * FP32 copy, which the refinement solves of the mixed-precision cleanup use)
+ * and not retained. Special unitary links in FP32 are kept as their first two
+ * rows on lattices whose extents are multiples of 4 (gdr_op_link_bytes).
  * Errors: ARG, OOM, HIP. */
 int gdr_wilson_create(gdr_ctx ctx, const int dims[4], const int bc[4], double kappa,
                       const gdr_c64* links, int links_on_device, int link_storage,

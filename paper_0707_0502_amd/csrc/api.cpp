@@ -289,7 +289,8 @@ int gdr_wilson_create(gdr_ctx c, const int dims[4], const int bc[4], double kapp
         HIPCHK(hipMemcpyAsync(tmp, links, nl * sizeof(double2), hipMemcpyHostToDevice, c->st));
         src = tmp;
     }
-    if (op->lst == GDR_LINKS_F32 && op->g.ltv == 8) {
+    bool su3 = false;
+    if (op->g.ltv == 8) {
         // special unitary links (to 1e-9) are stored for the FP32 operator as
         // their first two rows; any other field keeps all nine entries
         DMem mem;
@@ -302,12 +303,20 @@ int gdr_wilson_create(gdr_ctx c, const int dims[4], const int bc[4], double kapp
         double dev;
         std::memcpy(&dev, &bits, sizeof(dev));
         op->su3_dev = dev;
-        if (dev <= 1e-9) op->lst = LINK_R12;
+        su3 = dev <= 1e-9;
+        if (su3 && op->lst == GDR_LINKS_F32) op->lst = LINK_R12;
     }
     const size_t nlo = op->lst == LINK_R12 ? (size_t)24 * vol : nl;
     HIPCHK(hipMalloc(&op->ulo, nlo * (op->lst == GDR_LINKS_F16 ? sizeof(__half2) : sizeof(float2))));
     pack_links(src, op->u64, GDR_LINKS_F64, op->g, bc, c->st);
     pack_links(src, op->ulo, op->lst, op->g, bc, c->st);
+    if (op->lst == GDR_LINKS_F16) {
+        // FP32 copy for the refinement solves of the mixed-precision cleanup:
+        // an inner solve on FP16-rounded links gains only about 1e-3 per round
+        op->lre = su3 ? LINK_R12 : GDR_LINKS_F32;
+        HIPCHK(hipMalloc(&op->ure, (su3 ? (size_t)24 * vol : nl) * sizeof(float2)));
+        pack_links(src, op->ure, op->lre, op->g, bc, c->st);
+    }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->st));
     if (tmp) (void)hipFree(tmp);
@@ -317,6 +326,7 @@ int gdr_wilson_create(gdr_ctx c, const int dims[4], const int bc[4], double kapp
     catch (const GdrError& e) {
         if (op->u64) (void)hipFree(op->u64);
         if (op->ulo) (void)hipFree(op->ulo);
+        if (op->ure) (void)hipFree(op->ure);
         delete op;
         return fail(c, e.code, e.what());
     }
@@ -326,6 +336,7 @@ void gdr_op_destroy(gdr_op op) {
     if (!op) return;
     if (op->u64) (void)hipFree(op->u64);
     if (op->ulo) (void)hipFree(op->ulo);
+    if (op->ure) (void)hipFree(op->ure);
     if (op->bd64) (void)hipFree(op->bd64);
     if (op->bd32) (void)hipFree(op->bd32);
     delete op;

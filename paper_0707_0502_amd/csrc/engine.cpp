@@ -30,11 +30,11 @@ static inline double zabs(double2 a) { return std::hypot(a.x, a.y); }
 
 template <typename T>
 static const void* links_for(gdr_op_s* op) {
-    return std::is_same<T, double>::value ? (const void*)op->u64 : op->ulo;
+    return std::is_same<T, double>::value ? (const void*)op->u64 : op->refine ? op->ure : op->ulo;
 }
 template <typename T>
 static int lst_for(gdr_op_s* op) {
-    return std::is_same<T, double>::value ? GDR_LINKS_F64 : op->lst;
+    return std::is_same<T, double>::value ? GDR_LINKS_F64 : op->refine ? op->lre : op->lst;
 }
 
 // algorithmic bytes of one Wilson launch over nvec vectors: every link and
@@ -45,9 +45,10 @@ static double dslash_bytes(gdr_op_s* op, int nvec, bool add) {
     if (op->kind == 1)   // bidiagonal: 2n matrix entries, in, out (, add) per vector
         return (double)op->n * cs * (2 + nvec * (2 + (add ? 1 : 0)));
     const double vol = op->g.vol;
+    const int ls = lst_for<T>(op);
     double link = std::is_same<T, double>::value ? 16 * 36
-                  : op->lst == LINK_R12         ? 8 * 24
-                  : op->lst == GDR_LINKS_F16    ? 4 * 36
+                  : ls == LINK_R12              ? 8 * 24
+                  : ls == GDR_LINKS_F16         ? 4 * 36
                                                 : 8 * 36;
     return vol * (link + nvec * (12 * cs * 2 + (add ? 12 * cs : 0)));
 }
@@ -1171,6 +1172,9 @@ void true_residuals(gdr_op_s* op, int ns, const double2* sig, int nrhs, const do
 
 int cleanup(gdr_op_s* op, gdr_defl_s* defl, int ns, const double2* sig, int nrhs,
             const double2* B_eo, double2* X_eo, const gdr_params& p, Stats& S) {
+    // the refinement solves apply the operator with FP32 links even where the
+    // Krylov phases used FP16-stored ones
+    RefineLinks fp32_links(op);
     hipStream_t st = op->ctx->st;
     const int64_t n = op->n;
     DMem mem;

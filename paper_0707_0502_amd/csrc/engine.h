@@ -93,6 +93,9 @@ struct gdr_op_s {
     double2* u64 = nullptr; // FP64 links (internal layout)
     void* ulo = nullptr;    // FP32, FP16 or FP32 two-row (LINK_R12) links
     int lst = GDR_LINKS_F32;
+    void* ure = nullptr;    // FP16 storage only: FP32 links (lre: FP32 or LINK_R12) for the
+    int lre = GDR_LINKS_F32;  //   cleanup's refinement solves
+    bool refine = false;    // the FP32 operator reads ure while set (RefineLinks)
     int anti = 0;           // bit mu: direction mu antiperiodic (bc[mu] = -1)
     double su3_dev = -1;    // largest deviation of the links from SU(3) (-1: not checked)
     int kind = 0;             // 0: Wilson-Dirac lattice operator, 1: bidiagonal matrix
@@ -120,6 +123,17 @@ void op_pack(gdr_op_s* op, const double2* canon, typename CT<T>::t* dst, int64_t
 template <typename T>
 void op_unpack(gdr_op_s* op, const typename CT<T>::t* src, int64_t stride, double2* canon, int nvec,
                hipStream_t st);
+}  // namespace gdr
+
+namespace gdr {
+// Scope in which the FP32 operator of an FP16-storage operator reads its FP32
+// link copy (the refinement solves of the mixed-precision cleanup).
+struct RefineLinks {
+    gdr_op_s* op;
+    bool prev;
+    explicit RefineLinks(gdr_op_s* o) : op(o), prev(o->refine) { op->refine = op->ure != nullptr; }
+    ~RefineLinks() { op->refine = prev; }
+};
 }  // namespace gdr
 
 struct gdr_defl_s {
