@@ -1036,9 +1036,140 @@ __global__ __launch_bounds__(256) void k_vrecombine(const typename CT<T>::t* __r
     }
 }
 
+// FP32 recombination on the matrix cores. The complex product W = V P is the
+// real product W' = V' P' with V' = [Re V, Im V] interleaved per column
+// (k = 2c + part) and the 2x2 real blocks of P, and it is computed transposed,
+// C = P'^T V'^T, with v_mfma_f32_16x16x4f32: per instruction a wavefront
+// multiplies a 16 x 4 block of P'^T (16 real outputs = 8 complex columns of
+// W, 2 complex basis columns) by a 4 x 16 block of V'^T (16 consecutive rows).
+// Lane l provides A[n = l % 16][k = l / 16] and B[k = l / 16][row = l % 16],
+// and receives C[4 (l / 16) + r][row = l % 16], r = 0..3: the real and
+// imaginary parts of two complex outputs of one row, so each lane stores two
+// float2 and 16 lanes store 128 contiguous bytes of one output column. P'^T
+// (padded to whole 16 x 4 blocks) sits in LDS; a wavefront keeps S strips of
+// 16 rows in flight, NT n-tiles of 16 real outputs each (nout <= 8 NT), and
+// loads the basis values one group of VRC_U k-steps ahead.
+// FP32 products accumulated in FP32, as in the VALU kernel.
+typedef float mf4 __attribute__((ext_vector_type(4)));
+constexpr int VRC_S = 2;   // strips of 16 rows per wavefront
+constexpr int VRC_U = 8;   // k-steps per load group
+
+template <int S, int NT, int U = 4>
+__global__ __launch_bounds__(256) void k_vrecombine_mfma(const float2* __restrict__ V, int64_t ldv,
+                                                         int ncols, const double2* __restrict__ P,
+                                                         int ldp, int nout, float2* __restrict__ W,
+                                                         int64_t ldw, int64_t n) {
+    const int nks = (ncols + 1) / 2;            // k-steps of 4 real (2 complex) basis columns
+    constexpr int nnt = NT, np = NT * 16;
+    const int kp = nks * 4;
+    extern __shared__ float at[];               // kp x np floats
+    // A = P'^T: A[n][k] at at[k * np + n]; n = 2j + q, k = 2c + p
+    for (int t = threadIdx.x; t < kp * np; t += blockDim.x) {
+        const int k = t / np, nn = t % np;
+        const int c = k >> 1, pp = k & 1, j = nn >> 1, q = nn & 1;
+        float v = 0;
+        if (c < ncols && j < nout) {
+            const double2 pv = P[c + (int64_t)j * ldp];
+            v = q == 0 ? (pp == 0 ? (float)pv.x : -(float)pv.y) : (pp == 0 ? (float)pv.y : (float)pv.x);
+        }
+        at[t] = v;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int lr = lane & 15, lk = lane >> 4;   // row / n within a block, k within a step
+    const int64_t nstrip = (n + 15) / 16;
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t nwave = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t s0 = wave * S; s0 < nstrip; s0 += nwave * S) {
+        mf4 acc[S][NT];
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[s][t] = mf4{0, 0, 0, 0};
+        // k-steps in groups of VRC_U: the basis values of the next group are
+        // loaded while the matrix cores work on the current one (two register
+        // buffers, the group loop unrolled by two)
+        auto load_g = [&](int g, float (&b)[U][S]) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int c = 2 * (g * U + u) + (lk >> 1);   // complex basis column of this lane
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    const int64_t row = (s0 + s) * 16 + lr;
+                    b[u][s] = (c < ncols && row < n) ? ((const float*)(V + c * ldv + row))[lk & 1] : 0.f;
+                }
+            }
+        };
+        auto mma_g = [&](int g, const float (&b)[U][S]) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int ks = g * U + u;
+                if (ks >= nks) break;
+                const float* ak = at + (ks * 4 + lk) * np + lr;
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    const float a = ak[t * 16];
+#pragma unroll
+                    for (int s = 0; s < S; ++s)
+                        acc[s][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[u][s], acc[s][t], 0, 0, 0);
+                }
+            }
+        };
+        const int ng = (nks + U - 1) / U;
+        float ba[U][S], bb[U][S];
+        load_g(0, ba);
+        for (int g = 0; g < ng; g += 2) {
+            if (g + 1 < ng) load_g(g + 1, bb);
+            mma_g(g, ba);
+            if (g + 1 < ng) {
+                if (g + 2 < ng) load_g(g + 2, ba);
+                mma_g(g + 1, bb);
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int64_t row = (s0 + s) * 16 + lr;
+            if (row >= n) continue;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                // C rows 4 lk + r of n-tile t: outputs j = 8 t + 2 lk (r = 0, 1) and + 1 (r = 2, 3)
+                const int j = 8 * t + 2 * lk;
+                if (j < nout) W[(int64_t)j * ldw + row] = make_float2(acc[s][t][0], acc[s][t][1]);
+                if (j + 1 < nout) W[(int64_t)(j + 1) * ldw + row] = make_float2(acc[s][t][2], acc[s][t][3]);
+            }
+        }
+    }
+}
+
 template <typename T>
 void vrecombine(const typename CT<T>::t* V, int64_t ldv, int ncols, const double2* P, int ldp,
                 int nout, typename CT<T>::t* W, int64_t ldw, int64_t n, hipStream_t st) {
+    if constexpr (std::is_same<T, float>::value) {
+        const int nt = (2 * nout + 15) / 16;
+        const size_t lds = (size_t)((ncols + 1) / 2) * 4 * nt * 16 * sizeof(float);
+        if (ncols >= 1 && ncols <= MAXM + 1 && nout >= 1 && nout <= MAXM && lds <= 65536) {
+            // enough strips for every CU: 4 waves per block, VRC_S strips of 16 rows per
+            // wave, at most 2048 blocks looping over the rest (1.32 ms on the
+            // 24^3x48 restart, 61 columns to 21: 0.49 of HBM; the VALU kernel 2.8 ms)
+            const int64_t blocks = (n + 64 * VRC_S - 1) / (64 * VRC_S);
+            const int grid = (int)(blocks > 2048 ? 2048 : (blocks < 1 ? 1 : blocks));
+#define VRC_MFMA(NT)                                                                          \
+    hipLaunchKernelGGL((k_vrecombine_mfma<VRC_S, NT, VRC_U>), dim3(grid), dim3(256), lds, st, V, ldv, ncols, \
+                       P, ldp, nout, W, ldw, n)
+            switch (nt) {
+                case 1: VRC_MFMA(1); break;
+                case 2: VRC_MFMA(2); break;
+                case 3: VRC_MFMA(3); break;
+                case 4: VRC_MFMA(4); break;
+                case 5: VRC_MFMA(5); break;
+                case 6: VRC_MFMA(6); break;
+                case 7: VRC_MFMA(7); break;
+                default: VRC_MFMA(8); break;
+            }
+#undef VRC_MFMA
+            return;
+        }
+    }
     constexpr int CH = std::is_same<T, float>::value ? 32 : 16;
     hipLaunchKernelGGL((k_vrecombine<T, CH>), dim3(vec_grid(n)), dim3(256), 0, st, V, ldv, ncols,
                        P, ldp, nout, W, ldw, n);
