@@ -129,6 +129,28 @@ def dslash_standalone(gdr, ops, vol, reps=100, nsets=3):
     return rows
 
 
+TUNE_FORMS = {
+    "dslash_r12": "0/1: vector-loop kernel, x-fastest / (z,t)-blocked tile order; "
+                  "2/3: one block per tile and vector, same orders (one vector: 0/1 = orders)",
+    "vrecombine_mfma": "strips x k-steps per load group: 0 = 2x8, 1 = 4x4, 2 = 1x16",
+    "blk_update": "blocks per member: 0 = default cap, 1 = 512, 2 = 1024 or 2048, 3 = 4096",
+    "gs_update": "blocks per member: 0 = default cap, 1 = 512, 2 = 1024 or 2048, 3 = 4096",
+    "vcombine": "blocks per member: 0 = 8192, 1 = 2048, 2 = 4096, 3 = 16384",
+}
+
+
+def tune_shapes(gdr):
+    """The launch forms the tuner chose in this process, per kernel and shape."""
+    out = {}
+    for line in gdr.gdr_tune_report().splitlines():
+        key, _, rest = line.partition(" -> ")
+        if not rest:
+            continue
+        form, _, us = rest.partition(" (")
+        out[key] = {"form": int(form), "us_per_unit": float(us.split()[0])}
+    return {"chosen": out, "forms": TUNE_FORMS} if out else None
+
+
 def counter_traffic(kernel_class, workload):
     """HBM bytes per launch of a kernel class from the committed rocprofv3
     counter summary (profiles/*_traffic.md), if it covers this class and
@@ -357,6 +379,7 @@ def uneven_batch(a, gdr, synth, torch, np):
                                 "accumulation and refinement"},
         "roofline": roofline, "fp64": fp64, "cpu_baseline": cpu, "kernels_big_lattice": kern,
         "max_true_resid": max(v["max_true_resid"] for v in per.values()), "lattices": per,
+        "tune": tune_shapes(gdr),
     }
     print(json.dumps(out), flush=True)
     drop(runs)
@@ -535,6 +558,7 @@ def main():
         "max_true_resid": resid_max,
         "counters": counters,
         "kernels": kern,
+        "tune": tune_shapes(gdr),
     }
     print(json.dumps(out), flush=True)
     if a.copy_probe:

@@ -288,6 +288,30 @@ int gdr_defl_import(gdr_op op, int k, const gdr_c64* V, const gdr_c64* Hbar, int
                     gdr_defl* out);
 void gdr_defl_destroy(gdr_defl d);
 
+/* ---- Launch tuning --------------------------------------------------------
+ * Some launches have several equivalent forms (tile order and kernel variant
+ * of the Wilson operator, strips per wavefront of the restart recombination
+ * V_{k+1} = V_{m+1} P of Sec. 2.2, blocks per member of the Gram-Schmidt
+ * update sweeps and of the solution accumulation): each computes every output
+ * with the same operations in the same order, so the choice never changes a
+ * result. The first launches of a (kernel, shape) on a device time the forms
+ * in turn with HIP events; after 3 timings each the fastest is kept for the
+ * process. Environment: GDR_TUNE=0 keeps the default forms; GDR_TUNE_CACHE
+ * names a text file read at the first launch and appended to at each decision
+ * (one line "v1 <kernel>|<arch>|<shape> <form> <median us per unit of work>";
+ * malformed lines are skipped, an absent file is not an error). While forms
+ * are still timed, Arnoldi cycles run eagerly instead of from a HIP graph
+ * (at most four cycles per solve). Process-wide; thread-safe. */
+/* Read decisions from a cache file in the format above (on top of those read
+ * from GDR_TUNE_CACHE). Returns the number of lines taken, GDR_ERR_ARG for a
+ * NULL path or a file that cannot be opened. */
+int gdr_tune_load(const char* path);
+/* The decisions taken so far, one "<kernel>|<arch>|<shape> -> <form> (<us> us
+ * per unit)" line each, NUL-terminated into buf (host, len bytes, truncated
+ * to fit; buf may be NULL when len is 0). Returns the full length without the
+ * NUL, so a caller can size buf. */
+int64_t gdr_tune_report(char* buf, int64_t len);
+
 #ifdef __cplusplus
 }
 #endif

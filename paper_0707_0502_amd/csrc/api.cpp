@@ -6,6 +6,7 @@
 #include <cstring>
 
 #include "engine.h"
+#include "tune.h"
 
 using namespace gdr;
 
@@ -740,5 +741,21 @@ int gdr_defl_import(gdr_op op, int k, const gdr_c64* V, const gdr_c64* Hbar, int
 }
 
 void gdr_defl_destroy(gdr_defl d) { delete d; }
+
+int gdr_tune_load(const char* path) {
+    if (!path) return GDR_ERR_ARG;
+    const int k = tune_load(path);
+    return k < 0 ? GDR_ERR_ARG : k;
+}
+
+int64_t gdr_tune_report(char* buf, int64_t len) {
+    const std::string r = tune_report();
+    if (buf && len > 0) {
+        const size_t k = std::min<size_t>(r.size(), (size_t)(len - 1));
+        std::memcpy(buf, r.data(), k);
+        buf[k] = 0;
+    }
+    return (int64_t)r.size();
+}
 
 }  // extern "C"

@@ -10,10 +10,13 @@
 // per-column partial sums; a second kernel adds them in a fixed order, so
 // every result is bitwise reproducible. All accumulation is FP64.
 #include <cstdint>
+#include <cstdio>
 #include <initializer_list>
 #include <stdexcept>
+#include <string>
 
 #include "kernels.h"
+#include "tune.h"
 
 namespace gdr {
 
@@ -65,6 +68,26 @@ int cgs_nblk(int64_t n, int nmem, bool wide) {
     if (nb > cap) nb = cap;
     if (nb < 1) nb = 1;
     return (int)nb;
+}
+
+// Blocks per member of a row sweep whose rows are independent (update sweeps):
+// candidate 0 is cgs_nblk's choice, 1..3 other caps on the blocks per member.
+constexpr int SWEEP_NCAND = 4;
+static int sweep_nblk(int64_t n, int nmem, bool wide, int cand) {
+    const int dflt = cgs_nblk(n, nmem, wide);
+    if (cand <= 0 || cand >= SWEEP_NCAND) return dflt;
+    const int64_t alt = wide && nmem == 1 ? 1024 : 2048;
+    const int64_t caps[3] = {512, alt, 4096};
+    int64_t nb = ((n + 63) / 64 + 7) / 8;
+    if (nb > caps[cand - 1]) nb = caps[cand - 1];
+    return (int)(nb < 1 ? 1 : nb);
+}
+
+// tuning key of a row sweep: rows, members, vectors per pass, rows per lane
+static std::string sweep_shape(int64_t n, int nmem, int nx, bool r2) {
+    char b[64];
+    std::snprintf(b, sizeof b, "%lld|%d|%d|%d", (long long)n, nmem, nx, r2 ? 2 : 1);
+    return b;
 }
 
 // ---------------------------------------------------------------------------
@@ -385,9 +408,12 @@ void gs_update(const typename CT<T>::t* V, int64_t ldv, int64_t v_ms, int nc,
                int64_t y1_ms, const double2* coef, int64_t coef_ms, int64_t n, int nmem,
                hipStream_t st, const int* act) {
     constexpr bool f32 = std::is_same<T, float>::value;
-    dim3 grid(cgs_nblk(n, nmem, f32), nmem), blk(256);
     const bool r2 = f32 && pairable(n, {ldv, v_ms, x0_ms, x1 ? x1_ms : 0, y0_ms, y1 ? y1_ms : 0},
                                     {V, x0, x1, y0, y1});
+    // tuned blocks per member (identical results: rows are independent)
+    TuneScope ts("gs_update", sweep_shape(n, nmem, x1 ? 2 : 1, r2), SWEEP_NCAND, 0, st,
+                 nc + (x1 ? 4 : 2));
+    dim3 grid(sweep_nblk(n, nmem, f32, ts.choice()), nmem), blk(256);
 #define GS_UPD(NX, R)                                                                            \
     hipLaunchKernelGGL((k_gs_update<T, NX, NX, R>), grid, blk, 0, st, V, ldv, v_ms, nc, x0, x0_ms, \
                        x1, x1_ms, y0, y0_ms, y1, y1_ms, coef, coef_ms, n, act)
@@ -562,8 +588,10 @@ void blk_update(const typename CT<T>::t* V, int64_t ldv, int64_t v_ms, int nc,
                 typename CT<T>::t* X, int64_t ldx, int64_t x_ms, int nx, const double2* coef,
                 int64_t coef_ms, int64_t n, int nmem, hipStream_t st, const int* act, bool second) {
     constexpr bool f32 = std::is_same<T, float>::value;
-    dim3 grid(cgs_nblk(n, nmem, f32), nmem), blk(256);
     const bool r2 = f32 && pairable(n, {ldv, v_ms, ldx, x_ms}, {V, X});
+    // tuned blocks per member (identical results: rows are independent)
+    TuneScope ts("blk_update", sweep_shape(n, nmem, nx, r2), SWEEP_NCAND, 0, st, nc + 2 * nx);
+    dim3 grid(sweep_nblk(n, nmem, f32, ts.choice()), nmem), blk(256);
 #define BLK_UPD(NB, R)                                                                         \
     do {                                                                                       \
         if (second)                                                                            \
@@ -972,7 +1000,12 @@ void vcombine(const typename CT<T>::t* V, int64_t ldv, int64_t v_mstride, int nc
         return;
     }
     const bool r2 = f32 && pairable(n, {ldv, v_mstride}, {V});
-    const dim3 grid(vec_grid(n), nmem), blk(256);
+    // tuned grid (identical results: rows are independent)
+    TuneScope ts("vcombine", sweep_shape(n, nmem, nout, r2), 4, 0, st, ncols + nout);
+    static const int gcap[4] = {8192, 2048, 4096, 16384};
+    int64_t gx = (n + 255) / 256;
+    if (gx > gcap[ts.choice()]) gx = gcap[ts.choice()];
+    const dim3 grid((unsigned)gx, nmem), blk(256);
 #define VCOMB(R, MO)                                                                            \
     hipLaunchKernelGGL((k_vcombine<T, R, MO>), grid, blk, 0, st, V, ldv, v_mstride, ncols, coef, \
                        ldc, c_mstride, nout, out, o_stride, o_mstride, keep_mask, n, act)
@@ -1151,11 +1184,23 @@ void vrecombine(const typename CT<T>::t* V, int64_t ldv, int ncols, const double
             // enough strips for every CU: 4 waves per block, VRC_S strips of 16 rows per
             // wave, at most 2048 blocks looping over the rest (1.32 ms on the
             // 24^3x48 restart, 61 columns to 21: 0.49 of HBM; the VALU kernel 2.8 ms)
-            const int64_t blocks = (n + 64 * VRC_S - 1) / (64 * VRC_S);
+            // tuned (identical results: every output sums its k-steps in the same
+            // order): strips per wavefront and k-steps per load group
+            char shape[64];
+            std::snprintf(shape, sizeof shape, "%lld|%d|%d", (long long)n, ncols, nout);
+            TuneScope ts("vrecombine_mfma", shape, 3, 0, st);
+            const int S = ts.choice() == 1 ? 4 : ts.choice() == 2 ? 1 : VRC_S;
+            const int64_t blocks = (n + 64 * S - 1) / (64 * S);
             const int grid = (int)(blocks > 2048 ? 2048 : (blocks < 1 ? 1 : blocks));
-#define VRC_MFMA(NT)                                                                          \
-    hipLaunchKernelGGL((k_vrecombine_mfma<VRC_S, NT, VRC_U>), dim3(grid), dim3(256), lds, st, V, ldv, ncols, \
-                       P, ldp, nout, W, ldw, n)
+#define VRC_MFMA1(S_, NT, U_)                                                                 \
+    hipLaunchKernelGGL((k_vrecombine_mfma<S_, NT, U_>), dim3(grid), dim3(256), lds, st, V, ldv, \
+                       ncols, P, ldp, nout, W, ldw, n)
+#define VRC_MFMA(NT)                                             \
+    do {                                                         \
+        if (ts.choice() == 1) VRC_MFMA1(4, NT, 4);               \
+        else if (ts.choice() == 2) VRC_MFMA1(1, NT, 16);         \
+        else VRC_MFMA1(VRC_S, NT, VRC_U);                        \
+    } while (0)
             switch (nt) {
                 case 1: VRC_MFMA(1); break;
                 case 2: VRC_MFMA(2); break;
@@ -1167,6 +1212,7 @@ void vrecombine(const typename CT<T>::t* V, int64_t ldv, int ncols, const double
                 default: VRC_MFMA(8); break;
             }
 #undef VRC_MFMA
+#undef VRC_MFMA1
             return;
         }
     }

@@ -17,7 +17,9 @@
 // own L2; a batched launch puts the blocks of one tile for all its vectors
 // next to each other, so they share the tile's links through L2.
 #include "kernels.h"
+#include "tune.h"
 
+#include <cstdio>
 #include <stdexcept>
 #include <type_traits>
 
@@ -627,6 +629,21 @@ struct TileGeo {
     }
 };
 
+// Tile of sequence position q (per XCD, after the block remap) in tile order
+// `order`: 0 lexicographic (x fastest); 1 whole xy planes of tiles, then
+// 2 x 2 blocks of (z, t) tile coordinates (needs nt2 and nt3 even), so that
+// z and t neighbours come closer in the sequence
+__device__ __forceinline__ int tile_of(const Geom& g, int q, int order) {
+    if (order == 0) return q;
+    const int nxy = g.nt[0] * g.nt[1];
+    const int txy = q % nxy;
+    int r = q / nxy;
+    const int zl = r & 1, tl = (r >> 1) & 1;
+    r >>= 2;
+    const int zb = r % (g.nt[2] >> 1), tb = r / (g.nt[2] >> 1);
+    return txy + nxy * ((2 * zb + zl) + g.nt[2] * (2 * tb + tl));
+}
+
 // storage index of face entry e (0..511) of tile geometry tg: face f = e / 64
 // (2 mu + dir), site j = e % 64 across that face in the neighbouring tile
 __device__ __forceinline__ int halo_source(const TileGeo tg, int e) {
@@ -758,7 +775,7 @@ __global__ __launch_bounds__(256, 3) void k_dslash_r12(const float2* __restrict_
                                                       const float2* __restrict__ add, int64_t add_stride,
                                                       const float2* __restrict__ links, Geom g, float kappa,
                                                       DiagList dl, const int* __restrict__ act, int nvec,
-                                                      int anti) {
+                                                      int anti, int order) {
     __shared__ float2 sp[12 * 256];
     __shared__ float2 hl[8 * 6 * 64];
     const int nb = gridDim.x;
@@ -766,7 +783,7 @@ __global__ __launch_bounds__(256, 3) void k_dslash_r12(const float2* __restrict_
     const int lbv = (nb % 8 == 0) ? ((b % 8) * (nb / 8) + b / 8) : b;
     const int v = lbv % nvec;
     if (act && !act[v]) return;   // inactive member: uniform over the block, nothing loaded
-    const TileGeo tg(g, lbv / nvec);
+    const TileGeo tg(g, tile_of(g, lbv / nvec, order));
     const int local = threadIdx.x;
     const int site0 = (tg.T << 8) | local;
     const int64_t V = g.vol;
@@ -825,12 +842,12 @@ __global__ __launch_bounds__(256, 2) void k_dslash_r12v(const float2* __restrict
                                                        float2* __restrict__ out, int64_t out_stride,
                                                        const float2* __restrict__ links, Geom g, float kappa,
                                                        DiagList dl, const int* __restrict__ act, int nvec,
-                                                       int anti) {
+                                                       int anti, int order) {
     __shared__ float2 sp[12 * 256];
     __shared__ float2 hl[8 * 6 * 64];
     const int nb = gridDim.x;
     const int b = blockIdx.x;
-    const TileGeo tg(g, (nb % 8 == 0) ? ((b % 8) * (nb / 8) + b / 8) : b);
+    const TileGeo tg(g, tile_of(g, (nb % 8 == 0) ? ((b % 8) * (nb / 8) + b / 8) : b, order));
     const int local = threadIdx.x;
     const int site0 = (tg.T << 8) | local;
     const int64_t V = g.vol;
@@ -936,14 +953,24 @@ void dslash(const typename CT<TS>::t* in, int64_t in_stride, typename CT<TS>::t*
     if constexpr (std::is_same<TS, float>::value) {
         if (link_storage == LINK_R12) {
             if (g.ltv != 8) throw std::invalid_argument("dslash: LINK_R12 needs 4^4 tiles");
-            if (nvec >= DSLASH_VLOOP_MIN && !add)
+            // tuned choices (identical results): tile order, and for several
+            // vectors the vector-loop kernel or one block per tile and vector
+            const bool zt = g.nt[2] % 2 == 0 && g.nt[3] % 2 == 0;
+            const bool loop = nvec >= DSLASH_VLOOP_MIN && !add;
+            const int norder = zt ? 2 : 1;
+            char shape[96];
+            std::snprintf(shape, sizeof shape, "%dx%dx%dx%d|%d|%d", g.L[0], g.L[1], g.L[2], g.L[3],
+                          nvec, add ? 1 : 0);
+            TuneScope ts("dslash_r12", shape, loop ? 2 * norder : norder, 0, st);
+            const int order = ts.choice() % norder;
+            if (loop && ts.choice() < norder)
                 hipLaunchKernelGGL(k_dslash_r12v, dim3(g.vol >> 8), dim3(256), 0, st, in, in_stride,
                                    out, out_stride, (const float2*)links, g, (float)kappa, dl, act,
-                                   nvec, anti);
+                                   nvec, anti, order);
             else
                 hipLaunchKernelGGL(k_dslash_r12, grid, dim3(256), 0, st, in, in_stride, out,
                                    out_stride, add, add_stride, (const float2*)links, g,
-                                   (float)kappa, dl, act, nvec, anti);
+                                   (float)kappa, dl, act, nvec, anti, order);
             return;
         }
     }

@@ -14,6 +14,7 @@
 #include <limits>
 
 #include "engine.h"
+#include "tune.h"
 
 gdr_defl_s::~gdr_defl_s() {
     if (V) (void)hipFree(V);
@@ -320,6 +321,7 @@ struct Arnoldi {
     };
     std::vector<Cached> graphs;
     bool use_graph = false;
+    int eager_tuning = 0;   // cycles run eagerly for the launch tuner
 
     void body(int j0, const int* act, int nact) {
         fill_int(brk, -1, nmem, st);
@@ -339,15 +341,27 @@ struct Arnoldi {
             body(j0, act, nact);
             return;
         }
+        // while the launch tuner still times this cycle's kernels, the cycle
+        // runs eagerly (captured launches are not timed); at most 4 such cycles
+        if (eager_tuning < 4 && tune_active()) {
+            const long before = tune_new_open();
+            body(j0, act, nact);
+            ++eager_tuning;
+            if (tune_new_open() == before && tune_open() == 0) eager_tuning = 4;
+            return;
+        }
         for (auto& c : graphs)
             if (c.v == V && c.h == H && c.j0 == j0) {
                 HIPCHK(hipGraphLaunch(c.e, st));
                 return;
             }
         Cached c{V, H, j0, nullptr, nullptr};
-        HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        body(j0, act, nact);
-        HIPCHK(hipStreamEndCapture(st, &c.g));
+        {
+            TuneCaptureGuard quiet;   // no tuner event calls in any thread meanwhile
+            HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            body(j0, act, nact);
+            HIPCHK(hipStreamEndCapture(st, &c.g));
+        }
         HIPCHK(hipGraphInstantiate(&c.e, c.g, nullptr, nullptr, 0));
         graphs.push_back(c);
         HIPCHK(hipGraphLaunch(c.e, st));

@@ -36,7 +36,7 @@ SYMBOLS = [
     "gdr_op_tables", "gdr_op_dslash_bench",
     "gdr_params_default",
     "gdr_solve_dr_sh", "gdr_solve_proj_sh", "gdr_solve", "gdr_defl_k", "gdr_defl_export",
-    "gdr_defl_import", "gdr_defl_destroy",
+    "gdr_defl_import", "gdr_defl_destroy", "gdr_tune_load", "gdr_tune_report",
 ]
 
 
@@ -113,6 +113,9 @@ def load(path=LIB_PATH):
     lib.gdr_defl_import.argtypes = [vp, ip, vp, vp, ip, ctypes.POINTER(vp)]
     lib.gdr_defl_destroy.argtypes = [vp]
     lib.gdr_defl_destroy.restype = None
+    lib.gdr_tune_load.argtypes = [ctypes.c_char_p]
+    lib.gdr_tune_report.argtypes = [ctypes.c_char_p, i64]
+    lib.gdr_tune_report.restype = i64
     return lib
 
 
@@ -401,3 +404,17 @@ def gdr_defl_import(op, k, V, Hbar, precision=GDR_PREC_F64):
 
 def gdr_defl_destroy(defl):
     lib().gdr_defl_destroy(defl.h)
+
+
+def gdr_tune_load(path):
+    """Read launch-tuning decisions from a cache file; returns the lines taken
+    (GDR_ERR_ARG if the file cannot be opened)."""
+    return lib().gdr_tune_load(os.fsencode(path))
+
+
+def gdr_tune_report():
+    """The launch-tuning decisions so far, one line each."""
+    n = lib().gdr_tune_report(None, 0)
+    buf = ctypes.create_string_buffer(int(n) + 1)
+    lib().gdr_tune_report(buf, n + 1)
+    return buf.value.decode()

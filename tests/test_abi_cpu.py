@@ -74,3 +74,31 @@ def test_binding_rejects_missing_library(tmp_path):
     from paper_0707_0502_amd import gdr
     with pytest.raises(ImportError):
         gdr.load(str(tmp_path / "nope.so"))
+
+
+def test_tune_cache_parser(tmp_path):
+    """The launch-tuning cache reader takes well-formed "v1 <key> <form> <us>"
+    lines only and survives corrupt, absent and NULL inputs (host code only:
+    nothing here touches a device)."""
+    lib = ctypes.CDLL(LIB)
+    lib.gdr_tune_load.argtypes = [ctypes.c_char_p]
+    lib.gdr_tune_report.argtypes = [ctypes.c_char_p, ctypes.c_int64]
+    lib.gdr_tune_report.restype = ctypes.c_int64
+    f = tmp_path / "tune.txt"
+    f.write_bytes(b"v1 dslash_r12|gfx950|8x8x8x16|3|0 1 12.5\n"
+                  b"garbage\n\n"
+                  b"v2 dslash_r12|gfx950|8x8x8x16|3|0 1 12.5\n"
+                  b"v1 blk_update|gfx950|1|1|1|1 -1 3\n"
+                  b"v1 blk_update|gfx950|1|1|1|1 8 3\n"
+                  b"v1 blk_update|gfx950|1|1|1|1 1 nan\n"
+                  b"v1 blk_update|gfx950|1|1|1|1 1 -2\n"
+                  b"\xff\xfe\x00 binary\n"
+                  b"v1 onlykey\n"
+                  b"v1 vcombine|gfx950|7962624|1|3|2 3 0.25\n")
+    assert lib.gdr_tune_load(str(f).encode()) == 2
+    assert lib.gdr_tune_load(str(tmp_path / "absent.txt").encode()) == -1
+    assert lib.gdr_tune_load(None) == -1
+    # decisions are reported once a launch has used them; none on the host
+    assert lib.gdr_tune_report(None, 0) == 0
+    buf = ctypes.create_string_buffer(4)
+    assert lib.gdr_tune_report(buf, 4) == 0 and buf.value == b""
