@@ -17,6 +17,7 @@ struct Entry {
     int best = -1;                                 // decided candidate, -1 while tuning
     double best_us = 0;
     std::vector<std::vector<float>> ms;            // completed timings per candidate
+    std::vector<int> issued;                       // timings issued per candidate
     int next = 0;                                  // next candidate to time
 };
 
@@ -142,6 +143,7 @@ void harvest(State& s) {
         const bool ok = hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess;
         if (!ok) (void)hipGetLastError();
         auto it = s.table.find(p.key);
+        if (!ok && it != s.table.end() && it->second.best < 0) --it->second.issued[p.cand];
         if (ok && it != s.table.end() && it->second.best < 0) {
             Entry& e = it->second;
             e.ms[p.cand].push_back((float)(ms / p.work));
@@ -182,6 +184,7 @@ TuneScope::TuneScope(const char* kernel, const std::string& shape, int ncand, in
         Entry e;
         e.ncand = ncand;
         e.ms.assign(ncand, {});
+        e.issued.assign(ncand, 0);
         auto st_it = s.stored.find(key_);
         if (st_it != s.stored.end() && st_it->second.first < ncand) {
             e.best = st_it->second.first;
@@ -199,9 +202,17 @@ TuneScope::TuneScope(const char* kernel, const std::string& shape, int ncand, in
     }
     // graph capture here or in another thread: default, not timed
     if (capturing || s.capturing > 0) return;
-    // candidates in turn
-    choice_ = e.next;
-    e.next = (e.next + 1) % ncand;
+    // candidates in turn, TUNE_REPS timings each; launches issued while the
+    // last timings are still in flight take the default
+    int c = -1;
+    for (int t = 0; t < ncand && c < 0; ++t) {
+        const int q = (e.next + t) % ncand;
+        if (e.issued[q] < TUNE_REPS) c = q;
+    }
+    if (c < 0) return;
+    choice_ = c;
+    e.next = (c + 1) % ncand;
+    ++e.issued[c];
     a_ = get_event(s);
     if (a_ && hipEventRecord(a_, st) != hipSuccess) {   // error left for the caller's check
         s.pool.push_back(a_);
@@ -213,14 +224,20 @@ TuneScope::~TuneScope() {
     if (!a_) return;
     State& s = S();
     std::lock_guard<std::mutex> g(s.mu);
+    auto untime = [&] {   // this timing will not complete: its slot is issued again
+        auto it = s.table.find(key_);
+        if (it != s.table.end() && it->second.best < 0) --it->second.issued[choice_];
+    };
     if (s.capturing > 0) {   // a capture began meanwhile: drop this timing
         s.pool.push_back(a_);
+        untime();
         return;
     }
     hipEvent_t b = get_event(s);
     if (!b || hipEventRecord(b, st_) != hipSuccess) {   // error left for the caller's check
         s.pool.push_back(a_);
         if (b) s.pool.push_back(b);
+        untime();
         return;
     }
     s.pend.push_back({key_, choice_, work_, a_, b});
