@@ -107,7 +107,8 @@ def dslash_standalone(gdr, ops, vol, reps=100, nsets=3):
     one set), batch sizes 1, 3, 11, 12. Algorithmic bytes per launch count each
     link and spinor once (links amortised over the batch), the links as the
     operator stores them (gdr_op_link_bytes: 192 B/site for special unitary
-    FP32 links kept as two rows, 288 for nine entries, 144 FP16, 576 FP64),
+    FP32 links kept as two rows, 288 for nine entries, 96 and 144 for FP16
+    two-row and nine-entry storage, 576 FP64),
     spinors 192 B/site/vector FP32, 384 FP64. `gbs_480` restates FP32 rates
     on the nine-entry count (288 + 192 nb) for comparison with it."""
     import numpy as np
@@ -411,6 +412,9 @@ def main():
     ap.add_argument("--c5-links", choices=["f16", "f32"], default="f16",
                     help="link storage of the uneven batch's 32^3x64 lattice (default: the "
                          "workload's FP16)")
+    ap.add_argument("--hw-queues", type=int, default=12,
+                    help="hardware queues per process for the uneven batch (C5; 0: the "
+                         "environment's setting)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="end with a 256 MiB device copy (calibrates hardware byte counters)")
     a = ap.parse_args()
@@ -419,11 +423,14 @@ def main():
               "(requested --gpus %d)" % a.gpus, file=sys.stderr)
         sys.exit(2)
 
-    if a.workload == "C5":
+    if not 0 <= a.hw_queues <= 32:
+        print("--hw-queues must be 0..32", file=sys.stderr)
+        sys.exit(2)
+    if a.workload == "C5" and a.hw_queues > 0:
         # eleven concurrent streams: more hardware queues than HIP's default 4
         # let the small lattices' launches stop queueing behind the large
-        # one's (set before the HIP runtime starts; an explicit setting wins)
-        os.environ.setdefault("GPU_MAX_HW_QUEUES", "12")
+        # one's (must be set before the HIP runtime starts)
+        os.environ["GPU_MAX_HW_QUEUES"] = str(a.hw_queues)
 
     import numpy as np
     import torch

@@ -92,8 +92,9 @@ const char* gdr_last_error(gdr_ctx ctx);
  * it is copied into internal tile-blocked layouts (FP64 always, plus FP32
  * or FP16 per link_storage for the FP32 operator; with FP16 storage also an
  * FP32 copy, which the refinement solves of the mixed-precision cleanup use)
- * and not retained. Special unitary links in FP32 are kept as their first two
- * rows on lattices whose extents are multiples of 4 (gdr_op_link_bytes).
+ * and not retained. Special unitary links (to 1e-9) on lattices whose
+ * extents are multiples of 4 are kept, in FP32 or FP16, as their first two
+ * rows (gdr_op_link_bytes).
  * Errors: ARG, OOM, HIP. */
 int gdr_wilson_create(gdr_ctx ctx, const int dims[4], const int bc[4], double kappa,
                       const gdr_c64* links, int links_on_device, int link_storage,
@@ -115,10 +116,10 @@ int64_t gdr_op_size(gdr_op op);
 
 /* Bytes of link storage per lattice site that one application of the
  * operator reads at `precision` (GDR_PREC_F64: 576; GDR_PREC_F32: 288 for
- * FP32 links, 144 for FP16-stored links, 192 when the links are special
- * unitary and stored as their first two rows, the third being rebuilt as
- * the conjugated cross product of the two - chosen by gdr_wilson_create for
- * FP32 storage on lattices whose extents are multiples of 4). -1 for a
+ * FP32 links, 144 for FP16-stored links, 192 (FP32) or 96 (FP16) when the
+ * links are special unitary and stored as their first two rows, the third
+ * being rebuilt as the conjugated cross product of the two - chosen by
+ * gdr_wilson_create on lattices whose extents are multiples of 4). -1 for a
  * non-lattice operator or an unknown precision. */
 int gdr_op_link_bytes(gdr_op op, int precision);
 

@@ -312,12 +312,15 @@ int gdr_wilson_create(gdr_ctx c, const int dims[4], const int bc[4], double kapp
         op->su3_dev = dev;
         su3 = dev <= 1e-9;
         if (su3 && op->lst == GDR_LINKS_F32) op->lst = LINK_R12;
+        if (su3 && op->lst == GDR_LINKS_F16) op->lst = LINK_R12H;
     }
-    const size_t nlo = op->lst == LINK_R12 ? (size_t)24 * vol : nl;
-    HIPCHK(hipMalloc(&op->ulo, nlo * (op->lst == GDR_LINKS_F16 ? sizeof(__half2) : sizeof(float2))));
+    const bool two_row = op->lst == LINK_R12 || op->lst == LINK_R12H;
+    const bool fp16 = op->lst == GDR_LINKS_F16 || op->lst == LINK_R12H;
+    const size_t nlo = two_row ? (size_t)24 * vol : nl;
+    HIPCHK(hipMalloc(&op->ulo, nlo * (fp16 ? sizeof(__half2) : sizeof(float2))));
     pack_links(src, op->u64, GDR_LINKS_F64, op->g, bc, c->st);
     pack_links(src, op->ulo, op->lst, op->g, bc, c->st);
-    if (op->lst == GDR_LINKS_F16) {
+    if (fp16) {
         // FP32 copy for the refinement solves of the mixed-precision cleanup:
         // an inner solve on FP16-rounded links gains only about 1e-3 per round
         op->lre = su3 ? LINK_R12 : GDR_LINKS_F32;
@@ -410,7 +413,10 @@ int gdr_op_link_bytes(gdr_op op, int precision) {
     if (!op || op->kind != 0) return -1;
     if (precision == GDR_PREC_F64) return 4 * 9 * 16;
     if (precision != GDR_PREC_F32) return -1;
-    return op->lst == LINK_R12 ? 4 * 6 * 8 : op->lst == GDR_LINKS_F16 ? 4 * 9 * 4 : 4 * 9 * 8;
+    return op->lst == LINK_R12    ? 4 * 6 * 8
+           : op->lst == LINK_R12H ? 4 * 6 * 4
+           : op->lst == GDR_LINKS_F16 ? 4 * 9 * 4
+                                      : 4 * 9 * 8;
 }
 
 int gdr_op_apply(gdr_op op, gdr_c64 sigma, const gdr_c64* x, gdr_c64* y, int nvec, int precision) {

@@ -517,13 +517,16 @@ struct DslashHaloK {
 // boundary factor bc[mu] = -1 is applied here on the last slice (the stored
 // links carry none, since -U is not special unitary). 4^4 tiles only.
 
-// link of one hop: rows 0 and 1 at site ls, row 2 rebuilt
-__device__ __forceinline__ void ld_r12(const float2* __restrict__ lk, int64_t V, int ls,
+// link of one hop: rows 0 and 1 at site ls (FP32 or FP16 entries), row 2
+// rebuilt in FP32
+template <typename LT>
+__device__ __forceinline__ void ld_r12(const LT* __restrict__ lk, int64_t V, int ls,
                                        Z<float> (&u)[3][3]) {
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int bb = 0; bb < 3; ++bb) u[a][bb] = ld<float>(at(lk + (a * 3 + bb) * V, (unsigned)ls * 8u));
+        for (int bb = 0; bb < 3; ++bb)
+            u[a][bb] = ld<float>(at(lk + (a * 3 + bb) * V, (unsigned)ls * (unsigned)sizeof(LT)));
 #pragma unroll
     for (int bb = 0; bb < 3; ++bb) {
         const int b1 = (bb + 1) % 3, b2 = (bb + 2) % 3;
@@ -769,11 +772,13 @@ __device__ __forceinline__ void finish_r12(const Z<float> (&acc)[4][3], const fl
         }
 }
 
-// One block per (tile, vector): the halo kernel's staging with LINK_R12 links.
+// One block per (tile, vector): the halo kernel's staging with two-row links
+// (LT = float2: LINK_R12, __half2: LINK_R12H).
+template <typename LT>
 __global__ __launch_bounds__(256, 3) void k_dslash_r12(const float2* __restrict__ in, int64_t in_stride,
                                                       float2* __restrict__ out, int64_t out_stride,
                                                       const float2* __restrict__ add, int64_t add_stride,
-                                                      const float2* __restrict__ links, Geom g, float kappa,
+                                                      const LT* __restrict__ links, Geom g, float kappa,
                                                       DiagList dl, const int* __restrict__ act, int nvec,
                                                       int anti, int order) {
     __shared__ float2 sp[12 * 256];
@@ -838,9 +843,10 @@ __global__ __launch_bounds__(256, 3) void k_dslash_r12(const float2* __restrict_
 // boundary sign folded in) stay in registers for every vector; each vector
 // is staged and applied as in k_dslash_r12 (no added vector: launches with
 // one go to k_dslash_r12). Inactive members are skipped.
+template <typename LT>
 __global__ __launch_bounds__(256, 2) void k_dslash_r12v(const float2* __restrict__ in, int64_t in_stride,
                                                        float2* __restrict__ out, int64_t out_stride,
-                                                       const float2* __restrict__ links, Geom g, float kappa,
+                                                       const LT* __restrict__ links, Geom g, float kappa,
                                                        DiagList dl, const int* __restrict__ act, int nvec,
                                                        int anti, int order) {
     __shared__ float2 sp[12 * 256];
@@ -951,8 +957,9 @@ void dslash(const typename CT<TS>::t* in, int64_t in_stride, typename CT<TS>::t*
             int nvec, hipStream_t st, const int* act, int anti) {
     dim3 grid(((g.vol + 255) / 256) * nvec);
     if constexpr (std::is_same<TS, float>::value) {
-        if (link_storage == LINK_R12) {
-            if (g.ltv != 8) throw std::invalid_argument("dslash: LINK_R12 needs 4^4 tiles");
+        if (link_storage == LINK_R12 || link_storage == LINK_R12H) {
+            if (g.ltv != 8) throw std::invalid_argument("dslash: two-row links need 4^4 tiles");
+            const bool h = link_storage == LINK_R12H;
             // tuned choices (identical results): tile order, and for several
             // vectors the vector-loop kernel or one block per tile and vector
             const bool zt = g.nt[2] % 2 == 0 && g.nt[3] % 2 == 0;
@@ -961,16 +968,22 @@ void dslash(const typename CT<TS>::t* in, int64_t in_stride, typename CT<TS>::t*
             char shape[96];
             std::snprintf(shape, sizeof shape, "%dx%dx%dx%d|%d|%d", g.L[0], g.L[1], g.L[2], g.L[3],
                           nvec, add ? 1 : 0);
-            TuneScope ts("dslash_r12", shape, loop ? 2 * norder : norder, 0, st);
+            TuneScope ts(h ? "dslash_r12h" : "dslash_r12", shape, loop ? 2 * norder : norder, 0, st);
             const int order = ts.choice() % norder;
-            if (loop && ts.choice() < norder)
-                hipLaunchKernelGGL(k_dslash_r12v, dim3(g.vol >> 8), dim3(256), 0, st, in, in_stride,
-                                   out, out_stride, (const float2*)links, g, (float)kappa, dl, act,
-                                   nvec, anti, order);
-            else
-                hipLaunchKernelGGL(k_dslash_r12, grid, dim3(256), 0, st, in, in_stride, out,
-                                   out_stride, add, add_stride, (const float2*)links, g,
-                                   (float)kappa, dl, act, nvec, anti, order);
+#define R12_LAUNCH(LT)                                                                             \
+    do {                                                                                           \
+        if (loop && ts.choice() < norder)                                                          \
+            hipLaunchKernelGGL(k_dslash_r12v<LT>, dim3(g.vol >> 8), dim3(256), 0, st, in,          \
+                               in_stride, out, out_stride, (const LT*)links, g, (float)kappa, dl,  \
+                               act, nvec, anti, order);                                            \
+        else                                                                                       \
+            hipLaunchKernelGGL(k_dslash_r12<LT>, grid, dim3(256), 0, st, in, in_stride, out,       \
+                               out_stride, add, add_stride, (const LT*)links, g, (float)kappa, dl, \
+                               act, nvec, anti, order);                                            \
+    } while (0)
+            if (h) R12_LAUNCH(__half2);
+            else R12_LAUNCH(float2);
+#undef R12_LAUNCH
             return;
         }
     }

@@ -49,6 +49,7 @@ static double dslash_bytes(gdr_op_s* op, int nvec, bool add) {
     const int ls = lst_for<T>(op);
     double link = std::is_same<T, double>::value ? 16 * 36
                   : ls == LINK_R12              ? 8 * 24
+                  : ls == LINK_R12H             ? 4 * 24
                   : ls == GDR_LINKS_F16         ? 4 * 36
                                                 : 8 * 36;
     return vol * (link + nvec * (12 * cs * 2 + (add ? 12 * cs : 0)));

@@ -91,7 +91,7 @@ struct gdr_op_s {
     double kappa = 0;
     int64_t n = 0;          // 12 * volume
     double2* u64 = nullptr; // FP64 links (internal layout)
-    void* ulo = nullptr;    // FP32, FP16 or FP32 two-row (LINK_R12) links
+    void* ulo = nullptr;    // FP32, FP16, or two-row FP32 (LINK_R12) / FP16 (LINK_R12H) links
     int lst = GDR_LINKS_F32;
     void* ure = nullptr;    // FP16 storage only: FP32 links (lre: FP32 or LINK_R12) for the
     int lre = GDR_LINKS_F32;  //   cleanup's refinement solves

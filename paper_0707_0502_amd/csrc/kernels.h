@@ -15,8 +15,10 @@ template <typename T>
 void unpack_spinor(const typename CT<T>::t* src, int64_t stride, double2* canon, const Geom& g,
                    int nvec, hipStream_t st);
 // storage: 0 FP64 (double2), 1 FP32 (float2), 2 FP16 (__half2 per complex),
-// 3 FP32 rows 0 and 1 of special unitary links (LINK_R12; bc not folded)
+// 3 FP32 rows 0 and 1 of special unitary links (LINK_R12; bc not folded),
+// 4 the same rows in FP16 (LINK_R12H, __half2 per complex; bc not folded)
 constexpr int LINK_R12 = 3;
+constexpr int LINK_R12H = 4;
 void pack_links(const double2* canon, void* out, int storage, const Geom& g, const int bc[4],
                 hipStream_t st);
 // largest deviation of nlinks canonical 3x3 links from SU(3) (see layout.hip);

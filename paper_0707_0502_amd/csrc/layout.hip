@@ -83,12 +83,14 @@ __global__ void k_pack_links(const double2* __restrict__ canon, void* __restrict
     int c[4];
     lex_coords(g, lex, c[0], c[1], c[2], c[3]);
     const int s = site_of(g, c);
-    if (storage == 3) {
+    if (storage == 3 || storage == 4) {
         for (int mu = 0; mu < 4; ++mu) {
             const double2* src = canon + ((int64_t)mu * g.vol + lex) * 9;
-            for (int e = 0; e < 6; ++e)
-                ((float2*)out)[((int64_t)mu * 6 + e) * g.vol + s] =
-                    make_float2((float)src[e].x, (float)src[e].y);
+            for (int e = 0; e < 6; ++e) {
+                const int64_t o = ((int64_t)mu * 6 + e) * g.vol + s;
+                if (storage == 3) ((float2*)out)[o] = make_float2((float)src[e].x, (float)src[e].y);
+                else ((__half2*)out)[o] = __floats2half2_rn((float)src[e].x, (float)src[e].y);
+            }
         }
         return;
     }

@@ -132,7 +132,7 @@ def test_fp32_link_storage_choice(nv):
     antiperiodic factors applied there; a field that is not special unitary
     keeps all nine entries (288 B/site). Both match the oracle to FP32
     rounding, one vector or several per launch, with every direction
-    antiperiodic."""
+    antiperiodic. FP16 storage does the same with half the bytes."""
     from paper_0707_0502_amd import gdr
     dims, bc = (8, 4, 4, 8), (-1, -1, -1, -1)
     kappa, sig = 0.124, 0.07 - 0.02j
@@ -153,6 +153,17 @@ def test_fp32_link_storage_choice(nv):
         say("  link bytes", want, "nv", nv, "max rel err", err)
         assert err <= 1e-6
         gdr.gdr_op_destroy(op)
-    op = make_op(su3, kappa, bc, gdr.GDR_LINKS_F16)
-    assert gdr.gdr_op_link_bytes(op, gdr.GDR_PREC_F32) == 144
-    gdr.gdr_op_destroy(op)
+    # FP16 storage: two rows (96 B/site) for special unitary links, nine
+    # entries (144 B/site) otherwise; both to FP16 rounding
+    for links, want in ((su3, 96), (general, 144)):
+        ref = np.stack([wilson.apply_A(links, kappa, x.reshape(dims[::-1] + (4, 3)), sig, bc).ravel()
+                        for x in X])
+        op = make_op(links, kappa, bc, gdr.GDR_LINKS_F16)
+        assert gdr.gdr_op_link_bytes(op, gdr.GDR_PREC_F32) == want
+        y = empty(X.size)
+        gdr.gdr_op_apply(op, sig, dev(X.ravel()), y, nv, gdr.GDR_PREC_F32)
+        got = host(y).reshape(X.shape)
+        err = max(np.abs(got[v] - ref[v]).max() / np.abs(ref[v]).max() for v in range(nv))
+        say("  FP16 link bytes", want, "nv", nv, "max rel err", err)
+        assert err <= 2e-3
+        gdr.gdr_op_destroy(op)
