@@ -1,6 +1,7 @@
 """Build the HIP library libgdr.so for gfx950 with hipcc (in-tree).
 
-usage: python -m paper_0707_0502_amd.build [-j N]
+usage: python -m paper_0707_0502_amd.build [-j N] [--asan]
+(--asan: the host code built with AddressSanitizer into _build_asan/libgdr_asan.so)
 """
 import os
 import subprocess
@@ -22,22 +23,30 @@ FLAGS = [
 ]
 
 
+# AddressSanitizer build of the host code (device code unchanged), for the
+# CPU-only tests of the library's host paths: every -fsanitize= applies to the
+# host compilation only
+ASAN_OBJ = os.path.join(HERE, "_build_asan")
+ASAN_LIB = os.path.join(ASAN_OBJ, "libgdr_asan.so")
+ASAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer", "-g"]
+
+
 def sources():
     return sorted(f for f in os.listdir(SRC) if f.endswith((".hip", ".cpp")))
 
 
-def _compile(src):
-    out = os.path.join(OBJ, src + ".o")
-    cmd = [HIPCC] + FLAGS + ["-c", os.path.join(SRC, src), "-o", out]
+def _compile(src, asan=False):
+    out = os.path.join(ASAN_OBJ if asan else OBJ, src + ".o")
+    cmd = [HIPCC] + FLAGS + (ASAN_FLAGS if asan else []) + ["-c", os.path.join(SRC, src), "-o", out]
     r = subprocess.run(cmd, capture_output=True, text=True)
     return src, out, r.returncode, r.stdout + r.stderr
 
 
-def build(jobs=8, verbose=False):
-    os.makedirs(OBJ, exist_ok=True)
+def build(jobs=8, verbose=False, asan=False):
+    os.makedirs(ASAN_OBJ if asan else OBJ, exist_ok=True)
     srcs = sources()
     with ThreadPoolExecutor(max_workers=jobs) as ex:
-        results = list(ex.map(_compile, srcs))
+        results = list(ex.map(lambda f: _compile(f, asan), srcs))
     failed = False
     for src, _, rc, log in results:
         noisy = [l for l in log.splitlines() if "packed-fp32-ops" not in l and l.strip()]
@@ -48,17 +57,19 @@ def build(jobs=8, verbose=False):
             sys.stderr.write("%s:\n%s\n" % (src, "\n".join(noisy)))
     if failed:
         raise RuntimeError("HIP build failed")
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-o", tmp] + [r[1] for r in results]
+    lib = ASAN_LIB if asan else LIB
+    tmp = lib + ".tmp"
+    cmd = ([HIPCC, "--offload-arch=gfx950", "-shared"] + (["-Xarch_host", "-fsanitize=address"] if asan else [])
+           + ["-o", tmp] + [r[1] for r in results])
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":
     j = 8
     if "-j" in sys.argv:
         j = int(sys.argv[sys.argv.index("-j") + 1])
-    print(build(j, verbose="-v" in sys.argv))
+    print(build(j, verbose="-v" in sys.argv, asan="--asan" in sys.argv))
