@@ -1070,46 +1070,55 @@ __global__ __launch_bounds__(256) void k_vrecombine(const typename CT<T>::t* __r
 }
 
 // FP32 recombination on the matrix cores. The complex product W = V P is the
-// real product W' = V' P' with V' = [Re V, Im V] interleaved per column
-// (k = 2c + part) and the 2x2 real blocks of P, and it is computed transposed,
-// C = P'^T V'^T, with v_mfma_f32_16x16x4f32: per instruction a wavefront
-// multiplies a 16 x 4 block of P'^T (16 real outputs = 8 complex columns of
-// W, 2 complex basis columns) by a 4 x 16 block of V'^T (16 consecutive rows).
-// Lane l provides A[n = l % 16][k = l / 16] and B[k = l / 16][row = l % 16],
-// and receives C[4 (l / 16) + r][row = l % 16], r = 0..3: the real and
-// imaginary parts of two complex outputs of one row, so each lane stores two
-// float2 and 16 lanes store 128 contiguous bytes of one output column. P'^T
-// (padded to whole 16 x 4 blocks) sits in LDS; a wavefront keeps S strips of
-// 16 rows in flight, NT n-tiles of 16 real outputs each (nout <= 8 NT), and
-// loads the basis values one group of VRC_U k-steps ahead.
+// real product W' = V' P' with V' = [Re V, Im V] and the 2x2 real blocks of
+// P, and it is computed transposed, C = P'^T V'^T, with
+// v_mfma_f32_16x16x4f32: per instruction a wavefront multiplies a 16 x 4
+// block of P'^T (16 real outputs = 8 complex columns of W) by a 4 x 16 block
+// of V'^T (16 consecutive rows). Lane l provides A[n = l % 16][k = l / 16]
+// and B[k = l / 16][row = l % 16], and receives C[4 (l / 16) + r][row =
+// l % 16], r = 0..3: the real and imaginary parts of two complex outputs of
+// one row, so each lane stores two float2 and 16 lanes store 128 contiguous
+// bytes of one output column. The contraction index is taken in quads of four
+// complex basis columns: lane group g = l / 16 loads the whole complex entry
+// (8 bytes) of column 4q + g at its row and feeds its real part to one
+// instruction and its imaginary part to the next, whose A blocks hold the
+// matching rows of P'^T (the k index runs over (quad, part, column in quad)).
+// P'^T sits in LDS, padded to whole quads; a wavefront keeps S strips of 16
+// rows in flight, NT n-tiles of 16 real outputs each (nout <= 8 NT), and loads
+// the basis entries one group of U quads ahead.
 // FP32 products accumulated in FP32, as in the VALU kernel.
 typedef float mf4 __attribute__((ext_vector_type(4)));
 constexpr int VRC_S = 2;   // strips of 16 rows per wavefront
-constexpr int VRC_U = 8;   // k-steps per load group
+constexpr int VRC_U = 4;   // quads (8 k-steps) per load group
 
 template <int S, int NT, int U = 4>
 __global__ __launch_bounds__(256) void k_vrecombine_mfma(const float2* __restrict__ V, int64_t ldv,
                                                          int ncols, const double2* __restrict__ P,
                                                          int ldp, int nout, float2* __restrict__ W,
                                                          int64_t ldw, int64_t n) {
-    const int nks = (ncols + 1) / 2;            // k-steps of 4 real (2 complex) basis columns
-    constexpr int nnt = NT, np = NT * 16;
-    const int kp = nks * 4;
+    const int nq = (ncols + 3) / 4;             // quads of complex basis columns
+    constexpr int np = NT * 16;
+    const int kp = nq * 8;                      // real k entries: (quad, part, column in quad)
     extern __shared__ float at[];               // kp x np floats
-    // A = P'^T: A[n][k] at at[k * np + n]; n = 2j + q, k = 2c + p
+    // A = P'^T: A[nn][k] with nn = 16 tt + i at at[(k * 16 + i) * NT + tt], so
+    // that a lane reads its NT n-tiles' values contiguously; nn = 2j + q
+    // (output j, real/imag), k = (qd * 2 + pp) * 4 + g for basis column
+    // c = 4 qd + g, part pp
     for (int t = threadIdx.x; t < kp * np; t += blockDim.x) {
         const int k = t / np, nn = t % np;
-        const int c = k >> 1, pp = k & 1, j = nn >> 1, q = nn & 1;
+        const int idx = (k * 16 + (nn & 15)) * NT + (nn >> 4);
+        const int g = k & 3, pp = (k >> 2) & 1, qd = k >> 3;
+        const int c = 4 * qd + g, j = nn >> 1, q = nn & 1;
         float v = 0;
         if (c < ncols && j < nout) {
             const double2 pv = P[c + (int64_t)j * ldp];
             v = q == 0 ? (pp == 0 ? (float)pv.x : -(float)pv.y) : (pp == 0 ? (float)pv.y : (float)pv.x);
         }
-        at[t] = v;
+        at[idx] = v;
     }
     __syncthreads();
     const int lane = threadIdx.x & 63;
-    const int lr = lane & 15, lk = lane >> 4;   // row / n within a block, k within a step
+    const int lr = lane & 15, lk = lane >> 4;   // row / n within a block, column within a quad
     const int64_t nstrip = (n + 15) / 16;
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int64_t nwave = (int64_t)gridDim.x * (blockDim.x >> 6);
@@ -1119,44 +1128,49 @@ __global__ __launch_bounds__(256) void k_vrecombine_mfma(const float2* __restric
         for (int s = 0; s < S; ++s)
 #pragma unroll
             for (int t = 0; t < NT; ++t) acc[s][t] = mf4{0, 0, 0, 0};
-        // k-steps in groups of VRC_U: the basis values of the next group are
-        // loaded while the matrix cores work on the current one (two register
+        // quads in groups of U: the basis entries of the next group are loaded
+        // while the matrix cores work on the current one (two register
         // buffers, the group loop unrolled by two)
-        auto load_g = [&](int g, float (&b)[U][S]) {
+        auto load_g = [&](int g0, float2 (&b)[U][S]) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int c = 2 * (g * U + u) + (lk >> 1);   // complex basis column of this lane
+                const int c = 4 * (g0 * U + u) + lk;   // complex basis column of this lane
 #pragma unroll
                 for (int s = 0; s < S; ++s) {
                     const int64_t row = (s0 + s) * 16 + lr;
-                    b[u][s] = (c < ncols && row < n) ? ((const float*)(V + c * ldv + row))[lk & 1] : 0.f;
+                    f2v v{0.f, 0.f};
+                    if (c < ncols && row < n) v = __builtin_nontemporal_load((const f2v*)(V + c * ldv + row));
+                    b[u][s] = make_float2(v.x, v.y);
                 }
             }
         };
-        auto mma_g = [&](int g, const float (&b)[U][S]) {
+        auto mma_g = [&](int g0, const float2 (&b)[U][S]) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int ks = g * U + u;
-                if (ks >= nks) break;
-                const float* ak = at + (ks * 4 + lk) * np + lr;
+                const int qd = g0 * U + u;
+                if (qd >= nq) break;
+                const float* ar = at + ((qd * 8 + lk) * 16 + lr) * NT;   // real parts' rows
+                const float* ai = ar + 4 * 16 * NT;                       // imaginary parts' rows
 #pragma unroll
                 for (int t = 0; t < NT; ++t) {
-                    const float a = ak[t * 16];
+                    const float a0 = ar[t], a1 = ai[t];
 #pragma unroll
-                    for (int s = 0; s < S; ++s)
-                        acc[s][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[u][s], acc[s][t], 0, 0, 0);
+                    for (int s = 0; s < S; ++s) {
+                        acc[s][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b[u][s].x, acc[s][t], 0, 0, 0);
+                        acc[s][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b[u][s].y, acc[s][t], 0, 0, 0);
+                    }
                 }
             }
         };
-        const int ng = (nks + U - 1) / U;
-        float ba[U][S], bb[U][S];
+        const int ng = (nq + U - 1) / U;
+        float2 ba[U][S], bb[U][S];
         load_g(0, ba);
-        for (int g = 0; g < ng; g += 2) {
-            if (g + 1 < ng) load_g(g + 1, bb);
-            mma_g(g, ba);
-            if (g + 1 < ng) {
-                if (g + 2 < ng) load_g(g + 2, ba);
-                mma_g(g + 1, bb);
+        for (int g0 = 0; g0 < ng; g0 += 2) {
+            if (g0 + 1 < ng) load_g(g0 + 1, bb);
+            mma_g(g0, ba);
+            if (g0 + 1 < ng) {
+                if (g0 + 2 < ng) load_g(g0 + 2, ba);
+                mma_g(g0 + 1, bb);
             }
         }
 #pragma unroll
@@ -1179,13 +1193,13 @@ void vrecombine(const typename CT<T>::t* V, int64_t ldv, int ncols, const double
                 int nout, typename CT<T>::t* W, int64_t ldw, int64_t n, hipStream_t st) {
     if constexpr (std::is_same<T, float>::value) {
         const int nt = (2 * nout + 15) / 16;
-        const size_t lds = (size_t)((ncols + 1) / 2) * 4 * nt * 16 * sizeof(float);
+        const size_t lds = (size_t)((ncols + 3) / 4) * 8 * nt * 16 * sizeof(float);
         if (ncols >= 1 && ncols <= MAXM + 1 && nout >= 1 && nout <= MAXM && lds <= 65536) {
             // enough strips for every CU: 4 waves per block, VRC_S strips of 16 rows per
             // wave, at most 2048 blocks looping over the rest (1.32 ms on the
             // 24^3x48 restart, 61 columns to 21: 0.49 of HBM; the VALU kernel 2.8 ms)
-            // tuned (identical results: every output sums its k-steps in the same
-            // order): strips per wavefront and k-steps per load group
+            // tuned (identical results: every output sums its k entries in the
+            // same order): strips per wavefront and quads per load group
             char shape[64];
             std::snprintf(shape, sizeof shape, "%lld|%d|%d", (long long)n, ncols, nout);
             TuneScope ts("vrecombine_mfma", shape, 3, 0, st);
@@ -1197,8 +1211,8 @@ void vrecombine(const typename CT<T>::t* V, int64_t ldv, int ncols, const double
                        ncols, P, ldp, nout, W, ldw, n)
 #define VRC_MFMA(NT)                                             \
     do {                                                         \
-        if (ts.choice() == 1) VRC_MFMA1(4, NT, 4);               \
-        else if (ts.choice() == 2) VRC_MFMA1(1, NT, 16);         \
+        if (ts.choice() == 1) VRC_MFMA1(4, NT, 2);               \
+        else if (ts.choice() == 2) VRC_MFMA1(1, NT, 8);          \
         else VRC_MFMA1(VRC_S, NT, VRC_U);                        \
     } while (0)
             switch (nt) {
