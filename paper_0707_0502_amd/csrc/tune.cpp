@@ -25,6 +25,7 @@ struct Pending {
     std::string key;
     int cand;
     double work;
+    int dev;
     hipEvent_t a, b;
 };
 
@@ -36,7 +37,7 @@ struct State {
     std::map<std::string, Entry> table;
     std::map<std::string, std::pair<int, double>> stored;   // from the cache file
     std::vector<Pending> pend;
-    std::vector<hipEvent_t> pool;
+    std::map<int, std::vector<hipEvent_t>> pool;   // idle events per device
     std::map<int, std::string> arch;               // architecture name per device
     long new_open = 0;                             // keys created undecided
     int capturing = 0;                             // stream captures in progress
@@ -92,10 +93,12 @@ void ensure_loaded(State& s) {
     }
 }
 
-hipEvent_t get_event(State& s) {
-    if (!s.pool.empty()) {
-        hipEvent_t e = s.pool.back();
-        s.pool.pop_back();
+// an idle event of device dev (the current device)
+hipEvent_t get_event(State& s, int dev) {
+    auto& v = s.pool[dev];
+    if (!v.empty()) {
+        hipEvent_t e = v.back();
+        v.pop_back();
         return e;
     }
     hipEvent_t e = nullptr;
@@ -151,8 +154,8 @@ void harvest(State& s) {
             for (int c = 0; c < e.ncand; ++c) done = done && (int)e.ms[c].size() >= TUNE_REPS;
             if (done) decide(s, p.key, e);
         }
-        s.pool.push_back(p.a);
-        s.pool.push_back(p.b);
+        s.pool[p.dev].push_back(p.a);
+        s.pool[p.dev].push_back(p.b);
     }
     s.pend.swap(keep);
 }
@@ -210,14 +213,17 @@ TuneScope::TuneScope(const char* kernel, const std::string& shape, int ncand, in
         if (e.issued[q] < TUNE_REPS) c = q;
     }
     if (c < 0) return;
+    a_ = get_event(s, dev);
+    if (!a_) return;                                       // error left for the caller's check
+    if (hipEventRecord(a_, st) != hipSuccess) {            // error left for the caller's check
+        s.pool[dev].push_back(a_);
+        a_ = nullptr;
+        return;
+    }
     choice_ = c;
+    dev_ = dev;
     e.next = (c + 1) % ncand;
     ++e.issued[c];
-    a_ = get_event(s);
-    if (a_ && hipEventRecord(a_, st) != hipSuccess) {   // error left for the caller's check
-        s.pool.push_back(a_);
-        a_ = nullptr;
-    }
 }
 
 TuneScope::~TuneScope() {
@@ -229,18 +235,18 @@ TuneScope::~TuneScope() {
         if (it != s.table.end() && it->second.best < 0) --it->second.issued[choice_];
     };
     if (s.capturing > 0) {   // a capture began meanwhile: drop this timing
-        s.pool.push_back(a_);
+        s.pool[dev_].push_back(a_);
         untime();
         return;
     }
-    hipEvent_t b = get_event(s);
+    hipEvent_t b = get_event(s, dev_);
     if (!b || hipEventRecord(b, st_) != hipSuccess) {   // error left for the caller's check
-        s.pool.push_back(a_);
-        if (b) s.pool.push_back(b);
+        s.pool[dev_].push_back(a_);
+        if (b) s.pool[dev_].push_back(b);
         untime();
         return;
     }
-    s.pend.push_back({key_, choice_, work_, a_, b});
+    s.pend.push_back({key_, choice_, work_, dev_, a_, b});
 }
 
 int tune_load(const char* path) {
@@ -272,8 +278,8 @@ void tune_reset() {
     std::lock_guard<std::mutex> g(s.mu);
     for (auto& p : s.pend) {
         (void)hipEventSynchronize(p.b);
-        s.pool.push_back(p.a);
-        s.pool.push_back(p.b);
+        s.pool[p.dev].push_back(p.a);
+        s.pool[p.dev].push_back(p.b);
     }
     s.pend.clear();
     s.table.clear();

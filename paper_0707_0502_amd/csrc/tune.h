@@ -40,6 +40,7 @@ class TuneScope {
     int choice_ = 0;
     hipStream_t st_ = nullptr;
     double work_ = 1.0;
+    int dev_ = 0;
     hipEvent_t a_ = nullptr;   // start event while this launch is timed
 };
 
