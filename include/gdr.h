@@ -207,6 +207,9 @@ typedef struct {
     double refine_floor; /* mixed precision: each refinement round of the cleanup solves the
                           residual system in FP32 to relative tolerance max(0.3 tol / res,
                           refine_floor). 0: 1e-5. Must be in [0, 0.5]. */
+    int persistent;    /* gdr_solve_many only: 1 runs the first right-hand sides of all its
+                          lattices as one batch with persistent work-list operator launches
+                          (see there); 0 solves the lattices one after another. 0 or 1. */
 } gdr_params;
 
 /* kernel classes of the profiler (gdr_params.profile bit i = class i) */
@@ -224,7 +227,8 @@ typedef struct {
 
 /* Fill defaults: m_dr 40, k 15, m_proj 40, tol 1e-8, tol_extra sqrt(tol),
  * max_cycles 1000, FP64, batch 1, related 0, max_refine 8, profile 0, m_clean 0,
- * proj_k 0, use_graph 0, galerkin 0, sstep 4, sstep_reorth 20, refine_floor 0. */
+ * proj_k 0, use_graph 0, galerkin 0, sstep 4, sstep_reorth 20, refine_floor 0,
+ * persistent 0. */
 void gdr_params_default(gdr_params* p);
 
 typedef struct {
@@ -277,6 +281,30 @@ int gdr_solve(gdr_op op, int ns, const gdr_c64* sigma, int nrhs, const gdr_c64* 
               gdr_c64* X, const gdr_params* p, gdr_stats* st);
 
 /* ------------------------------------------------------- deflation handle */
+
+/* Independent problems on several lattices (Sec. 1, eq. (1.1) for each
+ * operator): (A_l - sigma_i I) x_i^{l,j} = b^{l,j}, l < nops, with the same
+ * ns shifts, nrhs right-hand sides and parameters for every lattice, each
+ * solved as gdr_solve solves it. B[l] (device, nrhs x n_l canonical
+ * complex128, n_l = gdr_op_size(ops[l])) and X[l] (device, nrhs x ns x n_l)
+ * belong to ops[l]'s context; st is NULL or an array of nops records, one per
+ * lattice. params->persistent = 0: the lattices one after another, each on
+ * its own context. params->persistent = 1 (mixed precision with s-step blocks,
+ * at most 16 Wilson operators whose links are stored as two rows in one
+ * precision, lattices of any sizes with extents multiples of 4, all on one
+ * device): GMRES-DR-Sh on the first right-hand sides runs for all lattices as
+ * one batch, on the first operator's context: every operator application is
+ * one persistent work-list launch over the tiles of all lattices, every
+ * Gram-Schmidt sweep and combination one launch over the lattices, each
+ * lattice keeping its own Krylov space, restarts and stopping rule. The
+ * extra right-hand side, the later right-hand sides and the cleanup then run
+ * per lattice on the lattice's own context, concurrently in host threads for
+ * lattices on different contexts. Returns GDR_OK when every lattice's solve
+ * does, else the first other status; errors (reported on the first
+ * operator's context): ARG (requirements, arguments), OOM, HIP, BREAKDOWN. */
+int gdr_solve_many(int nops, const gdr_op* ops, int ns, const gdr_c64* sigma, int nrhs,
+                   const gdr_c64* const* B, gdr_c64* const* X, const gdr_params* params,
+                   gdr_stats* st);
 
 /* Number k of deflation vectors (V holds k+1 columns). */
 int gdr_defl_k(gdr_defl d);

@@ -4,6 +4,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <string>
+#include <thread>
 
 #include "engine.h"
 #include "tune.h"
@@ -75,6 +77,10 @@ bool check_params(gdr_ctx_s* c, const gdr_params* p, int ns, bool need_dr) {
     }
     if (p->precision != GDR_PREC_F64 && p->precision != GDR_PREC_MIXED) {
         c->err = "precision must be GDR_PREC_F64 or GDR_PREC_MIXED";
+        return false;
+    }
+    if (p->persistent != 0 && p->persistent != 1) {
+        c->err = "persistent must be 0 or 1";
         return false;
     }
     return true;
@@ -253,6 +259,7 @@ void gdr_params_default(gdr_params* p) {
     p->sstep = 4;
     p->sstep_reorth = 20;
     p->refine_floor = 0;
+    p->persistent = 0;
 }
 
 int gdr_wilson_create(gdr_ctx c, const int dims[4], const int bc[4], double kappa,
@@ -679,6 +686,172 @@ int gdr_solve(gdr_op op, int ns, const gdr_c64* sigma, int nrhs, const gdr_c64* 
     if (st) st->t_total = t.sec();
     return rc;
     API_CATCH(c)
+}
+
+int gdr_solve_many(int nops, const gdr_op* ops, int ns, const gdr_c64* sigma, int nrhs,
+                   const gdr_c64* const* B, gdr_c64* const* X, const gdr_params* p, gdr_stats* st) {
+    if (nops < 1 || !ops) return GDR_ERR_ARG;
+    for (int l = 0; l < nops; ++l)
+        if (!ops[l]) return GDR_ERR_ARG;
+    gdr_ctx_s* c0 = ops[0]->ctx;
+    if (!sigma || !B || !X || nrhs < 1 || !p)
+        return fail(c0, GDR_ERR_ARG, "null argument or nrhs < 1");
+    if (!check_params(c0, p, ns, true) || !finite_shifts(c0, sigma, ns)) return GDR_ERR_ARG;
+    for (int l = 0; l < nops; ++l)
+        if (!B[l] || !X[l] || !solve_ptrs_ok(ops[l]->ctx, B[l], X[l])) {
+            if (ops[l]->ctx != c0) c0->err = ops[l]->ctx->err;
+            return fail(c0, GDR_ERR_ARG, c0->err.empty() ? "null right-hand side or solution"
+                                                         : c0->err.c_str());
+        }
+    if (!p->persistent) {
+        // one lattice after another, each a gdr_solve on its own context
+        int rc_all = GDR_OK;
+        for (int l = 0; l < nops; ++l) {
+            const int rc = gdr_solve(ops[l], ns, sigma, nrhs, B[l], X[l], p, st ? st + l : nullptr);
+            if (rc < 0) return fail(c0, rc, gdr_last_error(ops[l]->ctx));
+            if (rc != GDR_OK && rc_all == GDR_OK) rc_all = rc;
+        }
+        return rc_all;
+    }
+    // ---- one persistent batch for the first right-hand sides
+    if (nops > DSLASH_MAXV) return fail(c0, GDR_ERR_ARG, "persistent: at most 16 lattices");
+    if (p->precision != GDR_PREC_MIXED || p->sstep < 2)
+        return fail(c0, GDR_ERR_ARG, "persistent: needs mixed precision and sstep >= 2");
+    for (int l = 0; l < nops; ++l) {
+        gdr_op_s* q = ops[l];
+        if (q->kind != 0 || q->g.ltv != 8 || (q->lst != LINK_R12 && q->lst != LINK_R12H))
+            return fail(c0, GDR_ERR_ARG, "persistent: every operator must be a Wilson operator "
+                                         "with links stored as two rows (special unitary, extents "
+                                         "multiples of 4)");
+        if (q->lst != ops[0]->lst)
+            return fail(c0, GDR_ERR_ARG, "persistent: all lattices need the same link precision");
+        if (q->ctx->device != c0->device)
+            return fail(c0, GDR_ERR_ARG, "persistent: all lattices on one device");
+        for (int l2 = 0; l2 < l; ++l2)
+            if (ops[l2] == q) return fail(c0, GDR_ERR_ARG, "persistent: an operator appears twice");
+    }
+    for (int l = 0; l < nops; ++l) stats_reset(st ? st + l : nullptr);
+    API_TRY(c0)
+    HIPCHK(hipSetDevice(c0->device));
+    Timer t;
+    gdr_op_s set;
+    set.kind = 2;
+    set.ctx = c0;
+    set.parts.assign(ops, ops + nops);
+    set.n = 0;
+    for (int l = 0; l < nops; ++l) set.n = std::max(set.n, ops[l]->n);
+    {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c0->device) ==
+                hipSuccess && cus > 0)
+            set.list_blocks = 3 * cus;   // the work-list kernel keeps 3 blocks per CU resident
+        else
+            (void)hipGetLastError();
+    }
+    const int64_t n = set.n;
+    DMem mem;
+    double2* b1 = mem.get<double2>((size_t)nops * n);
+    double2* x1 = mem.get<double2>((size_t)nops * ns * n);
+    // every lattice's first right-hand side, zero beyond its own length
+    HIPCHK(hipMemsetAsync(b1, 0, (size_t)nops * n * sizeof(double2), c0->st));
+    for (int l = 0; l < nops; ++l) {
+        // operators on other contexts: their streams finished their own work
+        if (ops[l]->ctx != c0) HIPCHK(hipStreamSynchronize(ops[l]->ctx->st));
+        op_pack<double>(ops[l], (const double2*)B[l], b1 + (int64_t)l * n, n, 1, c0->st);
+    }
+    Stats S(nullptr, (unsigned)p->profile, c0->st, &c0->evpool);
+    ManyOut R;
+    struct Own {
+        ManyOut& r;
+        ~Own() {
+            for (gdr_defl_s* d : r.defl) delete d;
+        }
+    } own{R};
+    Timer tdr;
+    int rc = solve_dr_many(&set, ns, (const double2*)sigma, b1, x1, *p, S, R);
+    S.flush();
+    HIPCHK(hipStreamSynchronize(c0->st));
+    const double t_dr = tdr.sec();
+    // ---- per lattice: later right-hand sides, cleanup, final residuals; the
+    // lattices of one context in turn, different contexts concurrently
+    std::vector<int> rcs(nops, GDR_OK);
+    std::vector<std::string> errs(nops);
+    std::vector<gdr_ctx_s*> ctxs;
+    for (int l = 0; l < nops; ++l)
+        if (std::find(ctxs.begin(), ctxs.end(), ops[l]->ctx) == ctxs.end()) ctxs.push_back(ops[l]->ctx);
+    auto finish = [&](int l) {
+        gdr_op_s* op = ops[l];
+        gdr_ctx_s* c = op->ctx;
+        gdr_stats* sl = st ? st + l : nullptr;
+        try {
+            PoolScope ps(c);
+            HIPCHK(hipSetDevice(c->device));
+            const int64_t nl = op->n;
+            DMem lm;
+            double2* Beo = lm.get<double2>((size_t)nrhs * nl);
+            double2* Xeo = lm.get<double2>((size_t)nrhs * ns * nl);
+            op_pack<double>(op, (const double2*)B[l], Beo, nl, nrhs, c->st);
+            if (nrhs > 1) check_rhs(op, Beo + nl, nrhs - 1);
+            // the first right-hand side's solutions from the batch
+            HIPCHK(hipMemcpy2DAsync(Xeo, nl * sizeof(double2), x1 + (int64_t)l * ns * n,
+                                    n * sizeof(double2), nl * sizeof(double2), ns,
+                                    hipMemcpyDeviceToDevice, c->st));
+            Stats Sl(sl, (unsigned)p->profile, c->st, &c->evpool);
+            if (sl) {
+                sl->cycles_dr = R.cycles[l];
+                sl->mvp_dr = R.mvps[l];
+                sl->mvp_fp64 = R.cycles[l];
+                sl->t_phase[0] = t_dr;
+            }
+            int r = R.conv[l] ? GDR_OK : GDR_NOT_CONVERGED;
+            gdr_defl_s* d = R.defl[l];
+            if (nrhs > 1) {
+                if (!d) throw GdrError(GDR_ERR_BREAKDOWN, "first solve ended in a lucky breakdown: no deflation space");
+                const int r2 = solve_proj_batch(op, d, ns, (const double2*)sigma, nrhs - 1, Beo + nl,
+                                                Xeo + (int64_t)ns * nl, 1, *p, Sl);
+                if (r2 != GDR_OK) r = r2;
+            }
+            Timer tc;
+            r = cleanup(op, d, ns, (const double2*)sigma, nrhs, Beo, Xeo, *p, Sl);
+            if (sl) sl->t_phase[4] += tc.sec();
+            Sl.flush();
+            r = final_status(r, finish_stats(op, sl, ns, (const double2*)sigma, nrhs, Beo, Xeo, t,
+                                             p->precision),
+                             p->tol);
+            op_unpack<double>(op, Xeo, nl, (double2*)X[l], nrhs * ns, c->st);
+            HIPCHK(hipStreamSynchronize(c->st));
+            if (sl) sl->t_total = t.sec();
+            rcs[l] = r;
+        } catch (const GdrError& e) {
+            rcs[l] = e.code;
+            errs[l] = e.what();
+        } catch (const std::bad_alloc&) {
+            rcs[l] = GDR_ERR_OOM;
+            errs[l] = "device allocation failed";
+        } catch (const std::exception& e) {
+            rcs[l] = GDR_ERR_HIP;
+            errs[l] = e.what();
+        }
+    };
+    {
+        std::vector<std::thread> th;
+        for (gdr_ctx_s* c : ctxs)
+            th.emplace_back([&, c] {
+                for (int l = 0; l < nops; ++l)
+                    if (ops[l]->ctx == c) finish(l);
+            });
+        for (auto& x : th) x.join();
+    }
+    // the batch's own status only says which lattices the first phase left to
+    // the cleanup (mixed precision); each lattice's final status decides
+    (void)rc;
+    int rc_all = GDR_OK;
+    for (int l = 0; l < nops; ++l) {
+        if (rcs[l] < 0) return fail(c0, rcs[l], errs[l].c_str());
+        if (rcs[l] != GDR_OK && rc_all == GDR_OK) rc_all = rcs[l];
+    }
+    return rc_all;
+    API_CATCH(c0)
 }
 
 int gdr_defl_k(gdr_defl d) { return d ? d->k : -1; }

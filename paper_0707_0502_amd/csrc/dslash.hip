@@ -772,28 +772,19 @@ __device__ __forceinline__ void finish_r12(const Z<float> (&acc)[4][3], const fl
         }
 }
 
-// One block per (tile, vector): the halo kernel's staging with two-row links
-// (LT = float2: LINK_R12, __half2: LINK_R12H).
+// One tile of one vector with two-row links (LT = float2: LINK_R12, __half2:
+// LINK_R12H): stage the tile and its spin-projected halo, apply the eight
+// hops, write alpha ((1 - sigma) in - kappa D in) [+ add]. in, out and add
+// point at the vector's start; sp and hl are the block's LDS staging areas.
 template <typename LT>
-__global__ __launch_bounds__(256, 3) void k_dslash_r12(const float2* __restrict__ in, int64_t in_stride,
-                                                      float2* __restrict__ out, int64_t out_stride,
-                                                      const float2* __restrict__ add, int64_t add_stride,
-                                                      const LT* __restrict__ links, Geom g, float kappa,
-                                                      DiagList dl, const int* __restrict__ act, int nvec,
-                                                      int anti, int order) {
-    __shared__ float2 sp[12 * 256];
-    __shared__ float2 hl[8 * 6 * 64];
-    const int nb = gridDim.x;
-    const int b = blockIdx.x;
-    const int lbv = (nb % 8 == 0) ? ((b % 8) * (nb / 8) + b / 8) : b;
-    const int v = lbv % nvec;
-    if (act && !act[v]) return;   // inactive member: uniform over the block, nothing loaded
-    const TileGeo tg(g, tile_of(g, lbv / nvec, order));
+__device__ __forceinline__ void r12_tile(const float2* __restrict__ in, float2* __restrict__ out,
+                                         const float2* __restrict__ add, const LT* __restrict__ links,
+                                         const TileGeo& tg, int64_t V, float kappa, double2 d,
+                                         double alpha, int anti, float2* sp, float2* hl) {
     const int local = threadIdx.x;
     const int site0 = (tg.T << 8) | local;
-    const int64_t V = g.vol;
     const int hsrc[2] = {halo_source(tg, local), halo_source(tg, local + 256)};
-    stage_r12<false>(in + v * in_stride, V, site0, local, hsrc, sp, hl);
+    stage_r12<false>(in, V, site0, local, hsrc, sp, hl);
     __syncthreads();
     Z<float> acc[4][3];
 #pragma unroll
@@ -833,9 +824,54 @@ __global__ __launch_bounds__(256, 3) void k_dslash_r12(const float2* __restrict_
     hop(I2{}, I1{});
     hop(I3{}, I0{});
     hop(I3{}, I1{});
-    finish_r12(acc, sp, local, out + v * out_stride + site0,
-               add ? add + v * add_stride + site0 : nullptr, V, (float)dl.d[v].x, (float)dl.d[v].y,
-               (float)dl.alpha[v], kappa);
+    finish_r12(acc, sp, local, out + site0, add ? add + site0 : nullptr, V, (float)d.x, (float)d.y,
+               (float)alpha, kappa);
+}
+
+// One block per (tile, vector) with two-row links.
+template <typename LT>
+__global__ __launch_bounds__(256, 3) void k_dslash_r12(const float2* __restrict__ in, int64_t in_stride,
+                                                      float2* __restrict__ out, int64_t out_stride,
+                                                      const float2* __restrict__ add, int64_t add_stride,
+                                                      const LT* __restrict__ links, Geom g, float kappa,
+                                                      DiagList dl, const int* __restrict__ act, int nvec,
+                                                      int anti, int order) {
+    __shared__ float2 sp[12 * 256];
+    __shared__ float2 hl[8 * 6 * 64];
+    const int nb = gridDim.x;
+    const int b = blockIdx.x;
+    const int lbv = (nb % 8 == 0) ? ((b % 8) * (nb / 8) + b / 8) : b;
+    const int v = lbv % nvec;
+    if (act && !act[v]) return;   // inactive member: uniform over the block, nothing loaded
+    const TileGeo tg(g, tile_of(g, lbv / nvec, order));
+    r12_tile<LT>(in + v * in_stride, out + v * out_stride, add ? add + v * add_stride : nullptr,
+                 links, tg, g.vol, kappa, dl.d[v], dl.alpha[v], anti, sp, hl);
+}
+
+// Persistent work list over the vectors of several lattices (member v on
+// lattice L.g[v], its vector at in + v * in_stride): items are the (member,
+// tile) pairs in member order, and a grid of at most the resident blocks
+// takes them in turn (item = block, block + grid, ...), so one launch serves
+// every lattice however uneven their sizes. Inactive members cost one flag
+// read per item.
+template <typename LT>
+__global__ __launch_bounds__(256, 3) void k_dslash_r12_list(const float2* __restrict__ in,
+                                                           int64_t in_stride, float2* __restrict__ out,
+                                                           int64_t out_stride, LatList L, DiagList dl,
+                                                           const int* __restrict__ act) {
+    __shared__ float2 sp[12 * 256];
+    __shared__ float2 hl[8 * 6 * 64];
+    const int total = L.tile0[L.nm];
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        int v = 0;
+        while (v + 1 < L.nm && item >= L.tile0[v + 1]) ++v;
+        if (act && !act[v]) continue;   // uniform over the block
+        const Geom& g = L.g[v];
+        const TileGeo tg(g, item - L.tile0[v]);
+        r12_tile<LT>(in + v * in_stride, out + v * out_stride, nullptr, (const LT*)L.links[v], tg,
+                     g.vol, L.kappa[v], dl.d[v], dl.alpha[v], L.anti[v], sp, hl);
+        __syncthreads();   // the staging areas are reused by the next item
+    }
 }
 
 // Several vectors per launch: one block per tile loops over the vectors. The
@@ -1012,6 +1048,25 @@ void dslash(const typename CT<TS>::t* in, int64_t in_stride, typename CT<TS>::t*
                                g, (float)kappa, dl, act, nvec);
         }
     }
+}
+
+void dslash_list(const float2* in, int64_t in_stride, float2* out, int64_t out_stride,
+                 const LatList& L, int link_storage, const DiagList& dl, hipStream_t st,
+                 const int* act, int max_blocks) {
+    if (L.nm < 1 || L.nm > DSLASH_MAXV) throw std::invalid_argument("dslash_list: 1..16 members");
+    for (int v = 0; v < L.nm; ++v)
+        if (L.g[v].ltv != 8 || L.tile0[v + 1] - L.tile0[v] != (L.g[v].vol >> 8))
+            throw std::invalid_argument("dslash_list: members need 4^4 tiles and matching tile counts");
+    const int total = L.tile0[L.nm];
+    const int grid = total < max_blocks ? total : max_blocks;
+    if (link_storage == LINK_R12H)
+        hipLaunchKernelGGL(k_dslash_r12_list<__half2>, dim3(grid), dim3(256), 0, st, in, in_stride,
+                           out, out_stride, L, dl, act);
+    else if (link_storage == LINK_R12)
+        hipLaunchKernelGGL(k_dslash_r12_list<float2>, dim3(grid), dim3(256), 0, st, in, in_stride,
+                           out, out_stride, L, dl, act);
+    else
+        throw std::invalid_argument("dslash_list: two-row links only");
 }
 
 template void dslash<double>(const double2*, int64_t, double2*, int64_t, const double2*, int64_t,

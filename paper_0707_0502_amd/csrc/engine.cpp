@@ -43,6 +43,11 @@ static int lst_for(gdr_op_s* op) {
 template <typename T>
 static double dslash_bytes(gdr_op_s* op, int nvec, bool add) {
     double cs = std::is_same<T, double>::value ? 16 : 8;
+    if (op->kind == 2) {   // a set of lattices: the mean member's bytes per vector
+        double b = 0;
+        for (gdr_op_s* q : op->parts) b += dslash_bytes<T>(q, 1, add);
+        return op->parts.empty() ? 0 : b * nvec / op->parts.size();
+    }
     if (op->kind == 1)   // bidiagonal: 2n matrix entries, in, out (, add) per vector
         return (double)op->n * cs * (2 + nvec * (2 + (add ? 1 : 0)));
     const double vol = op->g.vol;
@@ -55,6 +60,11 @@ static double dslash_bytes(gdr_op_s* op, int nvec, bool add) {
     return vol * (link + nvec * (12 * cs * 2 + (add ? 12 * cs : 0)));
 }
 static double dslash_flops(gdr_op_s* op, int nvec) {
+    if (op->kind == 2) {
+        double f = 0;
+        for (gdr_op_s* q : op->parts) f += dslash_flops(q, 1);
+        return op->parts.empty() ? 0 : f * nvec / op->parts.size();
+    }
     if (op->kind == 1) return (double)op->n * nvec * 16.0;
     return (double)op->g.vol * nvec * 1368.0;
 }
@@ -62,7 +72,43 @@ static double dslash_flops(gdr_op_s* op, int nvec) {
 template <typename T>
 void op_apply(gdr_op_s* op, const typename CT<T>::t* in, int64_t in_stride,
               typename CT<T>::t* out, int64_t out_stride, const typename CT<T>::t* add,
-              int64_t add_stride, const DiagList& dl, int nvec, hipStream_t st, const int* act) {
+              int64_t add_stride, const DiagList& dl, int nvec, hipStream_t st, const int* act,
+              int mem0) {
+    if (op->kind == 2) {
+        if (nvec < 1) return;
+        if (mem0 < 0 || mem0 + nvec > (int)op->parts.size())
+            throw std::invalid_argument("lattice set: members out of range");
+        if constexpr (std::is_same<T, float>::value) {
+            // every member's operator in one persistent work-list launch
+            if (add) throw std::invalid_argument("lattice set: FP32 launches add no vector");
+            LatList L{};
+            L.nm = nvec;
+            int ls = -1;
+            for (int v = 0; v < nvec; ++v) {
+                gdr_op_s* q = op->parts[mem0 + v];
+                L.g[v] = q->g;
+                L.links[v] = links_for<T>(q);
+                L.kappa[v] = (float)q->kappa;
+                L.anti[v] = q->anti;
+                L.tile0[v + 1] = L.tile0[v] + (int)(q->g.vol >> 8);
+                const int lq = lst_for<T>(q);
+                if (ls >= 0 && lq != ls) throw std::invalid_argument("lattice set: mixed link storage");
+                ls = lq;
+            }
+            dslash_list(in, in_stride, out, out_stride, L, ls, dl, st, act, op->list_blocks);
+        } else {
+            // FP64: each member on its own lattice (once per restart cycle)
+            for (int v = 0; v < nvec; ++v) {
+                DiagList d1{};
+                d1.d[0] = dl.d[v];
+                d1.alpha[0] = dl.alpha[v];
+                op_apply<T>(op->parts[mem0 + v], in + v * in_stride, in_stride, out + v * out_stride,
+                            out_stride, add ? add + v * add_stride : nullptr, add_stride, d1, 1, st,
+                            act ? act + v : nullptr);
+            }
+        }
+        return;
+    }
     if (op->kind == 1) {
         const typename CT<T>::t* de;
         if constexpr (std::is_same<T, double>::value) de = op->bd64;
@@ -88,9 +134,9 @@ void op_unpack(gdr_op_s* op, const typename CT<T>::t* src, int64_t stride, doubl
 }
 template void op_apply<double>(gdr_op_s*, const double2*, int64_t, double2*, int64_t,
                                const double2*, int64_t, const DiagList&, int, hipStream_t,
-                               const int*);
+                               const int*, int);
 template void op_apply<float>(gdr_op_s*, const float2*, int64_t, float2*, int64_t, const float2*,
-                              int64_t, const DiagList&, int, hipStream_t, const int*);
+                              int64_t, const DiagList&, int, hipStream_t, const int*, int);
 template void op_pack<double>(gdr_op_s*, const double2*, double2*, int64_t, int, hipStream_t);
 template void op_pack<float>(gdr_op_s*, const double2*, float2*, int64_t, int, hipStream_t);
 template void op_unpack<double>(gdr_op_s*, const double2*, int64_t, double2*, int, hipStream_t);
@@ -194,10 +240,28 @@ struct Arnoldi {
             dl.d[v] = z(1);
             dl.alpha[v] = 1;
             // (A - c) / r: the operator's diagonal factor 1 - c, scale 1 / r
-            dlp.d[v] = z(1.0 - op->spec_c.x, -op->spec_c.y);
-            dlp.alpha[v] = 1.0 / op->spec_r;
+            // (a set of lattices: each member's own disc)
+            const gdr_op_s* q = op->kind == 2 && v < (int)op->parts.size() ? op->parts[v] : op;
+            dlp.d[v] = z(1.0 - q->spec_c.x, -q->spec_c.y);
+            dlp.alpha[v] = 1.0 / q->spec_r;
+        }
+        if (op->kind == 2) {
+            if (nmem != (int)op->parts.size() || nmem > DSLASH_MAXV)
+                throw std::invalid_argument("lattice set: one batch member per lattice, at most 16");
+            std::vector<double2> th(nmem);
+            std::vector<double> rh(nmem);
+            for (int b = 0; b < nmem; ++b) {
+                th[b] = op->parts[b]->spec_c;
+                rh[b] = op->parts[b]->spec_r;
+            }
+            thetas = mem.get<double2>(nmem);
+            rhos = mem.get<double>(nmem);
+            HIPCHK(hipMemcpyAsync(thetas, th.data(), nmem * sizeof(double2), hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(rhos, rh.data(), nmem * sizeof(double), hipMemcpyHostToDevice, st));
         }
     }
+    double2* thetas = nullptr;   // lattice sets: per-member disc of the s-step powers
+    double* rhos = nullptr;
 
     // Block size of the cycle: s-step blocks only for the FP32 basis
     void set_block(int s, double reorth_ = 20) {
@@ -228,7 +292,7 @@ struct Arnoldi {
                     const int nb = std::min(DSLASH_MAXV, nmem - b0);
                     prof->begin(GDR_K_DSLASH);
                     op_apply<T>(op, src + b0 * vms, vms, dst + b0 * vms, vms, nullptr, 0, dlp, nb, st,
-                                act ? act + b0 : nullptr);
+                                act ? act + b0 : nullptr, b0);
                     const int na = std::min(nb, nact - std::min(nact, b0));
                     prof->end(GDR_K_DSLASH, dslash_bytes<T>(op, na, false), dslash_flops(op, na));
                 }
@@ -250,6 +314,8 @@ struct Arnoldi {
             sa.h_ms = hms;
             sa.theta = op->spec_c;
             sa.rho = op->spec_r;
+            sa.thetas = thetas;
+            sa.rhos = rhos;
             sa.brk = brk;
             sa.reorth = reorth;
             fill_int(reo, 0, nmem, st);
@@ -292,7 +358,7 @@ struct Arnoldi {
             const int nb = std::min(DSLASH_MAXV, nmem - b0);
             prof->begin(GDR_K_DSLASH);
             op_apply<T>(op, col + b0 * vms, vms, w + b0 * n, n, nullptr, 0, dl, nb, st,
-                        act ? act + b0 : nullptr);
+                        act ? act + b0 : nullptr, b0);
             const int na = std::min(nb, nact - std::min(nact, b0));
             prof->end(GDR_K_DSLASH, dslash_bytes<T>(op, na, false), dslash_flops(op, na));
         }
@@ -631,6 +697,280 @@ int solve_dr_sh(gdr_op_s* op, int ns, const double2* sig, const double2* b_eo, d
     if (p.precision == GDR_PREC_MIXED)
         return dr_run<float>(op, ns, sig, b_eo, X_eo, p, S, defl_out, converged);
     return dr_run<double>(op, ns, sig, b_eo, X_eo, p, S, defl_out, converged);
+}
+
+// ---------------------------------------------------------------------------
+// GMRES-DR(m,k)-Sh on the first right-hand side of every lattice of a set
+// (op->kind == 2), the lattices as the members of one batch: each member
+// follows exactly the single-lattice algorithm of dr_run (its own Krylov
+// space, harmonic Ritz restart, FP64 residual replacement and stopping
+// rules); the operator of all members is one persistent work-list launch and
+// every sweep is one launch over the members. Member b's right-hand side is
+// b_eo + b*n and its ns solutions X + b*ns*n (n = the largest lattice's,
+// zero beyond the member's own). The deflation pair of member b comes back in
+// defl_out[b] for its own lattice (null after a lucky breakdown).
+int solve_dr_many(gdr_op_s* op, int ns, const double2* sig_h, const double2* b_eo, double2* X,
+                  const gdr_params& p, Stats& S, ManyOut& R) {
+    using T = float;
+    using C = typename CT<T>::t;
+    hipStream_t st = op->ctx->st;
+    const int64_t n = op->n;
+    const int L = (int)op->parts.size();
+    const int m = p.m_dr, k = p.k;
+    DMem mem;
+    const int64_t vms = (int64_t)(m + 1 + BASIS_PAD) * n;
+    C* Va = alloc_basis<T>(mem, (m + 1 + BASIS_PAD) * L - BASIS_PAD, n, st);
+    C* Vb = alloc_basis<T>(mem, (m + 1 + BASIS_PAD) * L - BASIS_PAD, n, st);
+    Arnoldi<T> A;
+    A.init(mem, op, m, L, Va, vms);
+    A.use_graph = p.use_graph != 0;
+    A.set_block(p.sstep, p.sstep_reorth);
+    A.prof = &S.prof;
+    const int64_t hms = A.hms;
+    const int64_t pms = (int64_t)(m + 1) * (k + 1);
+    const int64_t cms = (int64_t)(m + 1) * (ns + 1);
+    double2* Hn = mem.get<double2>((size_t)hms * L);
+    double2* c0 = mem.get<double2>((size_t)(m + 1) * L);
+    double2* c1 = mem.get<double2>((size_t)(m + 1) * L);
+    double2* coef = mem.get<double2>((size_t)cms * L);
+    double2* P = mem.get<double2>((size_t)pms * L);
+    CycleOut* outs = mem.get<CycleOut>((size_t)2 * L);
+    double2* sig = mem.get<double2>(ns);
+    double2* tG = mem.get<double2>((size_t)Arnoldi<T>::GMS * L);
+    double2* tcoef = mem.get<double2>((size_t)GS_COEF_MS * L);
+    double* tref = mem.get<double>(L);
+    int* tbrk = mem.get<int>(L);
+    double2* tH = mem.get<double2>((size_t)(k + 2) * L);
+    double* dsc = mem.get<double>(L);
+    int* act = mem.get<int>(L);
+    double2* rtrue = mem.get<double2>((size_t)n * L);
+    const int64_t bms = (int64_t)(sizeof(CycleOut) / sizeof(double2));
+    HIPCHK(hipMemcpyAsync(sig, sig_h, ns * sizeof(double2), hipMemcpyHostToDevice, st));
+    // rows beyond a member's own lattice are never written: zero once
+    HIPCHK(hipMemsetAsync(rtrue, 0, (size_t)n * L * sizeof(double2), st));
+
+    R.conv.assign(L, 0);
+    R.cycles.assign(L, 0);
+    R.mvps.assign(L, 0);
+    R.defl.assign(L, nullptr);
+    const std::vector<double> bnorm = norms_of(op, b_eo, L);
+    for (int b = 0; b < L; ++b)
+        if (!std::isfinite(bnorm[b])) throw GdrError(GDR_ERR_ARG, "right-hand side is not finite");
+    HIPCHK(hipMemsetAsync(X, 0, (size_t)L * ns * n * sizeof(double2), st));
+    std::vector<int> acth(L, 1);
+    std::vector<CycleOut> init(L);
+    std::vector<double2> ch((size_t)(m + 1) * L, z(0));
+    std::vector<double> invb(L, 0);
+    for (int b = 0; b < L; ++b) {
+        init[b] = CycleOut{};
+        init[b].snorm = bnorm[b];
+        for (int i = 0; i < MAXNS; ++i) init[b].beta[i] = z(1);
+        if (bnorm[b] > 0) {
+            ch[(size_t)b * (m + 1)] = z(bnorm[b]);
+            invb[b] = 1.0 / bnorm[b];
+        } else {
+            acth[b] = 0;   // b = 0: x = 0 is exact, no deflation space
+            R.conv[b] = 1;
+        }
+    }
+    HIPCHK(hipMemcpyAsync(outs, init.data(), L * sizeof(CycleOut), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(c0, ch.data(), ch.size() * sizeof(double2), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(dsc, invb.data(), L * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemsetAsync(Hn, 0, (size_t)hms * L * sizeof(double2), st));
+    HIPCHK(hipMemsetAsync(A.H, 0, (size_t)hms * L * sizeof(double2), st));
+    HIPCHK(hipMemcpyAsync(act, acth.data(), L * sizeof(int), hipMemcpyHostToDevice, st));
+    convert_scale<T>(b_eo, n, dsc, 1, Va, vms, n, L, st, act);
+
+    int cur = 1, prv = 0;
+    C* Vc = Va;
+    C* Vn = Vb;
+    double2* Hc = A.H;
+    double2* Hx = Hn;
+    double2* cc = c0;
+    double2* cx = c1;
+    int j0 = 0;
+    std::vector<double> best_true(L, std::numeric_limits<double>::infinity());
+    std::vector<int> stall(L, 0), brkh(L, -1);
+    std::vector<CycleOut> oh(L);
+    const unsigned allx = ns >= 32 ? 0xffffffffu : ((1u << ns) - 1u);
+    gdr_ctx_s* cx_ = op->ctx;
+    for (int cyc = 0; cyc < p.max_cycles; ++cyc) {
+        int nact = 0;
+        for (int b = 0; b < L; ++b) nact += acth[b];
+        if (nact == 0) break;
+        A.V = Vc;
+        A.H = Hc;
+        A.cycle(j0, act, nact);
+        HIPCHK(hipMemcpyAsync(outs + cur * L, init.data(), L * sizeof(CycleOut), hipMemcpyHostToDevice, st));
+        CycleArgs a{};
+        a.H = Hc;
+        a.h_ms = hms;
+        a.c = cc;
+        a.c_ms = m + 1;
+        a.sigma = sig;
+        a.sig_ms = 0;
+        a.beta = outs[prv * L].beta;
+        a.beta_ms = bms;
+        a.brk = A.brk;
+        a.coef = coef;
+        a.coef_ms = cms;
+        a.out = outs + cur * L;
+        a.restart = 0;
+        a.k = k;
+        a.P = P;
+        a.p_ms = pms;
+        a.Hnew = Hx;
+        a.hnew_ms = hms;
+        a.cnew = cx;
+        a.cnew_ms = m + 1;
+        a.m = m;
+        a.ns = ns;
+        a.act = act;
+        a.galerkin = p.galerkin;
+        S.prof.begin(GDR_K_SMALL);
+        cycle_small(a, L, st);
+        S.prof.end(GDR_K_SMALL, 0, 0);
+        // the restart half on the auxiliary stream, overlapping the solution
+        // update and the FP64 residuals (nothing below reads its outputs
+        // before the join)
+        HIPCHK(hipEventRecord(cx_->ev_fork, st));
+        HIPCHK(hipStreamWaitEvent(cx_->aux, cx_->ev_fork, 0));
+        {
+            CycleArgs ar = a;
+            ar.restart = 2;
+            hipEvent_t pm = S.prof.mark(GDR_K_SMALL, cx_->aux);
+            cycle_small(ar, L, cx_->aux);
+            S.prof.span(GDR_K_SMALL, pm, cx_->aux, 0, 0);
+        }
+        HIPCHK(hipEventRecord(cx_->ev_join, cx_->aux));
+        const double dn = (double)n * nact;
+        S.prof.begin(GDR_K_COMBINE);
+        vcombine<T>(Vc, n, vms, m, coef, m + 1, cms, ns, X, n, (int64_t)ns * n, allx, n, L, st, act);
+        S.prof.end(GDR_K_COMBINE, dn * (m * sizeof(C) + 32.0 * ns), dn * m * ns * 8);
+        {
+            // FP64 true residuals of shift 1, each member on its own lattice
+            DiagList dl{};
+            for (int b = 0; b < L; ++b) {
+                dl.d[b] = z(1.0 - sig_h[0].x, -sig_h[0].y);
+                dl.alpha[b] = -1;
+            }
+            S.prof.begin(GDR_K_OTHER);
+            op_apply<double>(op, X, (int64_t)ns * n, rtrue, n, b_eo, n, dl, L, st, act, 0);
+            S.prof.end(GDR_K_OTHER, dslash_bytes<double>(op, nact, true), dslash_flops(op, nact));
+            if (S.st) S.st->mvp_fp64 += nact;
+        }
+        HIPCHK(hipStreamWaitEvent(st, cx_->ev_join, 0));
+        HIPCHK(hipMemcpyAsync(oh.data(), outs + cur * L, L * sizeof(CycleOut), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(brkh.data(), A.brk, L * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        const std::vector<double> rtn = norms_of(op, rtrue, L);
+        // per member: convergence, stall of the FP32 recursion, lucky breakdown
+        std::vector<int> stop(L, 0), recomb(L, 0);
+        double w1 = 0, wm = 0;
+        int64_t mv = 0;
+        for (int b = 0; b < L; ++b) {
+            if (!acth[b]) continue;
+            R.cycles[b] += 1;
+            R.mvps[b] += m - j0;
+            mv = std::max(mv, R.mvps[b]);
+            if (oh[b].flags & 1)
+                throw GdrError(GDR_ERR_BREAKDOWN, "GMRES-DR-Sh: singular shifted system ((Q^H s)_{m+1} = 0)");
+            if (oh[b].flags & 2)
+                throw GdrError(GDR_ERR_BREAKDOWN, "GMRES-DR-Sh: harmonic Ritz eigensolver did not converge");
+            const double r1 = rtn[b] / bnorm[b];
+            double bmax = 1;
+            for (int i = 1; i < ns; ++i) bmax = std::max(bmax, zabs(oh[b].beta[i]));
+            const double rmax = r1 * bmax;
+            if (!std::isfinite(rmax)) throw GdrError(GDR_ERR_BREAKDOWN, "GMRES-DR-Sh: non-finite residual norm");
+            w1 = std::max(w1, oh[b].snorm / bnorm[b]);
+            wm = std::max(wm, rmax);
+            const bool conv = rmax <= p.tol || brkh[b] >= 0;
+            bool st_ = conv;
+            if (!conv) {
+                const double gap = std::fabs(rtn[b] - oh[b].snorm) / rtn[b];
+                if (rtn[b] < 0.9 * best_true[b]) {
+                    best_true[b] = rtn[b];
+                    stall[b] = 0;
+                } else {
+                    ++stall[b];
+                }
+                if (gap > 0.5 || stall[b] >= 3) st_ = true;
+            }
+            R.conv[b] = conv ? 1 : 0;
+            stop[b] = st_ || cyc + 1 >= p.max_cycles;
+            recomb[b] = brkh[b] < 0;   // a lucky breakdown leaves no deflation space
+        }
+        S.hist(0, cyc + 1, mv, w1, wm);
+        // restart of every member still active: V_{k+1} = V_{m+1} P, the last
+        // column re-orthogonalised, the FP64 residual's coordinates in V_{k+1}
+        S.prof.begin(GDR_K_RECOMBINE);
+        for (int b = 0; b < L; ++b)
+            if (acth[b] && recomb[b])
+                vrecombine<T>(Vc + b * vms, n, m + 1, P + b * pms, m + 1, k + 1, Vn + b * vms, n, n, st);
+        S.prof.end(GDR_K_RECOMBINE, dn * (m + k + 2) * sizeof(C), dn * (m + 1) * (k + 1) * 8);
+        C* col = Vn + (int64_t)k * n;
+        for (int pass = 0; pass < 2; ++pass) {
+            fill_int(tbrk, -1, L, st);
+            gs_dot<T, T>(Vn, n, vms, k + 1, col, vms, (const C*)nullptr, 0, A.partial, A.nblk, n, L, st,
+                         act);
+            reduce_cols(A.partial, A.nblk, k + 2, tG, Arnoldi<T>::GMS, nullptr, 0, L, st, act);
+            dcgs_coef(tG, Arnoldi<T>::GMS, k, 1, 1, nullptr, 0, 0, tcoef, GS_COEF_MS, tref, tbrk, 0.0, L,
+                      st, act);
+            gs_update<T>(Vn, n, vms, k, col, vms, (const C*)nullptr, 0, col, vms, (C*)nullptr, 0, tcoef,
+                         GS_COEF_MS, n, L, st, act);
+        }
+        gs_dot<T, double>(Vn, n, vms, k + 1, rtrue, n, nullptr, 0, A.partial, A.nblk, n, L, st, act);
+        reduce_cols(A.partial, A.nblk, k + 2, tH, k + 2, nullptr, 0, L, st, act);
+        HIPCHK(hipMemcpy2DAsync(cx, (m + 1) * sizeof(double2), tH, (k + 2) * sizeof(double2),
+                                (k + 1) * sizeof(double2), L, hipMemcpyDeviceToDevice, st));
+        // members that stop: their deflation pair, then they leave the batch
+        bool changed = false;
+        for (int b = 0; b < L; ++b) {
+            if (!acth[b] || !stop[b]) continue;
+            changed = true;
+            acth[b] = 0;
+            if (!recomb[b]) continue;
+            gdr_op_s* q = op->parts[b];
+            const int64_t nq = q->n;
+            gdr_defl_s* d = new gdr_defl_s;
+            d->op = q;
+            d->k = k;
+            d->prec = GDR_PREC_MIXED;
+            R.defl[b] = d;
+            HIPCHK(hipMalloc(&d->V, (size_t)(k + 1 + BASIS_PAD) * nq * sizeof(C)));
+            HIPCHK(hipMemsetAsync(d->V, 0, (size_t)(k + 1 + BASIS_PAD) * nq * sizeof(C), st));
+            HIPCHK(hipMemcpy2DAsync(d->V, nq * sizeof(C), Vn + b * vms, n * sizeof(C), nq * sizeof(C),
+                                    k + 1, hipMemcpyDeviceToDevice, st));
+            if (k > 0) {
+                HIPCHK(hipMalloc(&d->Hk, (size_t)(k + 1) * k * sizeof(double2)));
+                HIPCHK(hipMemcpy2DAsync(d->Hk, (k + 1) * sizeof(double2), Hx + b * hms,
+                                        (m + 1) * sizeof(double2), (k + 1) * sizeof(double2), k,
+                                        hipMemcpyDeviceToDevice, st));
+                d->Hk_host.resize((size_t)(k + 1) * k);
+                HIPCHK(hipMemcpyAsync(d->Hk_host.data(), d->Hk, (size_t)(k + 1) * k * sizeof(double2),
+                                      hipMemcpyDeviceToHost, st));
+            }
+        }
+        if (changed) {
+            HIPCHK(hipMemcpyAsync(act, acth.data(), L * sizeof(int), hipMemcpyHostToDevice, st));
+            HIPCHK(hipStreamSynchronize(st));
+        }
+        std::swap(Vc, Vn);
+        std::swap(Hc, Hx);
+        std::swap(cc, cx);
+        std::swap(cur, prv);
+        j0 = k;
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    if (S.st) {
+        for (int b = 0; b < L; ++b) {
+            S.st->cycles_dr += R.cycles[b];
+            S.st->mvp_dr += R.mvps[b];
+        }
+    }
+    for (int b = 0; b < L; ++b)
+        if (!R.conv[b]) return GDR_NOT_CONVERGED;
+    return GDR_OK;
 }
 
 // ---------------------------------------------------------------------------

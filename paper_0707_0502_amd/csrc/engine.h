@@ -98,13 +98,20 @@ struct gdr_op_s {
     bool refine = false;    // the FP32 operator reads ure while set (RefineLinks)
     int anti = 0;           // bit mu: direction mu antiperiodic (bc[mu] = -1)
     double su3_dev = -1;    // largest deviation of the links from SU(3) (-1: not checked)
-    int kind = 0;             // 0: Wilson-Dirac lattice operator, 1: bidiagonal matrix
+    int kind = 0;             // 0: Wilson-Dirac lattice operator, 1: bidiagonal matrix,
+                              // 2: a set of lattices batched together (see parts)
     double2* bd64 = nullptr;  // bidiagonal: diagonal (n) then superdiagonal (n), FP64
     float2* bd32 = nullptr;   //   and the FP32 copy
     // a disc holding the spectrum of A (centre, radius): the s-step basis is
     // built from powers of (A - centre) / radius
     double2 spec_c = {1, 0};
     double spec_r = 1;
+    // kind 2: member b of every batched launch is lattice parts[b]; vectors
+    // have n = the largest part's n and are zero beyond their own part's n.
+    // The FP32 operator of all members runs as one persistent work-list
+    // launch of at most list_blocks blocks.
+    std::vector<gdr_op_s*> parts;
+    int list_blocks = 768;
 };
 
 namespace gdr {
@@ -112,11 +119,13 @@ namespace gdr {
 // with 1 - sigma_v in dl.d[v] (Wilson: A = I - kappa D; bidiagonal: A = M),
 // and the conversions between the caller's canonical complex128 vectors and
 // the internal layout of type T.
+// mem0: batch member of vector 0 (a set of lattices applies member mem0 + v's
+// own operator to vector v; ignored by single operators)
 template <typename T>
 void op_apply(gdr_op_s* op, const typename CT<T>::t* in, int64_t in_stride,
               typename CT<T>::t* out, int64_t out_stride, const typename CT<T>::t* add,
               int64_t add_stride, const DiagList& dl, int nvec, hipStream_t st,
-              const int* act = nullptr);
+              const int* act = nullptr, int mem0 = 0);
 template <typename T>
 void op_pack(gdr_op_s* op, const double2* canon, typename CT<T>::t* dst, int64_t stride, int nvec,
              hipStream_t st);
@@ -305,6 +314,18 @@ struct Stats {
             st->theta[st->theta_len++] = gdr_c64{t[i].x, t[i].y};
     }
 };
+
+// GMRES-DR-Sh on the first right-hand sides of a set of lattices (op->kind
+// == 2) as one batch, mixed precision: member b's right-hand side at
+// b_eo + b*n, its solutions at X + b*ns*n (n = op->n); per-member results and
+// deflation pairs (each for its own lattice, owned by the caller) in R.
+struct ManyOut {
+    std::vector<int> conv, cycles;
+    std::vector<int64_t> mvps;
+    std::vector<gdr_defl_s*> defl;
+};
+int solve_dr_many(gdr_op_s* op, int ns, const double2* sig, const double2* b_eo, double2* X,
+                  const gdr_params& p, Stats& S, ManyOut& R);
 
 // whole-problem solver (internal layouts); returns GDR_OK / GDR_NOT_CONVERGED
 int solve_dr_sh(gdr_op_s* op, int ns, const double2* sig, const double2* b_eo, double2* X_eo,

@@ -38,6 +38,21 @@ struct DiagList {
 // TS spinor type; link storage per `link_storage`; compute in TS.
 // anti: bit mu set when direction mu is antiperiodic (used with LINK_R12,
 // whose links carry no boundary factor). Members with act[v] == 0 are skipped.
+// Several lattices' operators in one persistent launch (FP32 spinors,
+// two-row links): member v (v < nm <= DSLASH_MAXV) is a lattice of geometry
+// g[v] (4^4 tiles) whose tiles are the work items tile0[v] .. tile0[v+1]-1.
+struct LatList {
+    int nm;
+    int tile0[DSLASH_MAXV + 1];
+    Geom g[DSLASH_MAXV];
+    const void* links[DSLASH_MAXV];
+    float kappa[DSLASH_MAXV];
+    int anti[DSLASH_MAXV];
+};
+void dslash_list(const float2* in, int64_t in_stride, float2* out, int64_t out_stride,
+                 const LatList& L, int link_storage, const DiagList& dl, hipStream_t st,
+                 const int* act, int max_blocks);
+
 template <typename TS>
 void dslash(const typename CT<TS>::t* in, int64_t in_stride, typename CT<TS>::t* out,
             int64_t out_stride, const typename CT<TS>::t* add, int64_t add_stride,

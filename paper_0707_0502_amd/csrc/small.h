@@ -33,9 +33,10 @@ struct CycleArgs {
     // 2: restart only (one block per member; s read from the coefficient block)
     int restart;
     int k;
-    double2* P;             // (m+1) x (k+1), ldp = m+1
-    double2* Hnew;          // (m+1) x m zero except the leading (k+1) x k block
-    double2* cnew;          // m+1
+    double2* P;             // (m+1) x (k+1), ldp = m+1              (per member: + b*p_ms)
+    double2* Hnew;          // (m+1) x m zero except the leading (k+1) x k block (+ b*hnew_ms)
+    double2* cnew;          // m+1                                   (per member: + b*cnew_ms)
+    int64_t p_ms = 0, hnew_ms = 0, cnew_ms = 0;
     int m;
     int ns;
     const int* act;         // per member active flag (nullable)
@@ -94,6 +95,8 @@ struct SstepArgs {
     int64_t ldh, h_ms;
     double2 theta;
     double rho;
+    const double2* thetas = nullptr;   // per member centre and radius (members on
+    const double* rhos = nullptr;      //   different operators); else theta, rho
     int* brk;
     const int* act;
     double reorth;    // cancellation ratio above which a block gets a second sweep pair

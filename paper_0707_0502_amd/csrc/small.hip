@@ -364,6 +364,9 @@ __global__ __launch_bounds__(64) void k_cycle_small(CycleArgs a) {
     const double2* beta = a.beta + b * a.beta_ms;
     double2* coef = a.coef + b * a.coef_ms;
     CycleOut* out = a.out + b;
+    double2* const Pm = a.P ? a.P + b * a.p_ms : nullptr;
+    double2* const Hm = a.Hnew ? a.Hnew + b * a.hnew_ms : nullptr;
+    double2* const Cm = a.cnew ? a.cnew + b * a.cnew_ms : nullptr;
     const int ldh = m + 1;
     const int brk = a.brk[b];
     const int p = brk >= 0 ? brk + 1 : m;   // columns of this cycle
@@ -532,7 +535,7 @@ __global__ __launch_bounds__(64) void k_cycle_small(CycleArgs a) {
         // P to global
         for (int j = 0; j <= k; ++j)
             for (int r = lane; r <= m; r += 64)
-                a.P[j * (m + 1) + r] = j < k ? (r < m ? AT(Zs, r, j) : mk(0, 0)) : dv[r];
+                Pm[j * (m + 1) + r] = j < k ? (r < m ? AT(Zs, r, j) : mk(0, 0)) : dv[r];
         // Y = H P_k into A ((m+1) x k), H unshifted
         for (int r = lane; r <= m; r += 64)
             for (int j = 0; j < k; ++j) {
@@ -542,7 +545,7 @@ __global__ __launch_bounds__(64) void k_cycle_small(CycleArgs a) {
             }
         __syncthreads();
         // Hnew = P^H Y ((k+1) x k), zero elsewhere; c_new = P^H s_orig
-        for (int t = lane; t < (m + 1) * m; t += 64) a.Hnew[t] = mk(0, 0);
+        for (int t = lane; t < (m + 1) * m; t += 64) Hm[t] = mk(0, 0);
         __syncthreads();
         for (int t = lane; t < (k + 1) * k; t += 64) {
             const int i = t % (k + 1), j = t / (k + 1);
@@ -552,7 +555,7 @@ __global__ __launch_bounds__(64) void k_cycle_small(CycleArgs a) {
             } else {
                 for (int r = 0; r <= m; ++r) acc = cadd(acc, cjmul(dv[r], AT(A, r, j)));
             }
-            a.Hnew[j * (m + 1) + i] = acc;
+            Hm[j * (m + 1) + i] = acc;
         }
         // original s: recompute from coef column (written above)
         for (int i = lane; i <= m; i += 64) {
@@ -562,7 +565,7 @@ __global__ __launch_bounds__(64) void k_cycle_small(CycleArgs a) {
             } else if (i == k) {
                 for (int r = 0; r <= m; ++r) acc = cadd(acc, cjmul(dv[r], coef[ns * (m + 1) + r]));
             }
-            a.cnew[i] = acc;
+            Cm[i] = acc;
         }
         if (lane == 0) out->tclk[6] = wall_clock64();
         return;
@@ -760,8 +763,8 @@ __global__ __launch_bounds__(64) void k_sstep_small(SstepArgs a) {
     }
     // H columns j..j+bs-1 (rows 0..m), by rows across the lanes
     double2* H = a.H + b * a.h_ms;
-    const double2 th = a.theta;
-    const double rho = a.rho;
+    const double2 th = a.thetas ? a.thetas[b] : a.theta;
+    const double rho = a.rhos ? a.rhos[b] : a.rho;
     for (int r = lane; r <= a.m; r += 64) {
         double2 X[BLK_MAX];
         for (int c = 0; c < bs; ++c) {

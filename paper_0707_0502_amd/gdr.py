@@ -37,6 +37,7 @@ SYMBOLS = [
     "gdr_params_default",
     "gdr_solve_dr_sh", "gdr_solve_proj_sh", "gdr_solve", "gdr_defl_k", "gdr_defl_export",
     "gdr_defl_import", "gdr_defl_destroy", "gdr_tune_load", "gdr_tune_report",
+    "gdr_solve_many",
 ]
 
 
@@ -53,7 +54,7 @@ class gdr_params(ctypes.Structure):
                 ("m_clean", ctypes.c_int), ("proj_k", ctypes.c_int),
                 ("use_graph", ctypes.c_int), ("galerkin", ctypes.c_int),
                 ("sstep", ctypes.c_int), ("sstep_reorth", ctypes.c_double),
-                ("refine_floor", ctypes.c_double)]
+                ("refine_floor", ctypes.c_double), ("persistent", ctypes.c_int)]
 
 
 class gdr_stats(ctypes.Structure):
@@ -113,6 +114,9 @@ def load(path=LIB_PATH):
     lib.gdr_defl_import.argtypes = [vp, ip, vp, vp, ip, ctypes.POINTER(vp)]
     lib.gdr_defl_destroy.argtypes = [vp]
     lib.gdr_defl_destroy.restype = None
+    lib.gdr_solve_many.argtypes = [ip, ctypes.POINTER(vp), ip, ctypes.POINTER(gdr_c64), ip,
+                                   ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                   ctypes.POINTER(gdr_params), ctypes.POINTER(gdr_stats)]
     lib.gdr_tune_load.argtypes = [ctypes.c_char_p]
     lib.gdr_tune_report.argtypes = [ctypes.c_char_p, i64]
     lib.gdr_tune_report.restype = i64
@@ -379,6 +383,37 @@ def gdr_solve(op, sigmas, B, X, params, stats=None):
     pst = _stats(stats, nrhs, ns)
     return op.ctx.check(lib().gdr_solve(
         op.h, ns, _sig(sigmas), nrhs, pB, pX, ctypes.byref(params), pst))
+
+
+def gdr_solve_many(ops, sigmas, Bs, Xs, params, stats=None):
+    """Independent problems on several lattices: ops[l] with right-hand sides
+    Bs[l] (nrhs x n_l) into Xs[l] (nrhs x ns x n_l); stats: None or one Stats
+    per lattice. params.persistent selects the batched first phase."""
+    nops = len(ops)
+    if nops < 1 or len(Bs) != nops or len(Xs) != nops:
+        raise ValueError("one right-hand side and one solution buffer per operator")
+    ns = len(sigmas)
+    nrhs = _nrhs(Bs[0], ops[0].n)
+    hv = (ctypes.c_void_p * nops)(*[o.h for o in ops])
+    pb = (ctypes.c_void_p * nops)()
+    px = (ctypes.c_void_p * nops)()
+    for l, o in enumerate(ops):
+        pb[l] = _dev(Bs[l], "B[%d]" % l, nrhs * o.n).value
+        px[l] = _dev(Xs[l], "X[%d]" % l, nrhs * ns * o.n if ns > 0 else None).value
+    sa = None
+    if stats is not None:
+        if len(stats) != nops:
+            raise ValueError("one Stats per operator")
+        sa = (gdr_stats * nops)()
+        for l, s_ in enumerate(stats):
+            _stats(s_, nrhs, ns)
+            sa[l] = s_.s
+    rc = lib().gdr_solve_many(nops, hv, ns, _sig(sigmas), nrhs, pb, px, ctypes.byref(params),
+                              sa)
+    if sa is not None:
+        for l, s_ in enumerate(stats):
+            ctypes.memmove(ctypes.byref(s_.s), ctypes.byref(sa[l]), ctypes.sizeof(gdr_stats))
+    return ops[0].ctx.check(rc)
 
 
 def gdr_defl_k(defl):

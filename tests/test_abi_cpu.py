@@ -41,9 +41,9 @@ def test_struct_layouts_match_header(tmp_path):
 #include <stddef.h>
 #include "gdr.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(gdr_params), sizeof(gdr_stats),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(gdr_params), sizeof(gdr_stats),
          offsetof(gdr_params, tol), offsetof(gdr_params, max_refine), offsetof(gdr_params, galerkin), offsetof(gdr_params, sstep), offsetof(gdr_params, sstep_reorth),
-         offsetof(gdr_params, refine_floor),
+         offsetof(gdr_params, refine_floor), offsetof(gdr_params, persistent),
          offsetof(gdr_stats, mvp_dr), offsetof(gdr_stats, t_phase),
          offsetof(gdr_stats, resid), offsetof(gdr_stats, theta_len),
          offsetof(gdr_stats, k_ms), offsetof(gdr_stats, k_launches));
@@ -55,7 +55,7 @@ int main(void) {
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     P, S = gdr.gdr_params, gdr.gdr_stats
     want = [ctypes.sizeof(P), ctypes.sizeof(S), P.tol.offset, P.max_refine.offset, P.galerkin.offset, P.sstep.offset, P.sstep_reorth.offset,
-            P.refine_floor.offset,
+            P.refine_floor.offset, P.persistent.offset,
             S.mvp_dr.offset, S.t_phase.offset, S.resid.offset, S.theta_len.offset,
             S.k_ms.offset, S.k_launches.offset]
     assert got == want

@@ -169,3 +169,69 @@ def test_contexts_share_the_device_cache(inputs):
     for c, op in first:
         gdr.gdr_op_destroy(op)
         gdr.gdr_ctx_destroy(c)
+
+
+def test_uneven_batch_concurrent_persistent(inputs):
+    """The same batch with params.persistent = 1 for the ten small lattices:
+    one gdr_solve_many call runs their first right-hand sides as one batch
+    (one work-list operator launch over all their tiles per Arnoldi power,
+    one launch per sweep over the lattices), then each lattice's later
+    right-hand side and cleanup on its own context; concurrently the
+    32^3x64 lattice is solved by gdr_solve on its own thread. Every true
+    residual is checked as above."""
+    from paper_0707_0502_amd import gdr
+    runs = _make_runs(inputs, gdr.GDR_PREC_MIXED)
+    big = [r for r in runs if r["name"] == "C5"][0]
+    small = [r for r in runs if r["name"] != "C5"]
+    cfg0 = small[0]["cfg"]
+    for r in small:   # one batch: the same shifts, right-hand side count and parameters
+        assert r["cfg"]["sigmas"] == cfg0["sigmas"] and len(r["cfg"]["rhs"]) == len(cfg0["rhs"])
+        assert (r["cfg"]["m_dr"], r["cfg"]["k"], r["cfg"]["m_proj"]) == (cfg0["m_dr"], cfg0["k"], cfg0["m_proj"])
+    p = gdr.gdr_params_default(m_dr=cfg0["m_dr"], k=cfg0["k"], m_proj=cfg0["m_proj"], tol=cfg0["tol"],
+                               tol_extra=cfg0["tol_extra"], precision=gdr.GDR_PREC_MIXED,
+                               use_graph=1, persistent=1)
+    out = {}
+
+    def run_many():
+        t0 = time.perf_counter()
+        try:
+            out["rc"] = gdr.gdr_solve_many([r["op"] for r in small], cfg0["sigmas"],
+                                           [r["Bd"] for r in small], [r["X"] for r in small], p,
+                                           [r["st"] for r in small])
+        except gdr.GdrError as e:
+            out["rc"], out["err"] = e.code, str(e)
+        out["sec"] = time.perf_counter() - t0
+
+    def run_big():
+        t0 = time.perf_counter()
+        big["rc"] = gdr.gdr_solve(big["op"], big["cfg"]["sigmas"], big["Bd"], big["X"], big["p"],
+                                  big["st"])
+        big["sec"] = time.perf_counter() - t0
+
+    torch_mod().cuda.synchronize()
+    th = [threading.Thread(target=run_many), threading.Thread(target=run_big)]
+    t0 = time.perf_counter()
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    say("persistent batch: wall %.2f s, ten small lattices %.2f s (rc %s %s), 32^3x64 %.2f s"
+        % (time.perf_counter() - t0, out["sec"], out["rc"], out.get("err", ""), big["sec"]))
+    assert out["rc"] == gdr.GDR_OK and big["rc"] == gdr.GDR_OK
+    for r in runs:
+        cfg = r["cfg"]
+        say(r["name"], "max resid %.2e" % r["st"].resid.max(),
+            {k: v for k, v in r["st"].as_dict().items() if k.startswith("mvp")})
+        assert r["st"].resid.max() <= cfg["tol"]
+        assert r["st"].s.mvp_dr > 0
+        A = wilson.WilsonOperator(r["links"], r["kappa"])
+        nrhs, ns = len(cfg["rhs"]), len(cfg["sigmas"])
+        X = r["X"].cpu().numpy().reshape(nrhs, ns, -1)
+        pairs = [(j, i) for j in range(nrhs) for i in range(ns)]
+        if r["name"] == "C5":
+            pairs = [(0, 0), (nrhs - 1, ns - 1)]
+        for j, i in pairs:
+            res = np.linalg.norm(gmres.true_residual(A, r["B"][j], X[j, i], cfg["sigmas"][i]))
+            res /= np.linalg.norm(r["B"][j])
+            assert res <= cfg["tol"] * 1.01, (r["name"], j, i, res)
+    _drop(runs)
