@@ -229,8 +229,10 @@ def operator_timings(a, gdr, synth, ctx, op, dims, kappa, links, n):
 def uneven_batch(a, gdr, synth, torch, np):
     """The uneven mixed batch: one 32^3x64 lattice with FP16-stored links
     (8 shifts, 4 Z4 RHS) solved concurrently with six 12^4 and four 16^4
-    lattices (4 shifts, 2 RHS), each lattice on its own context and stream
-    and a host thread of its own, Arnoldi cycles replayed from HIP graphs.
+    lattices (4 shifts, 2 RHS), each lattice on its own context and stream,
+    Arnoldi cycles replayed from HIP graphs; the small lattices by one
+    gdr_solve_many call with persistent work-list launches (--c5-persistent 1,
+    the default) or each on a host thread of its own (0).
     value: wall time of the whole batch divided by its 24 right-hand sides;
     the same batch in plain FP64 (also concurrent, on contexts of its own) is
     timed first."""
@@ -274,6 +276,9 @@ def uneven_batch(a, gdr, synth, torch, np):
         torch.cuda.empty_cache()
 
     def batch(prec, profile_big=False):
+        if prec == gdr.GDR_PREC_MIXED and a.c5_persistent:
+            return batch_persistent(profile_big)
+
         def solve(r):
             cfg = r["cfg"]
             p = gdr.gdr_params_default(m_dr=cfg["m_dr"], k=cfg["k"], m_proj=cfg["m_proj"],
@@ -290,6 +295,51 @@ def uneven_batch(a, gdr, synth, torch, np):
             r["sec"] = time.perf_counter() - t0
             r["st"] = st
         threads = [threading.Thread(target=solve, args=(r,)) for r in runs]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    def batch_persistent(profile_big):
+        # the 32^3x64 lattice by gdr_solve on its own thread; the ten small
+        # lattices by one gdr_solve_many call (params.persistent = 1: their
+        # first right-hand sides as one batch of work-list launches, then each
+        # lattice's later right-hand side and cleanup on its own context)
+        big = next(r for r in runs if r["name"] == "C5")
+        small = [r for r in runs if r["name"] != "C5"]
+        c0 = small[0]["cfg"]
+
+        def solve_big():
+            cfg = big["cfg"]
+            p = gdr.gdr_params_default(m_dr=cfg["m_dr"], k=cfg["k"], m_proj=cfg["m_proj"],
+                                       tol=cfg["tol"], tol_extra=cfg["tol_extra"],
+                                       precision=gdr.GDR_PREC_MIXED, use_graph=1,
+                                       refine_floor=a.refine_floor, m_clean=a.m_clean)
+            if profile_big:
+                p.profile = 0xFF
+            st = gdr.Stats(len(cfg["rhs"]), len(cfg["sigmas"]))
+            t0 = time.perf_counter()
+            big["rc"] = gdr.gdr_solve(big["op"], cfg["sigmas"], big["Bd"], big["X"], p, st)
+            big["sec"] = time.perf_counter() - t0
+            big["st"] = st
+
+        def solve_small():
+            p = gdr.gdr_params_default(m_dr=c0["m_dr"], k=c0["k"], m_proj=c0["m_proj"],
+                                       tol=c0["tol"], tol_extra=c0["tol_extra"],
+                                       precision=gdr.GDR_PREC_MIXED, use_graph=1,
+                                       refine_floor=a.refine_floor, m_clean=a.m_clean,
+                                       persistent=1)
+            sts = [gdr.Stats(len(r["cfg"]["rhs"]), len(r["cfg"]["sigmas"])) for r in small]
+            rc = gdr.gdr_solve_many([r["op"] for r in small], c0["sigmas"],
+                                    [r["Bd"] for r in small], [r["X"] for r in small], p, sts)
+            for r, st in zip(small, sts):
+                r["rc"], r["st"], r["sec"] = rc, st, st.s.t_total
+
+        threads = [threading.Thread(target=solve_big), threading.Thread(target=solve_small)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for t in threads:
@@ -375,7 +425,10 @@ def uneven_batch(a, gdr, synth, torch, np):
                                "(n=25165824, FP16-stored links) 4 Z4 RHS x 8 shifts, GMRES-DR(60,20)-Sh + "
                                "GMRES(40)-Proj(20)-Sh; six 12^4 and four 16^4 lattices, 2 Z4 RHS x 4 "
                                "shifts, DR(40,15) + Proj(40,15); tol 1e-8; one context and stream per "
-                               "lattice, Arnoldi cycles replayed from HIP graphs",
+                               "lattice, Arnoldi cycles replayed from HIP graphs" +
+                               ("; the ten small lattices in one gdr_solve_many call whose first "
+                                "right-hand sides run as one batch of persistent work-list launches"
+                                if a.c5_persistent else ""),
                    "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES"),
                    "name": "C5", "nrhs": nrhs, "global_batch": nrhs, "parallelism": "1 GPU",
                    "precision": "mixed: FP32 matvec/Gram-Schmidt/basis, FP64 small problems, "
@@ -415,6 +468,9 @@ def main():
     ap.add_argument("--c5-links", choices=["f16", "f32"], default="f16",
                     help="link storage of the uneven batch's 32^3x64 lattice (default: the "
                          "workload's FP16)")
+    ap.add_argument("--c5-persistent", type=int, choices=[0, 1], default=1,
+                    help="uneven batch: the ten small lattices as one gdr_solve_many call with "
+                         "persistent work-list launches (1) or on contexts of their own (0)")
     ap.add_argument("--hw-queues", type=int, default=12,
                     help="hardware queues per process for the uneven batch (C5; 0: the "
                          "environment's setting)")
