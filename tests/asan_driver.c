@@ -44,6 +44,10 @@ int main(int argc, char** argv) {
     CHECK(gdr_solve_dr_sh(NULL, 1, &s, NULL, NULL, &p, NULL, NULL) == GDR_ERR_ARG);
     CHECK(gdr_solve_proj_sh(NULL, NULL, 1, &s, 1, NULL, NULL, &p, NULL) == GDR_ERR_ARG);
     CHECK(gdr_defl_export(NULL, NULL, NULL) == GDR_ERR_ARG);
+    CHECK(gdr_solve_many(0, NULL, 1, &s, 1, NULL, NULL, &p, NULL) == GDR_ERR_ARG);
+    gdr_op none[2] = {NULL, NULL};
+    CHECK(gdr_solve_many(2, none, 1, &s, 1, NULL, NULL, &p, NULL) == GDR_ERR_ARG);
+    CHECK(p.persistent == 0);
     int dims[4] = {4, 4, 4, 4}, bc[4] = {1, 1, 1, -1};
     gdr_op op = NULL;
     CHECK(gdr_wilson_create(NULL, dims, bc, 0.1, NULL, 0, GDR_LINKS_F32, &op) == GDR_ERR_ARG);
