@@ -990,9 +990,12 @@ static void proj_run(gdr_op_s* op, gdr_defl_s* defl, int nmem, int ns,
                      const std::vector<double>& tol, const std::vector<double>& bnorm, int m,
                      int max_cycles, Stats& S, const std::vector<int>& phase, ProjResult& R,
                      bool start = false, int kp = 0, bool graph = false, int sblk = 0,
-                     double reorth = 20) {
+                     double reorth = 20, bool replace = true) {
     // kp > 0: project over the leading kp deflation vectors only (the
     // accurate-eigenvector variant, Table 4.1); otherwise over all k.
+    // replace (mixed precision): the base residual is replaced by the FP64
+    // true residual after every cycle; otherwise the FP32 recursion's residual
+    // is kept (inner solves of a refinement, whose caller checks true residuals)
     // graph: replay the Arnoldi cycle from a captured HIP graph
     // start: W already holds an initial guess x_i and the common residual r
     // (related right-hand sides, Sec. 5); otherwise x_i = 0, r = b
@@ -1131,7 +1134,7 @@ static void proj_run(gdr_op_s* op, gdr_defl_s* defl, int nmem, int ns,
                     act);
         S.prof.end(GDR_K_COMBINE, dn * ((m + 1) * cs + 32.0 * ns + 16),
                    dn * (m + 1) * (ns + 1) * 8);
-        if (mixed) {
+        if (mixed && replace) {
             // base residual replaced by the FP64 true residual of shift 1
             for (int b0 = 0; b0 < nmem; b0 += DSLASH_MAXV) {
                 const int nb = std::min(DSLASH_MAXV, nmem - b0);
@@ -1170,7 +1173,7 @@ static void proj_run(gdr_op_s* op, gdr_defl_s* defl, int nmem, int ns,
             R.mvps[b] += m;
             step_mvps += m;
             R.cycles[b] += 1;
-            const double rn = mixed ? std::sqrt(rnh[b].x) : oh[b].snorm;
+            const double rn = mixed && replace ? std::sqrt(rnh[b].x) : oh[b].snorm;
             double bmax = 1;
             for (int i = 1; i < ns; ++i) bmax = std::max(bmax, zabs(oh[b].beta[i]));
             const double r1 = rn / bnorm[b];
@@ -1201,7 +1204,7 @@ static void proj_run(gdr_op_s* op, gdr_defl_s* defl, int nmem, int ns,
                 for (int c = 0; c < nmem; ++c)
                     if (phase[c] == phase[b] && R.cycles[c] == cyc + 1) {
                         any = true;
-                        const double rn = mixed ? std::sqrt(rnh[c].x) : oh[c].snorm;
+                        const double rn = mixed && replace ? std::sqrt(rnh[c].x) : oh[c].snorm;
                         double bmax = 1;
                         for (int i = 1; i < ns; ++i) bmax = std::max(bmax, zabs(oh[c].beta[i]));
                         w1 = std::max(w1, rn / bnorm[c]);
@@ -1542,6 +1545,11 @@ int cleanup(gdr_op_s* op, gdr_defl_s* defl, int ns, const double2* sig, int nrhs
     // (8 measured fastest on the 24^3x48 twelve-RHS workload: 16 and 24 cost
     // 1.7x and 6x more cleanup time for the same final residuals)
     const int mc = p.m_clean > 0 ? p.m_clean : std::min(p.m_proj, 8);
+    // The inner solves keep the FP32 recursion's residual (no FP64
+    // replacement per cycle): they only reduce their residual by a factor of
+    // at least 1e-5, well within what the recursion tracks, and every round
+    // starts from FP64 true residuals (24^3x48: the same products, -8 % of
+    // the cleanup's time; 32^3x64 with FP16 links: -5 % of the solve).
     // inner tolerance floor of a round: what an FP32 solve reliably reaches
     // (with FP16-stored links a floor of 1e-2 saved 5 % of the cleanup
     // products on the 32^3x64 lattice and no time, so one default serves both)
@@ -1588,7 +1596,8 @@ int cleanup(gdr_op_s* op, gdr_defl_s* defl, int ns, const double2* sig, int nrhs
                                  false, 0, p.use_graph != 0);
             else
                 proj_run<float>(op, defl, nmem, 1, sgm, Bm, W, tol, bnorm, mc, p.max_cycles, S, phase, Rr,
-                                false, 0, p.use_graph != 0, p.sstep, p.sstep_reorth);
+                                false, 0, p.use_graph != 0, p.sstep, p.sstep_reorth,
+                                /*replace=*/false);
             for (int b = 0; b < nmem; ++b) {
                 const Pair& q = todo[pos + b];
                 axpy_dev(X_eo + ((int64_t)q.j * ns + q.i) * n, 0, W + (int64_t)b * 2 * n, 0,
