@@ -919,13 +919,12 @@ __global__ __launch_bounds__(256) void k_vcombine(const typename CT<T>::t* __res
 }
 
 // The same combination when all members share one basis (v_ms = 0, the
-// deflation basis of the projection step): a block takes two members, so
-// each basis row is read once for both. One row per lane (8-byte FP32
-// loads): the two members' accumulators take the registers that the second
-// row takes in k_vcombine. Per row and output the sum runs over l in the
-// same order as in k_vcombine (the compiler may fuse the multiply-adds
-// differently, so results agree to rounding, not bit for bit).
-template <typename T, int MO>
+// deflation basis of the projection step): a block takes MG members, so
+// each basis row is read once for all of them. One row per lane (8-byte FP32
+// loads). Per row and output the sum runs over l in the same order as in
+// k_vcombine (the compiler may fuse the multiply-adds differently, so results
+// agree with it, and between MG = 2 and 4, to rounding, not bit for bit).
+template <typename T, int MO, int MG>
 __global__ __launch_bounds__(256) void k_vcombine2(const typename CT<T>::t* __restrict__ V,
                                                    int64_t ldv, int ncols,
                                                    const double2* __restrict__ coef, int ldc,
@@ -934,22 +933,27 @@ __global__ __launch_bounds__(256) void k_vcombine2(const typename CT<T>::t* __re
                                                    int64_t n, int nmem, const int* __restrict__ act) {
     using IO = RowIO<T, 1>;
     constexpr int CH = 8;
-    const int b0 = blockIdx.y * 2;
-    const bool on0 = !act || act[b0];
-    const bool on1 = b0 + 1 < nmem && (!act || act[b0 + 1]);
-    if (!on0 && !on1) return;   // uniform over the block
-    __shared__ double2 cs[2][(MAXM + 1) * MO];
-    for (int t = threadIdx.x; t < 2 * ncols * nout; t += blockDim.x) {
+    const int b0 = blockIdx.y * MG;
+    bool on[MG];
+    bool any = false;
+#pragma unroll
+    for (int m = 0; m < MG; ++m) {
+        on[m] = b0 + m < nmem && (!act || act[b0 + m]);
+        any = any || on[m];
+    }
+    if (!any) return;   // uniform over the block
+    __shared__ double2 cs[MG][(MAXM + 1) * MO];
+    for (int t = threadIdx.x; t < MG * ncols * nout; t += blockDim.x) {
         const int m = t / (ncols * nout), u = t % (ncols * nout);
         const int l = u % ncols, s = u / ncols;
-        cs[m][u] = (m == 0 || on1) ? coef[(b0 + m) * c_ms + l + s * ldc] : mk(0, 0);
+        cs[m][u] = on[m] ? coef[(b0 + m) * c_ms + l + s * ldc] : mk(0, 0);
     }
     __syncthreads();
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        double2 acc[2][MO];
+        double2 acc[MG][MO];
 #pragma unroll
-        for (int m = 0; m < 2; ++m)
+        for (int m = 0; m < MG; ++m)
 #pragma unroll
             for (int s = 0; s < MO; ++s) acc[m][s] = mk(0, 0);
         for (int l0 = 0; l0 < ncols; l0 += CH) {
@@ -963,15 +967,15 @@ __global__ __launch_bounds__(256) void k_vcombine2(const typename CT<T>::t* __re
                     double2 v;
                     IO::get(vr[c], &v);
 #pragma unroll
-                    for (int m = 0; m < 2; ++m)
+                    for (int m = 0; m < MG; ++m)
 #pragma unroll
                         for (int s = 0; s < MO; ++s)
                             if (s < nout) acc[m][s] = cadd(acc[m][s], cmul(v, cs[m][l0 + c + s * ncols]));
                 }
         }
 #pragma unroll
-        for (int m = 0; m < 2; ++m) {
-            if (!(m == 0 ? on0 : on1)) continue;
+        for (int m = 0; m < MG; ++m) {
+            if (!on[m]) continue;
 #pragma unroll
             for (int s = 0; s < MO; ++s)
                 if (s < nout) {
@@ -989,13 +993,20 @@ void vcombine(const typename CT<T>::t* V, int64_t ldv, int64_t v_mstride, int nc
               hipStream_t st, const int* act) {
     constexpr bool f32 = std::is_same<T, float>::value;
     if (v_mstride == 0 && nmem > 1 && nout <= 8) {
-        // one shared basis: two members per block
+        // one shared basis: four members per block for up to 4 outputs, two
+        // for more (the accumulators of MG x MO outputs stay in registers)
+        if (nout <= 4 && nmem > 2) {
+            const dim3 grid4(vec_grid(n), (nmem + 3) / 4), blk4(256);
+            hipLaunchKernelGGL((k_vcombine2<T, 4, 4>), grid4, blk4, 0, st, V, ldv, ncols, coef, ldc,
+                               c_mstride, nout, out, o_stride, o_mstride, keep_mask, n, nmem, act);
+            return;
+        }
         const dim3 grid2(vec_grid(n), (nmem + 1) / 2), blk2(256);
         if (nout <= 4)
-            hipLaunchKernelGGL((k_vcombine2<T, 4>), grid2, blk2, 0, st, V, ldv, ncols, coef, ldc,
+            hipLaunchKernelGGL((k_vcombine2<T, 4, 2>), grid2, blk2, 0, st, V, ldv, ncols, coef, ldc,
                                c_mstride, nout, out, o_stride, o_mstride, keep_mask, n, nmem, act);
         else
-            hipLaunchKernelGGL((k_vcombine2<T, 8>), grid2, blk2, 0, st, V, ldv, ncols, coef, ldc,
+            hipLaunchKernelGGL((k_vcombine2<T, 8, 2>), grid2, blk2, 0, st, V, ldv, ncols, coef, ldc,
                                c_mstride, nout, out, o_stride, o_mstride, keep_mask, n, nmem, act);
         return;
     }
