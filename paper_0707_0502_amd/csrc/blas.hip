@@ -148,6 +148,24 @@ static inline bool pairable(int64_t n, std::initializer_list<int64_t> strides,
     return true;
 }
 
+// Element i of a row array at a uniform base, addressed by a 32-bit byte
+// offset (callers keep i * sizeof(P) below 2^32): the global access then
+// takes the base in scalar registers and one 32-bit offset per lane, so a run
+// of stores needs no 64-bit address registers between them (reusing the
+// registers of a store still in flight costs a wait for all memory
+// operations of the wave).
+template <class P>
+static __device__ __forceinline__ P* at32(P* base, int64_t i) {
+    return (P*)((char*)base + (uint32_t)((uint64_t)i * sizeof(P)));
+}
+// a ? x : y on the components (a select of whole array elements can turn
+// into an indexed access that moves the array to scratch memory)
+static __device__ __forceinline__ double2 csel(bool a, double2 x, double2 y) {
+    return mk(a ? x.x : y.x, a ? x.y : y.y);
+}
+// rows per launch of the kernels that use at32 (2^27 rows of 16 bytes)
+constexpr int64_t AT32_ROWS = int64_t(1) << 27;
+
 // ---------------------------------------------------------------------------
 // Delayed classical Gram-Schmidt (DCGS2) passes of the Arnoldi step.
 //
@@ -858,8 +876,24 @@ void fill_int(int* p, int v, int n, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
-// out_s = keep_s * out_s + sum_l V_l coef[l + s*ldc]
+// out_s = keep_s * out_s + sum_l V_l coef[l + s*ldc], summed from out_s
+// (if kept) in the order of l.
+//
+// The coefficients are the same for every row, so they are read with uniform
+// (scalar) loads straight from `coef` and enter the multiply-adds as scalar
+// operands; each complex multiply-add is four FP64 fused multiply-adds. MO is
+// the number of outputs a launch computes: nout itself up to 8 (no output
+// computed in vain), else VC_MAXOUT, where outputs nout..MO-1 repeat output 0
+// (same coefficients, same store).
 constexpr int VC_MAXOUT = MAXNS + 2;
+
+// acc += v * w, real and imaginary parts each by two fused multiply-adds
+static __device__ __forceinline__ void cmac(double2& acc, double2 v, double2 w) {
+    acc.x = fma(v.x, w.x, acc.x);
+    acc.x = fma(-v.y, w.y, acc.x);
+    acc.y = fma(v.x, w.y, acc.y);
+    acc.y = fma(v.y, w.x, acc.y);
+}
 
 template <typename T, int R, int MO>
 __global__ __launch_bounds__(256) void k_vcombine(const typename CT<T>::t* __restrict__ V,
@@ -875,55 +909,55 @@ __global__ __launch_bounds__(256) void k_vcombine(const typename CT<T>::t* __res
     V += b * v_ms;
     coef += b * c_ms;
     out += b * o_ms;
-    __shared__ double2 cs[(MAXM + 1) * VC_MAXOUT];
-    for (int t = threadIdx.x; t < ncols * nout; t += blockDim.x) {
-        int l = t % ncols, s = t / ncols;
-        cs[t] = coef[l + s * ldc];
-    }
-    __syncthreads();
     for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * R; i < n;
          i += (int64_t)gridDim.x * blockDim.x * R) {
+        // A kept output starts its sum, loaded first (the loads' latency
+        // overlaps the basis loads); an output not kept loads output 0 and
+        // drops it, so no load sits in a branch of its own.
         double2 acc[MO][R];
 #pragma unroll
-        for (int s = 0; s < MO; ++s)
+        for (int s = 0; s < MO; ++s) {
+            const bool kp = s < nout && ((keep >> s) & 1u);
+            const double2* os = out + (kp ? s : 0) * o_stride;
 #pragma unroll
-            for (int r = 0; r < R; ++r) acc[s][r] = mk(0, 0);
+            for (int r = 0; r < R; ++r) acc[s][r] = csel(kp, *at32(os, i + r), mk(0, 0));
+        }
         for (int l0 = 0; l0 < ncols; l0 += CH) {
             typename IO::V vr[CH];
 #pragma unroll
             for (int c = 0; c < CH; ++c)
-                if (l0 + c < ncols) vr[c] = IO::ldnt(V + (int64_t)(l0 + c) * ldv + i);
+                if (l0 + c < ncols) vr[c] = IO::ldnt(at32(V + (int64_t)(l0 + c) * ldv, i));
 #pragma unroll
             for (int c = 0; c < CH; ++c)
                 if (l0 + c < ncols) {
                     double2 v[R];
                     IO::get(vr[c], v);
 #pragma unroll
-                    for (int s = 0; s < MO; ++s)
-                        if (s < nout) {
-                            const double2 w = cs[l0 + c + s * ncols];
+                    for (int s = 0; s < MO; ++s) {
+                        const double2 w = coef[l0 + c + (s < nout ? s : 0) * ldc];
 #pragma unroll
-                            for (int r = 0; r < R; ++r) acc[s][r] = cadd(acc[s][r], cmul(v[r], w));
-                        }
+                        for (int r = 0; r < R; ++r) cmac(acc[s][r], v[r], w);
+                    }
                 }
         }
+        // outputs nout..MO-1 repeat the store of output 0 (same address, same
+        // value): the stores run with no branch between them
 #pragma unroll
-        for (int s = 0; s < MO; ++s)
-            if (s < nout)
+        for (int s = 0; s < MO; ++s) {
+            const bool real = s < nout;
+            double2* os = out + (real ? s : 0) * o_stride;
 #pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    double2* o = out + s * o_stride + i + r;
-                    *o = ((keep >> s) & 1u) ? cadd(*o, acc[s][r]) : acc[s][r];
-                }
+            for (int r = 0; r < R; ++r) *at32(os, i + r) = csel(real, acc[s][r], acc[0][r]);
+        }
     }
 }
 
 // The same combination when all members share one basis (v_ms = 0, the
 // deflation basis of the projection step): a block takes MG members, so
 // each basis row is read once for all of them. One row per lane (8-byte FP32
-// loads). Per row and output the sum runs over l in the same order as in
-// k_vcombine (the compiler may fuse the multiply-adds differently, so results
-// agree with it, and between MG = 2 and 4, to rounding, not bit for bit).
+// loads). Per row and output the sum starts from the kept output and runs
+// over l in the same order, with the same operations, as in k_vcombine.
+// Members past nmem take member b0's coefficients and store nothing.
 template <typename T, int MO, int MG>
 __global__ __launch_bounds__(256) void k_vcombine2(const typename CT<T>::t* __restrict__ V,
                                                    int64_t ldv, int ncols,
@@ -942,46 +976,47 @@ __global__ __launch_bounds__(256) void k_vcombine2(const typename CT<T>::t* __re
         any = any || on[m];
     }
     if (!any) return;   // uniform over the block
-    __shared__ double2 cs[MG][(MAXM + 1) * MO];
-    for (int t = threadIdx.x; t < MG * ncols * nout; t += blockDim.x) {
-        const int m = t / (ncols * nout), u = t % (ncols * nout);
-        const int l = u % ncols, s = u / ncols;
-        cs[m][u] = on[m] ? coef[(b0 + m) * c_ms + l + s * ldc] : mk(0, 0);
-    }
-    __syncthreads();
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         double2 acc[MG][MO];
 #pragma unroll
         for (int m = 0; m < MG; ++m)
 #pragma unroll
-            for (int s = 0; s < MO; ++s) acc[m][s] = mk(0, 0);
+            for (int s = 0; s < MO; ++s) {
+                const bool kp = on[m] && s < nout && ((keep >> s) & 1u);
+                const double2 o = *at32(out + (int64_t)b0 * o_ms + (kp ? m * o_ms + s * o_stride : 0), i);
+                acc[m][s] = csel(kp, o, mk(0, 0));
+            }
         for (int l0 = 0; l0 < ncols; l0 += CH) {
             typename IO::V vr[CH];
 #pragma unroll
             for (int c = 0; c < CH; ++c)
-                if (l0 + c < ncols) vr[c] = IO::ldnt(V + (int64_t)(l0 + c) * ldv + i);
+                if (l0 + c < ncols) vr[c] = IO::ldnt(at32(V + (int64_t)(l0 + c) * ldv, i));
 #pragma unroll
             for (int c = 0; c < CH; ++c)
                 if (l0 + c < ncols) {
                     double2 v;
                     IO::get(vr[c], &v);
 #pragma unroll
-                    for (int m = 0; m < MG; ++m)
+                    for (int m = 0; m < MG; ++m) {
+                        const double2* cm = coef + (int64_t)(b0 + m < nmem ? b0 + m : b0) * c_ms;
 #pragma unroll
                         for (int s = 0; s < MO; ++s)
-                            if (s < nout) acc[m][s] = cadd(acc[m][s], cmul(v, cs[m][l0 + c + s * ncols]));
+                            cmac(acc[m][s], v, cm[l0 + c + (s < nout ? s : 0) * ldc]);
+                    }
                 }
         }
+        // per member, outputs nout..MO-1 repeat the store of output 0, as in
+        // k_vcombine
 #pragma unroll
         for (int m = 0; m < MG; ++m) {
             if (!on[m]) continue;
 #pragma unroll
-            for (int s = 0; s < MO; ++s)
-                if (s < nout) {
-                    double2* o = out + (int64_t)(b0 + m) * o_ms + s * o_stride + i;
-                    *o = ((keep >> s) & 1u) ? cadd(*o, acc[m][s]) : acc[m][s];
-                }
+            for (int s = 0; s < MO; ++s) {
+                const bool real = s < nout;
+                *at32(out + (int64_t)(b0 + m) * o_ms + (real ? s : 0) * o_stride, i) =
+                    csel(real, acc[m][s], acc[m][0]);
+            }
         }
     }
 }
@@ -992,22 +1027,31 @@ void vcombine(const typename CT<T>::t* V, int64_t ldv, int64_t v_mstride, int nc
               int64_t o_stride, int64_t o_mstride, unsigned keep_mask, int64_t n, int nmem,
               hipStream_t st, const int* act) {
     constexpr bool f32 = std::is_same<T, float>::value;
+    if (nout < 1 || nout > VC_MAXOUT) throw std::runtime_error("vcombine: output count out of range");
+    if (n > AT32_ROWS) {   // rows are independent: launches of at most AT32_ROWS rows
+        for (int64_t r0 = 0; r0 < n; r0 += AT32_ROWS)
+            vcombine<T>(V + r0, ldv, v_mstride, ncols, coef, ldc, c_mstride, nout, out + r0, o_stride,
+                        o_mstride, keep_mask, std::min(AT32_ROWS, n - r0), nmem, st, act);
+        return;
+    }
     if (v_mstride == 0 && nmem > 1 && nout <= 8) {
         // one shared basis: four members per block for up to 4 outputs, two
         // for more (the accumulators of MG x MO outputs stay in registers)
-        if (nout <= 4 && nmem > 2) {
-            const dim3 grid4(vec_grid(n), (nmem + 3) / 4), blk4(256);
-            hipLaunchKernelGGL((k_vcombine2<T, 4, 4>), grid4, blk4, 0, st, V, ldv, ncols, coef, ldc,
-                               c_mstride, nout, out, o_stride, o_mstride, keep_mask, n, nmem, act);
-            return;
+#define VCOMB2(MO, MG)                                                                           \
+    hipLaunchKernelGGL((k_vcombine2<T, MO, MG>), dim3(vec_grid(n), (nmem + MG - 1) / MG),      \
+                       dim3(256), 0, st, V, ldv, ncols, coef, ldc, c_mstride, nout, out, o_stride, \
+                       o_mstride, keep_mask, n, nmem, act)
+        switch (nout) {
+            case 1: VCOMB2(1, 4); break;
+            case 2: VCOMB2(2, 4); break;
+            case 3: VCOMB2(3, 4); break;
+            case 4: VCOMB2(4, 4); break;
+            case 5: VCOMB2(5, 2); break;
+            case 6: VCOMB2(6, 2); break;
+            case 7: VCOMB2(7, 2); break;
+            default: VCOMB2(8, 2); break;
         }
-        const dim3 grid2(vec_grid(n), (nmem + 1) / 2), blk2(256);
-        if (nout <= 4)
-            hipLaunchKernelGGL((k_vcombine2<T, 4, 2>), grid2, blk2, 0, st, V, ldv, ncols, coef, ldc,
-                               c_mstride, nout, out, o_stride, o_mstride, keep_mask, n, nmem, act);
-        else
-            hipLaunchKernelGGL((k_vcombine2<T, 8, 2>), grid2, blk2, 0, st, V, ldv, ncols, coef, ldc,
-                               c_mstride, nout, out, o_stride, o_mstride, keep_mask, n, nmem, act);
+#undef VCOMB2
         return;
     }
     const bool r2 = f32 && pairable(n, {ldv, v_mstride}, {V});
@@ -1020,16 +1064,25 @@ void vcombine(const typename CT<T>::t* V, int64_t ldv, int64_t v_mstride, int nc
 #define VCOMB(R, MO)                                                                            \
     hipLaunchKernelGGL((k_vcombine<T, R, MO>), grid, blk, 0, st, V, ldv, v_mstride, ncols, coef, \
                        ldc, c_mstride, nout, out, o_stride, o_mstride, keep_mask, n, act)
+#define VCOMB_ALL(R)                          \
+    switch (nout) {                           \
+        case 1: VCOMB(R, 1); break;           \
+        case 2: VCOMB(R, 2); break;           \
+        case 3: VCOMB(R, 3); break;           \
+        case 4: VCOMB(R, 4); break;           \
+        case 5: VCOMB(R, 5); break;           \
+        case 6: VCOMB(R, 6); break;           \
+        case 7: VCOMB(R, 7); break;           \
+        case 8: VCOMB(R, 8); break;           \
+        default: VCOMB(1, VC_MAXOUT); break;  \
+    }
     // accumulators sized for the outputs at hand (r = V s and up to 16 shifts)
     if (r2) {
-        if (nout <= 4) VCOMB(f32 ? 2 : 1, 4);
-        else if (nout <= 8) VCOMB(f32 ? 2 : 1, 8);
-        else VCOMB(1, VC_MAXOUT);
+        VCOMB_ALL(f32 ? 2 : 1)
     } else {
-        if (nout <= 4) VCOMB(1, 4);
-        else if (nout <= 8) VCOMB(1, 8);
-        else VCOMB(1, VC_MAXOUT);
+        VCOMB_ALL(1)
     }
+#undef VCOMB_ALL
 #undef VCOMB
 }
 
