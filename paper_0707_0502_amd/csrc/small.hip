@@ -232,13 +232,26 @@ __device__ __forceinline__ void rot_row_seq(double2* M, int r, int k0, int k1, c
     AT(M, r, k1) = a;
 }
 
-// Complex Schur form of the upper Hessenberg T by single-shift QR with
-// Wilkinson shifts; Z accumulates. During a bulge-chase sweep only the row
-// updates and the column updates of the 4-row window around the bulge are
-// applied at once; the column updates of the rows above the window and the
-// updates of Z are applied after the sweep, row by row in rotation order
-// (left and right rotations commute, so the result is the same similarity).
-// Returns 0 on success.
+// value of v in lane l (l uniform), through scalar registers
+__device__ __forceinline__ double rlane(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double2 rlane2(double2 v, int l) { return mk(rlane(v.x, l), rlane(v.y, l)); }
+
+// Complex Schur form of the upper Hessenberg T (nn <= 64) by single-shift QR
+// with Wilkinson shifts; Z accumulates. A bulge-chase sweep runs one lane per
+// column: lane c carries the current value of its column in the row being
+// rotated, applies each left rotation to it (writing the finished upper row)
+// and reads the next row's value, so the sweep needs no LDS round trip or
+// barrier between rotations. A right rotation kk is applied at once only to
+// rows kk+1 and kk+2 (the values the next rotations are computed from, taken
+// from lanes kk and kk+1); its updates of the rows above and of Z follow
+// after the sweep, row by row in rotation order (left and right rotations
+// commute, and every entry receives its rotations of each side in order, so
+// the result is the same similarity). Returns 0 on success.
 __device__ int schur(double2* T, double2* Z, int nn, double* rc, double2* rs, long long* nrot) {
     const int lane = threadIdx.x;
     const double eps = 2.220446049250313e-16;
@@ -278,15 +291,12 @@ __device__ int schur(double2* T, double2* Z, int nn, double* rc, double2* rs, lo
             const double2 e1 = cadd(mid, sq), e2 = csub(mid, sq);
             mu = cabs(csub(e1, d)) <= cabs(csub(e2, d)) ? e1 : e2;
         }
-        for (int kk = lo; kk < hi; ++kk) {
-            double2 x, y;
-            if (kk == lo) {
-                x = csub(AT(T, lo, lo), mu);
-                y = AT(T, lo + 1, lo);
-            } else {
-                x = AT(T, kk, kk - 1);
-                y = AT(T, kk + 1, kk - 1);
-            }
+        const int col = lane;
+        const bool incol = col < nn && col >= lo;
+        double2 carry = incol ? AT(T, lo, col) : mk(0, 0);   // row kk of column col
+        double2 nxt = incol ? AT(T, lo + 1, col) : mk(0, 0);   // row kk+1 of column col
+        double2 x = csub(AT(T, lo, lo), mu), y = AT(T, lo + 1, lo);
+        for (int kk = __builtin_amdgcn_readfirstlane(lo); kk < hi; ++kk) {
             double c;
             double2 sv;
             givens_fast(x, y, c, sv);
@@ -294,30 +304,36 @@ __device__ int schur(double2* T, double2* Z, int nn, double* rc, double2* rs, lo
                 rc[kk] = c;
                 rs[kk] = sv;
             }
-            // full row update (lanes = columns); the annihilated bulge entry
-            // is stored as an exact zero
-            const int c0 = kk > lo ? kk - 1 : lo;
-            for (int col = c0 + lane; col < nn; col += 64) {
-                const double2 a = AT(T, kk, col), b = AT(T, kk + 1, col);
+            // row kk+2 is untouched so far: its subdiagonal entry and the
+            // values of the columns right of it
+            const bool two = kk + 2 <= hi;
+            const double2 b2 = two ? AT(T, kk + 2, kk + 1) : mk(0, 0);
+            const double2 pre = (two && col < nn && col >= kk + 2) ? AT(T, kk + 2, col) : mk(0, 0);
+            // left rotation of rows kk, kk+1 (columns from kk-1; the
+            // annihilated bulge entry becomes an exact zero)
+            if (incol && col >= kk - 1) {
+                const double2 a = carry, b = nxt;
                 AT(T, kk, col) = cadd(cscale(a, c), cmul(sv, b));
-                AT(T, kk + 1, col) = (kk > lo && col == kk - 1) ? mk(0, 0) : csub(cscale(b, c), cjmul(sv, a));
+                carry = (kk > lo && col == kk - 1) ? mk(0, 0) : csub(cscale(b, c), cjmul(sv, a));
             }
-            wsync();
-            // column update of the window rows max(lo, kk-1) .. min(kk+2, hi)
-            const int r0 = kk - 1 > lo ? kk - 1 : lo;
-            const int r1 = min(kk + 3, hi + 1);
-            if (lane < r1 - r0) {
-                const int r = r0 + lane;
-                const double2 a = AT(T, r, kk), b = AT(T, r, kk + 1);
-                AT(T, r, kk) = cadd(cscale(a, c), cjmul(sv, b));
-                AT(T, r, kk + 1) = csub(cscale(b, c), cmul(sv, a));
-            }
-            wsync();
+            // right rotation of columns kk, kk+1 in rows kk+1 (lanes kk, kk+1)
+            // and kk+2 (zero and the subdiagonal entry: the new bulge)
+            const double2 u = rlane2(carry, kk), v = rlane2(carry, kk + 1);
+            const double2 u2 = cadd(cscale(u, c), cjmul(sv, v));
+            const double2 v2 = csub(cscale(v, c), cmul(sv, u));
+            const double2 bulge = cjmul(sv, b2), w2 = cscale(b2, c);
+            if (col == kk) carry = u2;
+            if (col == kk + 1) carry = v2;
+            nxt = col == kk ? bulge : (col == kk + 1 ? w2 : pre);
+            x = u2;
+            y = bulge;
         }
-        // deferred column updates: row r < lo takes every rotation of the
-        // sweep, row r in [lo, hi] the rotations kk >= r + 2
+        if (incol) AT(T, min(col + 2, hi), col) = carry;
+        wsync();
+        // deferred right rotations: row r < lo takes every rotation of the
+        // sweep, row r in [lo, hi] the rotations kk >= r
         if (nrot && lane == 0) *nrot += hi - lo;
-        for (int r = lane; r <= hi; r += 64) rot_row_seq(T, r, r < lo ? lo : r + 2, hi, rc, rs);
+        for (int r = lane; r <= hi; r += 64) rot_row_seq(T, r, r < lo ? lo : r, hi, rc, rs);
         for (int r = lane; r < nn; r += 64) rot_row_seq(Z, r, lo, hi, rc, rs);
         wsync();
         ++iter;
