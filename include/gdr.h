@@ -196,10 +196,12 @@ typedef struct {
                           GDR_ERR_BREAKDOWN. */
     int sstep;         /* FP32 Arnoldi of the mixed path: 0 or 1 one vector per step (delayed
                           classical Gram-Schmidt twice, two sweeps over the basis per step);
-                          2..4 blocks of sstep vectors (powers of (A - c)/r on a disc holding
-                          the spectrum, block Gram-Schmidt twice and a Cholesky factor: four
-                          sweeps per block). Same Krylov space and Arnoldi relation; the FP64
-                          path always takes one vector per step. */
+                          2..8 blocks of sstep vectors (powers of (A - c)/r on a disc holding
+                          the spectrum, block Gram-Schmidt with a Cholesky factor: two sweeps
+                          per block, four when the second pair runs; blocks of 5..8 take the
+                          FP64 matrix-core sweeps and need an operator size divisible by 16,
+                          else blocks of 4 are used). Same Krylov space and Arnoldi relation;
+                          the FP64 path always takes one vector per step. */
     double sstep_reorth; /* s-step blocks: one projection and one update sweep per block unless
                           the projection removed more than this ratio of a block vector's norm
                           squared (its FP32 rounding would then leave components along the
@@ -227,7 +229,7 @@ typedef struct {
 
 /* Fill defaults: m_dr 40, k 15, m_proj 40, tol 1e-8, tol_extra sqrt(tol),
  * max_cycles 1000, FP64, batch 1, related 0, max_refine 8, profile 0, m_clean 0,
- * proj_k 0, use_graph 0, galerkin 0, sstep 4, sstep_reorth 20, refine_floor 0,
+ * proj_k 0, use_graph 0, galerkin 0, sstep 8, sstep_reorth 20, refine_floor 0,
  * persistent 0. */
 void gdr_params_default(gdr_params* p);
 

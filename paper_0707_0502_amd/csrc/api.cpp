@@ -64,7 +64,7 @@ bool check_params(gdr_ctx_s* c, const gdr_params* p, int ns, bool need_dr) {
         return false;
     }
     if (p->sstep < 0 || p->sstep > BLK_MAX) {
-        c->err = "need 0 <= sstep <= 4";
+        c->err = "need 0 <= sstep <= 8";
         return false;
     }
     if (!(p->sstep_reorth >= 0)) {
@@ -256,7 +256,7 @@ void gdr_params_default(gdr_params* p) {
     p->proj_k = 0;
     p->use_graph = 0;
     p->galerkin = 0;
-    p->sstep = 4;
+    p->sstep = 8;
     p->sstep_reorth = 20;
     p->refine_floor = 0;
     p->persistent = 0;

@@ -569,12 +569,218 @@ __global__ __launch_bounds__(256) void k_blk_update(
     }
 }
 
+// Blocks of 5..8 vectors (FP32 basis) on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64: A[i][k] from lane i + 16k, B[k][j] from lane
+// j + 16k; register v of lane l holds D[l / 16 + 4v][l % 16]). With 16 FP64
+// accumulators per lane the VALU sweeps above take two basis columns per
+// pass at this width and re-read the block for every pair; the matrix cores
+// keep the sums of all columns in 16 x 16 tiles spread over the wavefront,
+// so every row of the basis and of the block is read once. Complex products
+// are real ones over (real, imaginary) pairs: sum_k conj(v) x is
+// (vr xr + vi xi) + i (vr xi - vi xr). The FP32 entries convert exactly, so
+// the products are FP64 throughout, as in the VALU sweeps (sums in another
+// order). n must be a multiple of 16 (16-row chunks).
+typedef double d4v __attribute__((ext_vector_type(4)));
+constexpr int B8_MT = (MAXM + 1 + 15) / 16;   // column tiles of a projection sweep
+
+__device__ __forceinline__ d4v mfma64(double a, double b, d4v c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Projection sweep G[c][a] = sum_rows conj(V_c) X_a, c < nc, a < nx <= 8:
+// M = basis columns (16 per tile), N = (a, re/im), K = (row, re/im). A
+// wavefront takes 16-row chunks of its block's rows (lane group lg = lane / 16
+// holds rows 4lg..4lg+3 of the chunk); the four wavefronts' tiles are summed
+// in LDS into the block's partial sums (same layout as k_blk_dot).
+template <bool SECOND>
+__global__ __launch_bounds__(256) void k_blk_dot8(const float2* __restrict__ V, int64_t ldv,
+                                                  int64_t v_ms, int nc, const float2* __restrict__ X,
+                                                  int64_t ldx, int64_t x_ms, int nx,
+                                                  double2* __restrict__ partial, int nblk, int64_t n,
+                                                  const int* __restrict__ act) {
+    const int mem = blockIdx.y;
+    if (act && !act[mem]) return;
+    V += mem * v_ms;
+    X += mem * x_ms;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int64_t per = ((n + nblk - 1) / nblk + 63) / 64 * 64;
+    const int64_t r0 = (int64_t)blockIdx.x * per;
+    const int64_t r1 = r0 + per < n ? r0 + per : n;
+    const int nmt = (nc + 15) >> 4;
+    const int xa = li >> 1, xc = li & 1;   // block vector and part of this lane's N column
+    const float2* xp = X + (int64_t)(xa < nx ? xa : 0) * ldx;
+    d4v acc[B8_MT];
+#pragma unroll
+    for (int tm = 0; tm < B8_MT; ++tm) acc[tm] = d4v{0, 0, 0, 0};
+    for (int64_t row0 = r0 + 16 * wv; row0 < r1; row0 += 64) {
+        const int64_t rr = row0 + 4 * lg;
+        f4v x01 = {0, 0, 0, 0}, x23 = {0, 0, 0, 0};
+        if (xa < nx) {
+            x01 = *(const f4v*)(xp + rr);
+            x23 = *(const f4v*)(xp + rr + 2);
+        }
+        const float xs[8] = {x01.x, x01.y, x01.z, x01.w, x23.x, x23.y, x23.z, x23.w};
+        double bop[8];   // K entry (row t = u / 2, part u % 2) of N column (xa, xc)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const float xr = xs[2 * (u >> 1)], xi = xs[2 * (u >> 1) + 1];
+            bop[u] = (u & 1) == 0 ? (xc == 0 ? xr : xi) : (xc == 0 ? xi : -xr);
+        }
+        float vs[B8_MT][8];
+#pragma unroll
+        for (int tm = 0; tm < B8_MT; ++tm) {
+            const int c = tm * 16 + li;
+            f4v v01 = {0, 0, 0, 0}, v23 = {0, 0, 0, 0};
+            if (tm < nmt && c < nc) {
+                const float2* vp = V + (int64_t)c * ldv + rr;
+                v01 = __builtin_nontemporal_load((const f4v*)vp);
+                v23 = __builtin_nontemporal_load((const f4v*)(vp + 2));
+            }
+            vs[tm][0] = v01.x;
+            vs[tm][1] = v01.y;
+            vs[tm][2] = v01.z;
+            vs[tm][3] = v01.w;
+            vs[tm][4] = v23.x;
+            vs[tm][5] = v23.y;
+            vs[tm][6] = v23.z;
+            vs[tm][7] = v23.w;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int tm = 0; tm < B8_MT; ++tm)
+                if (tm < nmt) acc[tm] = mfma64(vs[tm][u], bop[u], acc[tm]);
+    }
+    __shared__ double red[4][B8_MT][16][16];
+#pragma unroll
+    for (int tm = 0; tm < B8_MT; ++tm)
+        if (tm < nmt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) red[wv][tm][lg + 4 * v][li] = acc[tm][v];
+    __syncthreads();
+    double2* pout = partial + (int64_t)mem * nx * nc * nblk + blockIdx.x;
+    for (int e = threadIdx.x; e < nmt * 128; e += 256) {
+        const int tm = e >> 7, i = (e >> 3) & 15, a = e & 7;
+        const int c = tm * 16 + i;
+        if (c < nc && a < nx) {
+            double re = 0, im = 0;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                re += red[w][tm][i][2 * a];
+                im += red[w][tm][i][2 * a + 1];
+            }
+            pout[(int64_t)(a * nc + c) * nblk] = mk(re, im);
+        }
+    }
+}
+
+// Update sweep X_q <- sum_a bt[q][a] X_a - sum_c V_c cf[q][c], q < nx <= 8
+// (coefficients as in k_blk_update): M = outputs (q, re/im), N = rows (16 per
+// tile), K = (input, re/im) over the inputs V_0..V_{nc-1}, X_0..X_{nx-1}. An
+// MFMA pair (t, p) takes inputs 4t..4t+3 (lane group lg = lane / 16 supplies
+// input 4t + lg) with their real parts (p = 0) and imaginary parts (p = 1), so
+// a lane loads whole complex entries and feeds each to two MFMAs. The
+// coefficient operand of lane position l and pair (t, p) is the same in every
+// wavefront: staged once per block in LDS. A wavefront takes four 16-row tiles
+// at a time. Lane l ends with output lg + 4v of row l % 16: lanes of even and
+// odd lg pair up into complex results, stored as 128-byte runs per column.
+constexpr int B8_T2 = (MAXM + 1 + 8 + 3) / 4;   // input quads of an update sweep
+template <bool SECOND>
+__global__ __launch_bounds__(256) void k_blk_update8(const float2* __restrict__ V, int64_t ldv,
+                                                     int64_t v_ms, int nc, float2* X, int64_t ldx,
+                                                     int64_t x_ms, int nx,
+                                                     const double2* __restrict__ coef,
+                                                     int64_t coef_ms, int64_t n,
+                                                     const int* __restrict__ act) {
+    const int mem = blockIdx.y;
+    if (act && !act[mem]) return;
+    V += mem * v_ms;
+    X += mem * x_ms;
+    coef += mem * coef_ms;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int nin = nc + nx, T2 = (nin + 3) >> 2;
+    __shared__ double aop[B8_T2][2][64];
+    for (int e = threadIdx.x; e < T2 * 128; e += 256) {
+        const int t = e >> 7, pt = (e >> 6) & 1, l = e & 63;
+        const int q = (l & 15) >> 1, comp = l & 1, inp = 4 * t + (l >> 4);
+        double2 w = mk(0, 0);
+        if (q < nx && inp < nin)
+            w = inp < nc ? cscale(coef[q * (MAXM + 1) + inp], -1.0)
+                         : coef[BLK_MAX * (MAXM + 1) + q * BLK_MAX + (inp - nc)];
+        aop[t][pt][l] = comp == 0 ? (pt == 0 ? w.x : -w.y) : (pt == 0 ? w.y : w.x);
+    }
+    __syncthreads();
+    for (int64_t rb = ((int64_t)blockIdx.x * 4 + wv) * 64; rb < n; rb += (int64_t)gridDim.x * 256) {
+        d4v d[4];
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) d[rt] = d4v{0, 0, 0, 0};
+        // rows of this lane in the four tiles (those past n, in the last
+        // chunk, read row n - 16 + li and are not stored)
+        int64_t rows[4];
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) {
+            const int64_t row = rb + rt * 16 + li;
+            rows[rt] = row < n ? row : n - 16 + li;
+        }
+        // four input quads per round: every load issued before the MFMAs, none
+        // in a branch (an input past the last reads column 0 with coefficient 0)
+        for (int t0 = 0; t0 < T2; t0 += 4) {
+            float2 xv[4][4];
+            double a0[4], a1[4];
+#pragma unroll
+            for (int tt = 0; tt < 4; ++tt) {
+                const int t = t0 + tt;
+                const int inp = 4 * t + lg;
+                const bool on = t < T2 && inp < nin;
+                const float2* col = !on ? V : inp < nc ? V + (int64_t)inp * ldv : X + (int64_t)(inp - nc) * ldx;
+#pragma unroll
+                for (int rt = 0; rt < 4; ++rt) xv[tt][rt] = col[rows[rt]];
+                const int ts = t < B8_T2 ? t : B8_T2 - 1;
+                a0[tt] = t < T2 ? aop[ts][0][lane] : 0.0;
+                a1[tt] = t < T2 ? aop[ts][1][lane] : 0.0;
+            }
+#pragma unroll
+            for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+                for (int rt = 0; rt < 4; ++rt) {
+                    d[rt] = mfma64(a0[tt], xv[tt][rt].x, d[rt]);
+                    d[rt] = mfma64(a1[tt], xv[tt][rt].y, d[rt]);
+                }
+        }
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const double im = __shfl_down(d[rt][v], 16, 64);
+                const int qo = (lg >> 1) + 2 * v;
+                const int64_t row = rb + rt * 16 + li;
+                if ((lg & 1) == 0 && qo < nx && row < n)
+                    X[(int64_t)qo * ldx + row] = make_float2((float)d[rt][v], (float)im);
+            }
+    }
+}
+
 template <typename T>
 void blk_dot(const typename CT<T>::t* V, int64_t ldv, int64_t v_ms, int nc,
              const typename CT<T>::t* X, int64_t ldx, int64_t x_ms, int nx, double2* partial,
              int nblk, int64_t n, int nmem, hipStream_t st, const int* act, bool second) {
     dim3 grid(nblk, nmem), blk(256);
     constexpr bool f32 = std::is_same<T, float>::value;
+    if (nx > 4) {
+        if (!f32 || n % 16 != 0 || nx > 8 || (nc + 15) / 16 > B8_MT)
+            throw std::runtime_error("blk_dot: blocks of 5..8 need FP32, n % 16 == 0 and nc <= MAXM + 1");
+        const float2* Vf = (const float2*)V;
+        const float2* Xf = (const float2*)X;
+        if (second)
+            hipLaunchKernelGGL(k_blk_dot8<true>, grid, blk, 0, st, Vf, ldv, v_ms, nc, Xf, ldx, x_ms, nx,
+                               partial, nblk, n, act);
+        else
+            hipLaunchKernelGGL(k_blk_dot8<false>, grid, blk, 0, st, Vf, ldv, v_ms, nc, Xf, ldx, x_ms, nx,
+                               partial, nblk, n, act);
+        return;
+    }
     const bool r2 = f32 && pairable(n, {ldv, v_ms, ldx, x_ms}, {V, X});
 #define BLK_DOT(NX, R)                                                                          \
     do {                                                                                        \
@@ -610,6 +816,19 @@ void blk_update(const typename CT<T>::t* V, int64_t ldv, int64_t v_ms, int nc,
     // tuned blocks per member (identical results: rows are independent)
     TuneScope ts("blk_update", sweep_shape(n, nmem, nx, r2), SWEEP_NCAND, 0, st, nc + 2 * nx);
     dim3 grid(sweep_nblk(n, nmem, f32, ts.choice()), nmem), blk(256);
+    if (nx > 4) {
+        if (!f32 || n % 16 != 0 || nx > 8 || (nc + nx + 3) / 4 > B8_T2)
+            throw std::runtime_error("blk_update: blocks of 5..8 need FP32, n % 16 == 0 and nc <= MAXM");
+        const float2* Vf = (const float2*)V;
+        float2* Xf = (float2*)X;
+        if (second)
+            hipLaunchKernelGGL(k_blk_update8<true>, grid, blk, 0, st, Vf, ldv, v_ms, nc, Xf, ldx, x_ms, nx,
+                               coef, coef_ms, n, act);
+        else
+            hipLaunchKernelGGL(k_blk_update8<false>, grid, blk, 0, st, Vf, ldv, v_ms, nc, Xf, ldx, x_ms, nx,
+                               coef, coef_ms, n, act);
+        return;
+    }
 #define BLK_UPD(NB, R)                                                                         \
     do {                                                                                       \
         if (second)                                                                            \

@@ -97,7 +97,7 @@ template <> __device__ __forceinline__ float2 from_d<float>(double2 a) {
 // Small sizes
 constexpr int MAXM = 64;     // max restart length m
 constexpr int MAXNS = 16;    // max shifts
-constexpr int BLK_MAX = 4;   // max block of the s-step Arnoldi cycle
+constexpr int BLK_MAX = 8;   // max block of the s-step Arnoldi cycle
 // block update coefficients per member: coef[o*(MAXM+1) + c], beta[o][a] after them
 constexpr int BLK_COEF_MS = BLK_MAX * (MAXM + 1) + BLK_MAX * BLK_MAX;
 constexpr int MAXK = 63;

@@ -266,6 +266,8 @@ struct Arnoldi {
     // Block size of the cycle: s-step blocks only for the FP32 basis
     void set_block(int s, double reorth_ = 20) {
         sblk = (std::is_same<T, float>::value && s >= 2) ? std::min(s, BLK_MAX) : 0;
+        // blocks of more than 4 run on the matrix-core sweeps, in 16-row chunks
+        if (sblk > 4 && n % 16 != 0) sblk = 4;
         reorth = reorth_;
     }
 

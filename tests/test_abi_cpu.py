@@ -66,7 +66,7 @@ def test_params_default_host_only():
     p = gdr.gdr_params_default()
     assert (p.m_dr, p.k, p.m_proj, p.precision, p.batch, p.profile) == (40, 15, 40, gdr.GDR_PREC_F64, 1, 0)
     assert p.tol == 1e-8 and p.tol_extra == 0
-    assert (p.proj_k, p.use_graph, p.galerkin, p.sstep, p.sstep_reorth) == (0, 0, 0, 4, 20.0)
+    assert (p.proj_k, p.use_graph, p.galerkin, p.sstep, p.sstep_reorth) == (0, 0, 0, 8, 20.0)
     assert p.refine_floor == 0.0
 
 

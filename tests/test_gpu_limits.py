@@ -71,7 +71,7 @@ def test_m64_16_shifts_fp64_parity(c1_two_rhs):
 
 @pytest.mark.parametrize("k", [30, 63])
 def test_m64_16_shifts_mixed(c1_two_rhs, k):
-    """The same limits in mixed precision (s-step blocks of 4 across the
+    """The same limits in mixed precision (s-step blocks of 8 across the
     whole 64-column basis), k = 30 and k = m - 1 = 63: every true FP64
     residual at most 1e-8."""
     from paper_0707_0502_amd import gdr

@@ -276,7 +276,7 @@ def test_solver_argument_errors(c1):
     op = make_op(links, kappa)
     x = empty(len(sig) * op.n)
     for bad in (dict(m_dr=10, k=10), dict(m_dr=70, k=5), dict(m_proj=0), dict(tol=0.0),
-                dict(precision=5), dict(sstep=5), dict(sstep_reorth=-1.0),
+                dict(precision=5), dict(sstep=9), dict(sstep_reorth=-1.0),
                 dict(refine_floor=0.7), dict(refine_floor=-1e-3), dict(m_clean=65)):
         p = params(cfg, gdr.GDR_PREC_F64)
         for k_, v in bad.items():

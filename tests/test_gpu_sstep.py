@@ -1,7 +1,8 @@
 """The s-step Arnoldi cycle of the FP32 path (gdr_params.sstep = block size):
 the deflation pair it hands over satisfies the Arnoldi relation
 A V_k = V_{k+1} H_bar_k and V_{k+1} is orthonormal, both to FP32 accuracy,
-for block sizes 1 (one vector per step), 2, 3 and 4, on the bidiagonal matrix
+for block sizes 1 (one vector per step) to 8 (5..8 on the matrix-core
+sweeps), on the bidiagonal matrix
 and on a Wilson lattice; the mixed solves it drives reach the tolerance."""
 import numpy as np
 import pytest
@@ -12,10 +13,10 @@ from tests.gpu_common import config_data, ctx, dev, empty, host, make_op, say
 pytestmark = pytest.mark.gpu
 
 
-def bidiag_op():
+def bidiag_op(n=1000):
     from paper_0707_0502_amd import gdr
-    d = np.concatenate([[0.1], np.arange(1, 1000)]).astype(np.complex128)
-    e = np.ones(999, np.complex128)
+    d = np.concatenate([[0.1], np.arange(1, n)]).astype(np.complex128)
+    e = np.ones(n - 1, np.complex128)
 
     def mv(v):
         w = d * v
@@ -38,20 +39,22 @@ def relation(gdr, op, defl, mv_host, n):
 
 
 @pytest.mark.parametrize("reorth", [20.0, 0.0])
-@pytest.mark.parametrize("sstep", [1, 2, 3, 4])
+@pytest.mark.parametrize("sstep", [1, 2, 3, 4, 5, 6, 7, 8])
 def test_arnoldi_relation_bidiagonal(sstep, reorth):
     from paper_0707_0502_amd import gdr
-    op, mv = bidiag_op()
-    b = np.random.default_rng(5).standard_normal(1000) + 0j
+    # blocks of more than 4 run on the matrix-core sweeps, which take n % 16 == 0
+    n = 1000 if sstep <= 4 else 1024
+    op, mv = bidiag_op(n)
+    b = np.random.default_rng(5).standard_normal(n) + 0j
     sig = [0, -0.4, -2]
-    x = empty(3 * 1000)
+    x = empty(3 * n)
     st = gdr.Stats(1, 3)
     p = gdr.gdr_params_default(m_dr=25, k=10, tol=1e-6, max_cycles=2, precision=gdr.GDR_PREC_MIXED,
                                sstep=sstep, sstep_reorth=reorth)
     rc, defl = gdr.gdr_solve_dr_sh(op, sig, dev(b), x, p, st)
     say("sstep", sstep, "reorth", reorth, "rc", rc, "hist", st.hist[:, 3])
     assert defl is not None
-    rel, orth = relation(gdr, op, defl, mv, 1000)
+    rel, orth = relation(gdr, op, defl, mv, n)
     say("  A V_k - V_{k+1} H_k rel %.3e, orthonormality %.3e" % (rel, orth))
     assert rel <= 1e-5 and orth <= 1e-5
     gdr.gdr_defl_destroy(defl)
@@ -59,7 +62,7 @@ def test_arnoldi_relation_bidiagonal(sstep, reorth):
 
 
 @pytest.mark.parametrize("reorth", [20.0, 0.0])
-@pytest.mark.parametrize("sstep", [1, 4])
+@pytest.mark.parametrize("sstep", [1, 4, 6, 8])
 def test_arnoldi_relation_wilson(sstep, reorth):
     from paper_0707_0502_amd import gdr
     cfg, links, kappa, B = config_data("C1")
