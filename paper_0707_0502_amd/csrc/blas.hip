@@ -590,7 +590,7 @@ __device__ __forceinline__ d4v mfma64(double a, double b, d4v c) {
 // Projection sweep G[c][a] = sum_rows conj(V_c) X_a, c < nc, a < nx <= 8:
 // M = basis columns (16 per tile), N = (a, re/im), K = (row, re/im). A
 // wavefront takes 16-row chunks of its block's rows (lane group lg = lane / 16
-// holds rows 4lg..4lg+3 of the chunk); the four wavefronts' tiles are summed
+// holds four rows of the chunk); the four wavefronts' tiles are summed
 // in LDS into the block's partial sums (same layout as k_blk_dot).
 template <bool SECOND>
 __global__ __launch_bounds__(256) void k_blk_dot8(const float2* __restrict__ V, int64_t ldv,
@@ -614,11 +614,13 @@ __global__ __launch_bounds__(256) void k_blk_dot8(const float2* __restrict__ V, 
 #pragma unroll
     for (int tm = 0; tm < B8_MT; ++tm) acc[tm] = d4v{0, 0, 0, 0};
     for (int64_t row0 = r0 + 16 * wv; row0 < r1; row0 += 64) {
-        const int64_t rr = row0 + 4 * lg;
+        // rows of lane group lg: 2lg, 2lg+1 and 8+2lg, 9+2lg of the chunk, so
+        // each 16-byte load of the four groups covers 64 contiguous bytes
+        const int64_t ra = row0 + 2 * lg, rb8 = row0 + 8 + 2 * lg;
         f4v x01 = {0, 0, 0, 0}, x23 = {0, 0, 0, 0};
         if (xa < nx) {
-            x01 = *(const f4v*)(xp + rr);
-            x23 = *(const f4v*)(xp + rr + 2);
+            x01 = *(const f4v*)(xp + ra);
+            x23 = *(const f4v*)(xp + rb8);
         }
         const float xs[8] = {x01.x, x01.y, x01.z, x01.w, x23.x, x23.y, x23.z, x23.w};
         double bop[8];   // K entry (row t = u / 2, part u % 2) of N column (xa, xc)
@@ -633,9 +635,9 @@ __global__ __launch_bounds__(256) void k_blk_dot8(const float2* __restrict__ V, 
             const int c = tm * 16 + li;
             f4v v01 = {0, 0, 0, 0}, v23 = {0, 0, 0, 0};
             if (tm < nmt && c < nc) {
-                const float2* vp = V + (int64_t)c * ldv + rr;
-                v01 = __builtin_nontemporal_load((const f4v*)vp);
-                v23 = __builtin_nontemporal_load((const f4v*)(vp + 2));
+                const float2* vp = V + (int64_t)c * ldv;
+                v01 = __builtin_nontemporal_load((const f4v*)(vp + ra));
+                v23 = __builtin_nontemporal_load((const f4v*)(vp + rb8));
             }
             vs[tm][0] = v01.x;
             vs[tm][1] = v01.y;
