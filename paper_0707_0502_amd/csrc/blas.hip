@@ -726,13 +726,14 @@ __global__ __launch_bounds__(256) void k_blk_update8(const float2* __restrict__ 
             const int64_t row = rb + rt * 16 + li;
             rows[rt] = row < n ? row : n - 16 + li;
         }
-        // four input quads per round: every load issued before the MFMAs, none
-        // in a branch (an input past the last reads column 0 with coefficient 0)
-        for (int t0 = 0; t0 < T2; t0 += 4) {
-            float2 xv[4][4];
-            double a0[4], a1[4];
+        // two input quads per round (four measured 2 % slower: two waves per
+        // SIMD instead of four): every load issued before the MFMAs, none in a
+        // branch (an input past the last reads column 0 with coefficient 0)
+        for (int t0 = 0; t0 < T2; t0 += 2) {
+            float2 xv[2][4];
+            double a0[2], a1[2];
 #pragma unroll
-            for (int tt = 0; tt < 4; ++tt) {
+            for (int tt = 0; tt < 2; ++tt) {
                 const int t = t0 + tt;
                 const int inp = 4 * t + lg;
                 const bool on = t < T2 && inp < nin;
@@ -744,7 +745,7 @@ __global__ __launch_bounds__(256) void k_blk_update8(const float2* __restrict__ 
                 a1[tt] = t < T2 ? aop[ts][1][lane] : 0.0;
             }
 #pragma unroll
-            for (int tt = 0; tt < 4; ++tt)
+            for (int tt = 0; tt < 2; ++tt)
 #pragma unroll
                 for (int rt = 0; rt < 4; ++rt) {
                     d[rt] = mfma64(a0[tt], xv[tt][rt].x, d[rt]);
