@@ -319,20 +319,6 @@ __global__ __launch_bounds__(512) void k_shared_dot(
     }
 }
 
-template <typename T, typename TX>
-void shared_dot(const typename CT<T>::t* V, int64_t ldv, int nc, const typename CT<TX>::t* x,
-                int64_t x_ms, double2* partial, int nblk, int64_t n, int nmem, hipStream_t st,
-                const int* act) {
-    if (nc < 1 || nc > SHARED_NC_MAX) throw std::invalid_argument("shared_dot: nc out of range");
-    dim3 grid(nblk, (nmem + SHARED_MG - 1) / SHARED_MG), blk(512);
-    hipLaunchKernelGGL((k_shared_dot<T, TX>), grid, blk, 0, st, V, ldv, nc, x, x_ms, partial,
-                       nblk, n, nmem, act);
-}
-
-template void shared_dot<float, double>(const float2*, int64_t, int, const double2*, int64_t,
-                                        double2*, int, int64_t, int, hipStream_t, const int*);
-template void shared_dot<double, double>(const double2*, int64_t, int, const double2*, int64_t,
-                                         double2*, int, int64_t, int, hipStream_t, const int*);
 
 // k_gs_update: one sweep forms NO outputs
 //   y_o = sum_a beta[o][a] x_a - sum_{c<nc} V_c coef[o][c]
@@ -676,6 +662,172 @@ __global__ __launch_bounds__(256) void k_blk_dot8(const float2* __restrict__ V, 
         }
     }
 }
+
+// Batched projection on one shared basis, G[c][b] = sum_rows conj(V_c) X_b
+// for c < nc <= 32 (FP32 basis) and FP64 member vectors X_b, on the FP64
+// matrix cores: M = basis columns (two tiles of 16), N = (member, re/im)
+// with eight members per tile and two tiles per block, K = (row, re/im), in
+// the 16-row chunks of k_blk_dot8. A block takes gs_dot's row range for 16
+// members, so every basis row is read once for all of them (the VALU form
+// reads it once per group of SHARED_MG members); ||X_b||^2 is summed on the
+// VALU from the same loads. Partial sums in gs_dot's layout, column nc the
+// squared norm. n must be a multiple of 16.
+constexpr int SD8_MEM = 16;
+static_assert(SHARED_NC_MAX <= 32, "k_shared_dot8 holds two column tiles");
+
+__global__ __launch_bounds__(256) void k_shared_dot8(const float2* __restrict__ V, int64_t ldv,
+                                                     int nc, const double2* __restrict__ X,
+                                                     int64_t x_ms, double2* __restrict__ partial,
+                                                     int nblk, int64_t n, int nmem,
+                                                     const int* __restrict__ act) {
+    const int g0 = blockIdx.y * SD8_MEM;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int xa = li >> 1, xc = li & 1;   // member (in its tile) and part of this lane's N column
+    // per N tile: any member active (uniform), its first active member, and
+    // this lane's member; an inactive lane reads the first active member's
+    // rows (same cache lines as that lane) and uses zeros
+    bool ton[2], mon[2];
+    const double2* xp[2];
+    bool any = false;
+#pragma unroll
+    for (int tn = 0; tn < 2; ++tn) {
+        int first = -1;
+        for (int a = 7; a >= 0; --a) {
+            const int m = g0 + tn * 8 + a;
+            if (m < nmem && (!act || act[m])) first = m;
+        }
+        ton[tn] = first >= 0;
+        any = any || ton[tn];
+        const int m = g0 + tn * 8 + xa;
+        mon[tn] = m < nmem && (!act || act[m]);
+        xp[tn] = X + (int64_t)(mon[tn] ? m : (first >= 0 ? first : g0)) * x_ms;
+    }
+    if (!any) return;   // uniform over the block
+    const int64_t per = ((n + nblk - 1) / nblk + 63) / 64 * 64;
+    const int64_t r0 = (int64_t)blockIdx.x * per;
+    const int64_t r1 = r0 + per < n ? r0 + per : n;
+    const int nmt = (nc + 15) >> 4;
+    d4v acc[2][2];
+#pragma unroll
+    for (int tm = 0; tm < 2; ++tm)
+#pragma unroll
+        for (int tn = 0; tn < 2; ++tn) acc[tm][tn] = d4v{0, 0, 0, 0};
+    double s2[2] = {0, 0};
+    for (int64_t row0 = r0 + 16 * wv; row0 < r1; row0 += 64) {
+        // rows of lane group lg: 2lg, 2lg+1, 8+2lg, 9+2lg of the chunk
+        const int64_t ra = row0 + 2 * lg, rb8 = row0 + 8 + 2 * lg;
+        double bop[2][8];   // K entry (row u / 2, part u % 2) of N column (xa, xc)
+#pragma unroll
+        for (int tn = 0; tn < 2; ++tn) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) bop[tn][u] = 0;
+            if (ton[tn]) {
+                const double2* p = xp[tn];
+                double2 xv[4] = {p[ra], p[ra + 1], p[rb8], p[rb8 + 1]};
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    xv[t] = csel(mon[tn], xv[t], mk(0, 0));
+                    s2[tn] += xc == 0 ? xv[t].x * xv[t].x + xv[t].y * xv[t].y : 0.0;
+                    bop[tn][2 * t] = xc == 0 ? xv[t].x : xv[t].y;
+                    bop[tn][2 * t + 1] = xc == 0 ? xv[t].y : -xv[t].x;
+                }
+            }
+        }
+        float vs[2][8];
+#pragma unroll
+        for (int tm = 0; tm < 2; ++tm) {
+            const int c = tm * 16 + li;
+            f4v v01 = {0, 0, 0, 0}, v23 = {0, 0, 0, 0};
+            if (tm < nmt) {
+                const float2* vp = V + (int64_t)(c < nc ? c : 0) * ldv;
+                v01 = __builtin_nontemporal_load((const f4v*)(vp + ra));
+                v23 = __builtin_nontemporal_load((const f4v*)(vp + rb8));
+                if (c >= nc) {
+                    v01 = f4v{0, 0, 0, 0};
+                    v23 = f4v{0, 0, 0, 0};
+                }
+            }
+            vs[tm][0] = v01.x;
+            vs[tm][1] = v01.y;
+            vs[tm][2] = v01.z;
+            vs[tm][3] = v01.w;
+            vs[tm][4] = v23.x;
+            vs[tm][5] = v23.y;
+            vs[tm][6] = v23.z;
+            vs[tm][7] = v23.w;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int tm = 0; tm < 2; ++tm)
+                if (tm < nmt)
+#pragma unroll
+                    for (int tn = 0; tn < 2; ++tn)
+                        if (ton[tn]) acc[tm][tn] = mfma64(vs[tm][u], bop[tn][u], acc[tm][tn]);
+    }
+    __shared__ double red[4][2][2][16][16];
+    __shared__ double nrm[4][4][SD8_MEM];
+#pragma unroll
+    for (int tm = 0; tm < 2; ++tm)
+#pragma unroll
+        for (int tn = 0; tn < 2; ++tn)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) red[wv][tm][tn][lg + 4 * v][li] = acc[tm][tn][v];
+    if (xc == 0) {
+        nrm[wv][lg][xa] = s2[0];
+        nrm[wv][lg][8 + xa] = s2[1];
+    }
+    __syncthreads();
+    const int nval = nc + 1;
+    for (int e = threadIdx.x; e < nmt * 16 * SD8_MEM; e += 256) {
+        const int tm = e / (16 * SD8_MEM), i = (e / SD8_MEM) & 15, ml = e % SD8_MEM;
+        const int c = tm * 16 + i, m = g0 + ml;
+        if (c < nc && m < nmem && (!act || act[m])) {
+            double re = 0, im = 0;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                re += red[w][tm][ml >> 3][i][2 * (ml & 7)];
+                im += red[w][tm][ml >> 3][i][2 * (ml & 7) + 1];
+            }
+            partial[((int64_t)m * nval + c) * nblk + blockIdx.x] = mk(re, im);
+        }
+    }
+    if (threadIdx.x < SD8_MEM) {
+        const int m = g0 + threadIdx.x;
+        if (m < nmem && (!act || act[m])) {
+            double t = 0;
+#pragma unroll
+            for (int w = 0; w < 4; ++w)
+#pragma unroll
+                for (int g = 0; g < 4; ++g) t += nrm[w][g][threadIdx.x];
+            partial[((int64_t)m * nval + nc) * nblk + blockIdx.x] = mk(t, 0);
+        }
+    }
+}
+
+template <typename T, typename TX>
+void shared_dot(const typename CT<T>::t* V, int64_t ldv, int nc, const typename CT<TX>::t* x,
+                int64_t x_ms, double2* partial, int nblk, int64_t n, int nmem, hipStream_t st,
+                const int* act) {
+    if (nc < 1 || nc > SHARED_NC_MAX) throw std::invalid_argument("shared_dot: nc out of range");
+    if constexpr (std::is_same<T, float>::value && std::is_same<TX, double>::value) {
+        if (n % 16 == 0) {   // FP32 basis, FP64 members: the matrix-core form
+            dim3 grid(nblk, (nmem + SD8_MEM - 1) / SD8_MEM), blk(256);
+            hipLaunchKernelGGL(k_shared_dot8, grid, blk, 0, st, V, ldv, nc, x, x_ms, partial, nblk,
+                               n, nmem, act);
+            return;
+        }
+    }
+    dim3 grid(nblk, (nmem + SHARED_MG - 1) / SHARED_MG), blk(512);
+    hipLaunchKernelGGL((k_shared_dot<T, TX>), grid, blk, 0, st, V, ldv, nc, x, x_ms, partial,
+                       nblk, n, nmem, act);
+}
+
+template void shared_dot<float, double>(const float2*, int64_t, int, const double2*, int64_t,
+                                        double2*, int, int64_t, int, hipStream_t, const int*);
+template void shared_dot<double, double>(const double2*, int64_t, int, const double2*, int64_t,
+                                         double2*, int, int64_t, int, hipStream_t, const int*);
 
 // Update sweep X_q <- sum_a bt[q][a] X_a - sum_c V_c cf[q][c], q < nx <= 8
 // (coefficients as in k_blk_update): M = outputs (q, re/im), N = rows (16 per
