@@ -1416,14 +1416,14 @@ void vcombine(const typename CT<T>::t* V, int64_t ldv, int64_t v_mstride, int nc
                        dim3(256), 0, st, V, ldv, ncols, coef, ldc, c_mstride, nout, out, o_stride, \
                        o_mstride, keep_mask, n, nmem, act)
         switch (nout) {
-            case 1: VCOMB2(1, 4); break;
-            case 2: VCOMB2(2, 4); break;
+            case 1: VCOMB2(1, 8); break;
+            case 2: VCOMB2(2, 8); break;
             case 3: VCOMB2(3, 4); break;
             case 4: VCOMB2(4, 4); break;
-            case 5: VCOMB2(5, 2); break;
-            case 6: VCOMB2(6, 2); break;
-            case 7: VCOMB2(7, 2); break;
-            default: VCOMB2(8, 2); break;
+            case 5: VCOMB2(5, 4); break;
+            case 6: VCOMB2(6, 4); break;
+            case 7: VCOMB2(7, 4); break;
+            default: VCOMB2(8, 4); break;
         }
 #undef VCOMB2
         return;
