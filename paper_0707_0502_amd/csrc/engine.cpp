@@ -1556,10 +1556,53 @@ int cleanup(gdr_op_s* op, gdr_defl_s* defl, int ns, const double2* sig, int nrhs
     // (with FP16-stored links a floor of 1e-2 saved 5 % of the cleanup
     // products on the 32^3x64 lattice and no time, so one default serves both)
     const double floor_tol = p.refine_floor > 0 ? p.refine_floor : 1e-5;
+    // one refinement batch: up to 16 (RHS, shift) pairs, each solving for the
+    // correction of its solution from its FP64 true residual
+    constexpr int CMAX = 16;
+    struct Pair { int j, i; double res; };
+    DMem cm;
+    double2* Bm = cm.get<double2>((size_t)CMAX * n);
+    double2* W = cm.get<double2>((size_t)CMAX * 2 * n);
+    std::vector<Pair> pend;
+    auto solve_pending = [&]() {
+        const int nmem = (int)pend.size();
+        if (nmem == 0) return;
+        std::vector<double> tol(nmem), bnorm(nmem);
+        std::vector<int> phase(nmem, 8);
+        std::vector<double2> sgm(nmem);
+        for (int b = 0; b < nmem; ++b) {
+            const Pair& q = pend[b];
+            bnorm[b] = q.res * bn[q.j];
+            tol[b] = std::min(0.5, std::max(0.3 * p.tol / q.res, floor_tol));
+            sgm[b] = sig[q.i];
+        }
+        ProjResult Rr;
+        if (defl && defl->prec == GDR_PREC_F64)
+            proj_run<double>(op, defl, nmem, 1, sgm, Bm, W, tol, bnorm, mc, p.max_cycles, S, phase, Rr,
+                             false, 0, p.use_graph != 0);
+        else
+            proj_run<float>(op, defl, nmem, 1, sgm, Bm, W, tol, bnorm, mc, p.max_cycles, S, phase, Rr,
+                            false, 0, p.use_graph != 0, p.sstep, p.sstep_reorth,
+                            /*replace=*/false);
+        for (int b = 0; b < nmem; ++b) {
+            const Pair& q = pend[b];
+            axpy_dev(X_eo + ((int64_t)q.j * ns + q.i) * n, 0, W + (int64_t)b * 2 * n, 0, nullptr, 0, n,
+                     1, st);
+            if (S.st) {
+                S.st->mvp_cleanup += Rr.mvps[b];
+                S.st->cycles_cleanup += Rr.cycles[b];
+            }
+        }
+        HIPCHK(hipStreamSynchronize(st));
+        pend.clear();
+    };
     for (int round = 0; round <= p.max_refine && !done; ++round) {
-        // pairs above tolerance
-        struct Pair { int j, i; double res; };
-        std::vector<Pair> todo;
+        // Every pair's FP64 true residual, one right-hand side's shifts per
+        // operator launch. A pair above tolerance takes a copy of its residual
+        // into the next batch slot (the pairs are independent, so a full batch
+        // is solved at once, before the later right-hand sides are checked).
+        const bool solve = round < p.max_refine;
+        int above = 0;
         for (int j = 0; j < nrhs; ++j) {
             residual_vectors(op, ns, sig, B_eo + (int64_t)j * n, X_eo + (int64_t)j * ns * n, R);
             auto rn = norms_of(op, R, ns);
@@ -1569,48 +1612,17 @@ int cleanup(gdr_op_s* op, gdr_defl_s* defl, int ns, const double2* sig, int nrhs
                 if (!std::isfinite(rel))
                     throw GdrError(GDR_ERR_BREAKDOWN, "mixed-precision cleanup: non-finite true residual");
                 if (round == 0 && S.st) S.st->resid_main = std::max(S.st->resid_main, rel);
-                if (!(rel <= p.tol)) todo.push_back({j, i, rel});
+                if (rel <= p.tol) continue;
+                ++above;
+                if (!solve) continue;
+                copy_vec(R + (int64_t)i * n, 0, Bm + (int64_t)pend.size() * n, 0, n, 1, st);
+                pend.push_back({j, i, rel});
+                if ((int)pend.size() == CMAX) solve_pending();
             }
         }
-        if (todo.empty() || round == p.max_refine) {
-            done = todo.empty();
-            break;
-        }
-        for (size_t pos = 0; pos < todo.size(); pos += 16) {
-            const int nmem = (int)std::min<size_t>(16, todo.size() - pos);
-            DMem cm;
-            double2* Bm = cm.get<double2>((size_t)nmem * n);
-            double2* W = cm.get<double2>((size_t)nmem * 2 * n);
-            std::vector<double> tol(nmem), bnorm(nmem);
-            std::vector<int> phase(nmem, 8);
-            std::vector<double2> sgm(nmem);
-            for (int b = 0; b < nmem; ++b) {
-                const Pair& q = todo[pos + b];
-                residual_vectors(op, 1, sig + q.i, B_eo + (int64_t)q.j * n,
-                                 X_eo + ((int64_t)q.j * ns + q.i) * n, Bm + b * n);
-                bnorm[b] = q.res * bn[q.j];
-                tol[b] = std::min(0.5, std::max(0.3 * p.tol / q.res, floor_tol));
-                sgm[b] = sig[q.i];
-            }
-            ProjResult Rr;
-            if (defl && defl->prec == GDR_PREC_F64)
-                proj_run<double>(op, defl, nmem, 1, sgm, Bm, W, tol, bnorm, mc, p.max_cycles, S, phase, Rr,
-                                 false, 0, p.use_graph != 0);
-            else
-                proj_run<float>(op, defl, nmem, 1, sgm, Bm, W, tol, bnorm, mc, p.max_cycles, S, phase, Rr,
-                                false, 0, p.use_graph != 0, p.sstep, p.sstep_reorth,
-                                /*replace=*/false);
-            for (int b = 0; b < nmem; ++b) {
-                const Pair& q = todo[pos + b];
-                axpy_dev(X_eo + ((int64_t)q.j * ns + q.i) * n, 0, W + (int64_t)b * 2 * n, 0,
-                         nullptr, 0, n, 1, st);
-                if (S.st) {
-                    S.st->mvp_cleanup += Rr.mvps[b];
-                    S.st->cycles_cleanup += Rr.cycles[b];
-                }
-            }
-            HIPCHK(hipStreamSynchronize(st));
-        }
+        solve_pending();
+        done = above == 0;
+        if (!solve) break;
     }
     return done ? GDR_OK : GDR_NOT_CONVERGED;
 }
