@@ -217,12 +217,31 @@ __device__ __forceinline__ void wsync() {
 }
 
 // Apply the rotations kk = k0..k1-1 (parameters rc/rs[kk]) to columns
-// kk, kk+1 of row r of M, in order, carrying the running entry.
+// kk, kk+1 of row r of M, in order, carrying the running entry. Runs of 8
+// rotations load their row entries and parameters first: rotation kk reads
+// column kk+1 and writes column kk, so no entry a run reads was written in
+// it, and the loads are not each waited for in turn.
 __device__ __forceinline__ void rot_row_seq(double2* M, int r, int k0, int k1, const double* rc,
                                             const double2* rs) {
     if (k0 >= k1) return;
     double2 a = AT(M, r, k0);
-    for (int kk = k0; kk < k1; ++kk) {
+    int kk = k0;
+    for (; kk + 8 <= k1; kk += 8) {
+        double2 b[8], sv[8];
+        double c[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            b[t] = AT(M, r, kk + 1 + t);
+            c[t] = rc[kk + t];
+            sv[t] = rs[kk + t];
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            AT(M, r, kk + t) = cadd(cscale(a, c[t]), cjmul(sv[t], b[t]));
+            a = csub(cscale(b[t], c[t]), cmul(sv[t], a));
+        }
+    }
+    for (; kk < k1; ++kk) {
         const double2 b = AT(M, r, kk + 1);
         const double c = rc[kk];
         const double2 sv = rs[kk];
@@ -263,13 +282,17 @@ __device__ int schur(double2* T, double2* Z, int nn, double* rc, double2* rs, lo
     int hi = nn - 1, iter = 0, total = 0;
     while (hi > 0) {
         if (total > 60 * nn) return 1;
-        // deflation test on squared magnitudes: |t_{l,l-1}|^2 <= eps^2 (|t_{l-1,l-1}|^2 + |t_{l,l}|^2)
-        int l = hi;
-        for (; l > 0; --l) {
-            double tst = cabs2(AT(T, l - 1, l - 1)) + cabs2(AT(T, l, l));
+        // deflation test on squared magnitudes: |t_{l,l-1}|^2 <= eps^2 (|t_{l-1,l-1}|^2 + |t_{l,l}|^2);
+        // lane l tests subdiagonal entry l, and l is the largest l <= hi that
+        // passes (0 if none)
+        bool negl = false;
+        if (lane >= 1 && lane <= hi) {
+            double tst = cabs2(AT(T, lane - 1, lane - 1)) + cabs2(AT(T, lane, lane));
             if (tst == 0.0) tst = fro * fro;
-            if (cabs2(AT(T, l, l - 1)) <= eps * eps * tst) break;
+            negl = cabs2(AT(T, lane, lane - 1)) <= eps * eps * tst;
         }
+        const unsigned long long bal = __ballot(negl);
+        const int l = bal ? 63 - __clzll((long long)bal) : 0;
         wsync();
         if (l > 0 && lane == 0) AT(T, l, l - 1) = mk(0, 0);
         wsync();
@@ -296,7 +319,16 @@ __device__ int schur(double2* T, double2* Z, int nn, double* rc, double2* rs, lo
         double2 carry = incol ? AT(T, lo, col) : mk(0, 0);   // row kk of column col
         double2 nxt = incol ? AT(T, lo + 1, col) : mk(0, 0);   // row kk+1 of column col
         double2 x = csub(AT(T, lo, lo), mu), y = AT(T, lo + 1, lo);
+        // row kk+2 is untouched until rotation kk+2 (and the right rotations
+        // wait for the end of the sweep): its subdiagonal entry and the values
+        // of the columns right of it are loaded one rotation ahead
+        double2 b2n = lo + 2 <= hi ? AT(T, lo + 2, lo + 1) : mk(0, 0);
+        double2 pren = (lo + 2 <= hi && col < nn && col >= lo + 2) ? AT(T, lo + 2, col) : mk(0, 0);
         for (int kk = __builtin_amdgcn_readfirstlane(lo); kk < hi; ++kk) {
+            const double2 b2 = b2n, pre = pren;
+            const bool three = kk + 3 <= hi;
+            b2n = three ? AT(T, kk + 3, kk + 2) : mk(0, 0);
+            pren = (three && col < nn && col >= kk + 3) ? AT(T, kk + 3, col) : mk(0, 0);
             double c;
             double2 sv;
             givens_fast(x, y, c, sv);
@@ -304,11 +336,6 @@ __device__ int schur(double2* T, double2* Z, int nn, double* rc, double2* rs, lo
                 rc[kk] = c;
                 rs[kk] = sv;
             }
-            // row kk+2 is untouched so far: its subdiagonal entry and the
-            // values of the columns right of it
-            const bool two = kk + 2 <= hi;
-            const double2 b2 = two ? AT(T, kk + 2, kk + 1) : mk(0, 0);
-            const double2 pre = (two && col < nn && col >= kk + 2) ? AT(T, kk + 2, col) : mk(0, 0);
             // left rotation of rows kk, kk+1 (columns from kk-1; the
             // annihilated bulge entry becomes an exact zero)
             if (incol && col >= kk - 1) {
