@@ -579,7 +579,7 @@ __device__ __forceinline__ d4v mfma64(double a, double b, d4v c) {
 // holds four rows of the chunk); the four wavefronts' tiles are summed
 // in LDS into the block's partial sums (same layout as k_blk_dot).
 template <bool SECOND>
-__global__ __launch_bounds__(256) void k_blk_dot8(const float2* __restrict__ V, int64_t ldv,
+__global__ __launch_bounds__(256, 4) void k_blk_dot8(const float2* __restrict__ V, int64_t ldv,
                                                   int64_t v_ms, int nc, const float2* __restrict__ X,
                                                   int64_t ldx, int64_t x_ms, int nx,
                                                   double2* __restrict__ partial, int nblk, int64_t n,
@@ -599,7 +599,10 @@ __global__ __launch_bounds__(256) void k_blk_dot8(const float2* __restrict__ V, 
     d4v acc[B8_MT];
 #pragma unroll
     for (int tm = 0; tm < B8_MT; ++tm) acc[tm] = d4v{0, 0, 0, 0};
-    for (int64_t row0 = r0 + 16 * wv; row0 < r1; row0 += 64) {
+    // loads of one 16-row chunk: the B operand (block entries) and the A
+    // operands of the first NT column tiles
+    auto load = [&](int64_t row0, double (&bop)[8], auto& vs, auto ntc) {
+        constexpr int NT = decltype(ntc)::value;
         // rows of lane group lg: 2lg, 2lg+1 and 8+2lg, 9+2lg of the chunk, so
         // each 16-byte load of the four groups covers 64 contiguous bytes
         const int64_t ra = row0 + 2 * lg, rb8 = row0 + 8 + 2 * lg;
@@ -609,15 +612,14 @@ __global__ __launch_bounds__(256) void k_blk_dot8(const float2* __restrict__ V, 
             x23 = *(const f4v*)(xp + rb8);
         }
         const float xs[8] = {x01.x, x01.y, x01.z, x01.w, x23.x, x23.y, x23.z, x23.w};
-        double bop[8];   // K entry (row t = u / 2, part u % 2) of N column (xa, xc)
+        // K entry (row t = u / 2, part u % 2) of N column (xa, xc)
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const float xr = xs[2 * (u >> 1)], xi = xs[2 * (u >> 1) + 1];
             bop[u] = (u & 1) == 0 ? (xc == 0 ? xr : xi) : (xc == 0 ? xi : -xr);
         }
-        float vs[B8_MT][8];
 #pragma unroll
-        for (int tm = 0; tm < B8_MT; ++tm) {
+        for (int tm = 0; tm < NT; ++tm) {
             const int c = tm * 16 + li;
             f4v v01 = {0, 0, 0, 0}, v23 = {0, 0, 0, 0};
             if (tm < nmt && c < nc) {
@@ -634,11 +636,38 @@ __global__ __launch_bounds__(256) void k_blk_dot8(const float2* __restrict__ V, 
             vs[tm][6] = v23.z;
             vs[tm][7] = v23.w;
         }
+    };
+    auto mma = [&](const double (&bop)[8], const auto& vs, auto ntc) {
+        constexpr int NT = decltype(ntc)::value;
 #pragma unroll
         for (int u = 0; u < 8; ++u)
 #pragma unroll
-            for (int tm = 0; tm < B8_MT; ++tm)
+            for (int tm = 0; tm < NT; ++tm)
                 if (tm < nmt) acc[tm] = mfma64(vs[tm][u], bop[u], acc[tm]);
+    };
+    if (nmt <= 2) {
+        // one or two column tiles: a chunk holds few bytes per wavefront, so
+        // two chunks (64 rows apart, this wavefront's next one) are loaded
+        // before either's MFMAs; each accumulator takes its chunks in the
+        // same order as below
+        using N2 = std::integral_constant<int, 2>;
+        for (int64_t row0 = r0 + 16 * wv; row0 < r1; row0 += 128) {
+            const bool two = row0 + 64 < r1;   // uniform
+            double bopA[8], bopB[8];
+            float vsA[2][8], vsB[2][8];
+            load(row0, bopA, vsA, N2{});
+            load(two ? row0 + 64 : row0, bopB, vsB, N2{});
+            mma(bopA, vsA, N2{});
+            if (two) mma(bopB, vsB, N2{});
+        }
+    } else {
+        using NM = std::integral_constant<int, B8_MT>;
+        for (int64_t row0 = r0 + 16 * wv; row0 < r1; row0 += 64) {
+            double bop[8];
+            float vs[B8_MT][8];
+            load(row0, bop, vs, NM{});
+            mma(bop, vs, NM{});
+        }
     }
     __shared__ double red[4][B8_MT][16][16];
 #pragma unroll
