@@ -84,10 +84,13 @@ void gs_dot(const typename CT<T>::t* V, int64_t ldv, int64_t v_ms, int nc,
             const typename CT<TX>::t* x0, int64_t x0_ms, const typename CT<TX>::t* x1,
             int64_t x1_ms, double2* partial, int nblk, int64_t n, int nmem, hipStream_t st,
             const int* act = nullptr);
-// The same sums (one vector per member, nval = nc + 1, the same partials bit
-// for bit) when every member projects on one shared basis V: the basis is
-// read once per group of SHARED_MG members instead of once per member.
-// Needs nc <= SHARED_NC_MAX; V is the same for all members (no member stride).
+// The same sums (one vector per member, nval = nc + 1) when every member
+// projects on one shared basis V. An FP32 basis with FP64 members and n a
+// multiple of 16 runs on the FP64 matrix cores, 16 members per block (the
+// basis read once per 16 members; the sums in another order than gs_dot's);
+// otherwise the VALU form reads the basis once per group of SHARED_MG members
+// and gives gs_dot's partials bit for bit. Needs nc <= SHARED_NC_MAX; V is
+// the same for all members (no member stride).
 constexpr int SHARED_MG = 4;
 constexpr int SHARED_NC_MAX = 32;
 template <typename T, typename TX>
