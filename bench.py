@@ -245,6 +245,26 @@ def uneven_batch(a, gdr, synth, torch, np):
         inputs.append((name, cfg, links, B))
         log("bench: inputs", name, cfg["dims"])
 
+    def cu_stream(small):
+        # a stream whose kernels run on part of the CUs: the small lattices on
+        # a.c5_cu_split CUs of each XCD, the 32^3x64 lattice on the rest. The
+        # set {32x + 8c + x} holds a.c5_cu_split CUs of every XCD whether mask
+        # bit i names a CU of XCD i % 8 or of XCD i // 32.
+        import ctypes
+        ncu = torch.cuda.get_device_properties(0).multi_processor_count
+        if ncu != 256:
+            raise SystemExit("--c5-cu-split assumes 256 CUs in 8 XCDs (found %d CUs)" % ncu)
+        sel = {32 * x + 8 * c + x for x in range(8) for c in range(a.c5_cu_split)}
+        bits = [(i in sel) == small for i in range(256)]
+        words = [sum(1 << b for b in range(32) if bits[32 * w + b]) for w in range(8)]
+        hip = ctypes.CDLL("libamdhip64.so")
+        h = ctypes.c_void_p()
+        arr = (ctypes.c_uint32 * 8)(*words)
+        rc = hip.hipExtStreamCreateWithCUMask(ctypes.byref(h), ctypes.c_uint32(8), arr)
+        if rc != 0:
+            raise SystemExit("hipExtStreamCreateWithCUMask failed: %d" % rc)
+        return torch.cuda.ExternalStream(h.value)
+
     def make_runs():
         # one context, stream and operator per lattice; each context keeps
         # its own device-memory cache, so the FP64 and the mixed batch get
@@ -252,7 +272,7 @@ def uneven_batch(a, gdr, synth, torch, np):
         # crowd the mixed one into allocating inside its timed region)
         out = []
         for name, cfg, links, B in inputs:
-            stream = torch.cuda.Stream()
+            stream = cu_stream(name != "C5") if a.c5_cu_split else torch.cuda.Stream()
             ctx = gdr.gdr_ctx_create(0, stream.cuda_stream)
             lst = gdr.GDR_LINKS_F16 if cfg.get("links") == "f16" else gdr.GDR_LINKS_F32
             if a.c5_links == "f32":
@@ -447,8 +467,7 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=None,
                     help="untimed steps first (default 1; 2 for C5, whose first concurrent batch "
-                         "after the FP64 one still grows the shared device-memory pool: 3.56 s "
-                         "against 2.98 s for the steps after it)")
+                         "after the FP64 one still grows the shared device-memory cache)")
     ap.add_argument("--workload", default="C4")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
@@ -471,6 +490,9 @@ def main():
     ap.add_argument("--c5-links", choices=["f16", "f32"], default="f16",
                     help="link storage of the uneven batch's 32^3x64 lattice (default: the "
                          "workload's FP16)")
+    ap.add_argument("--c5-cu-split", type=int, default=0,
+                    help="uneven batch: the small lattices' streams on this many CUs of each XCD, "
+                         "the 32^3x64 lattice's on the others (CU-masked streams; 0: all CUs)")
     ap.add_argument("--c5-persistent", type=int, choices=[0, 1], default=1,
                     help="uneven batch: the ten small lattices as one gdr_solve_many call with "
                          "persistent work-list launches (1) or on contexts of their own (0)")

@@ -33,10 +33,13 @@ void DevPool::attach(int dev) {
     if (s.cap == 0) {
         // a block released to the driver is expensive to get back (after
         // large frees, hipMalloc of a multi-GB block has taken 0.3-0.9 s), so
-        // up to half of the device may stay idle: enough for every phase of a
-        // 32^3x64 solve (about 130 GB) to find its buffers again
+        // up to 60 % of the device may stay idle: enough for every phase of a
+        // 32^3x64 solve (about 130 GB) to find its buffers again while other
+        // contexts on the device keep theirs (at half the device, ten small
+        // lattices' caches pushed the 32^3x64 lattice's projection buffers
+        // out between solves, and each solve allocated them again)
         size_t fr = 0, tot = 0;
-        if (hipMemGetInfo(&fr, &tot) == hipSuccess) s.cap = tot / 2;
+        if (hipMemGetInfo(&fr, &tot) == hipSuccess) s.cap = tot / 10 * 6;
         else (void)hipGetLastError();
     }
     g_reg.push_back(this);
