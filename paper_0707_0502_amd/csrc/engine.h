@@ -32,7 +32,7 @@ namespace gdr {
 // call; returning them here instead of to the driver lets the next call (or
 // the next batch of the same call) reuse them without mapping new memory.
 // Best fit within +25 % (sizes rounded up to 2 MiB). The idle blocks of all
-// contexts on one device together stay below half of the device's memory:
+// contexts on one device together stay below 60 % of the device's memory:
 // returning a block past that releases the returning context's least
 // recently returned blocks. An allocation that fails releases the context's
 // own idle blocks and retries, then the idle blocks of every other context
