@@ -55,11 +55,18 @@ __device__ __forceinline__ bool key_less(double2 a, double2 b) {
 
 // Householder QR of the first `cols` columns of the rows x ctot LDS matrix A;
 // the remaining columns receive Q^H. R is left in the upper triangle.
-__device__ void hh_qr(double2* A, int rows, int cols, int ctot, double2* hv) {
+// Column j may be nonzero down to row max(j + 1, band) only (band = rows:
+// dense): an upper Hessenberg matrix whose leading block is dense down to
+// row band, as the cycle's H_bar after a restart to band deflation vectors.
+// The reflector of column j then has nonzeros in rows j..max(j + 1, band)
+// only, and the loops stop there (the rows below hold exact zeros, so the
+// result is that of the dense loops).
+__device__ void hh_qr(double2* A, int rows, int cols, int ctot, double2* hv, int band) {
     const int lane = threadIdx.x;
     for (int j = 0; j < cols && j < rows; ++j) {
+        const int end = min(rows, max(j + 2, band + 1));   // rows j..end-1
         double ss = 0;
-        for (int r = j + lane; r < rows; r += 64) ss += cabs2(AT(A, r, j));
+        for (int r = j + lane; r < end; r += 64) ss += cabs2(AT(A, r, j));
         ss = wred(ss);
         const double alpha = sqrt(ss);
         const double2 x0 = AT(A, j, j);
@@ -67,17 +74,17 @@ __device__ void hh_qr(double2* A, int rows, int cols, int ctot, double2* hv) {
         __syncthreads();
         if (!(alpha > 0.0)) continue;
         const double2 ph = ax0 > 0 ? cscale(x0, 1.0 / ax0) : mk(1, 0);
-        for (int r = j + lane; r < rows; r += 64)
+        for (int r = j + lane; r < end; r += 64)
             hv[r] = (r == j) ? cadd(x0, cscale(ph, alpha)) : AT(A, r, j);
         const double tau = 1.0 / (alpha * (alpha + ax0));   // 2 / ||v||^2
         __syncthreads();
         for (int c = j + 1 + lane; c < ctot; c += 64) {
             double2 d = mk(0, 0);
-            for (int r = j; r < rows; ++r) d = cadd(d, cjmul(hv[r], AT(A, r, c)));
+            for (int r = j; r < end; ++r) d = cadd(d, cjmul(hv[r], AT(A, r, c)));
             d = cscale(d, tau);
-            for (int r = j; r < rows; ++r) AT(A, r, c) = csub(AT(A, r, c), cmul(hv[r], d));
+            for (int r = j; r < end; ++r) AT(A, r, c) = csub(AT(A, r, c), cmul(hv[r], d));
         }
-        for (int r = j + lane; r < rows; r += 64) AT(A, r, j) = (r == j) ? cscale(ph, -alpha) : mk(0, 0);
+        for (int r = j + lane; r < end; r += 64) AT(A, r, j) = (r == j) ? cscale(ph, -alpha) : mk(0, 0);
         __syncthreads();
     }
 }
@@ -437,7 +444,7 @@ __global__ __launch_bounds__(64) void k_cycle_small(CycleArgs a) {
                 AT(A, r, c) = v;
             }
         __syncthreads();
-        hh_qr(A, rows, p, p + 1, hv);
+        hh_qr(A, rows, p, p + 1, hv, a.k);
         for (int r = lane; r < p; r += 64) dv[r] = AT(A, r, p);
         __syncthreads();
         base_ok = back_sub(A, p, dv);
@@ -505,7 +512,7 @@ __global__ __launch_bounds__(64) void k_cycle_small(CycleArgs a) {
                 AT(A, r, c) = v;
             }
         __syncthreads();
-        hh_qr(A, m, m, m + 1, hv);
+        hh_qr(A, m, m, m + 1, hv, m);
         for (int r = lane; r < m; r += 64) fv[r] = AT(A, r, m);
         __syncthreads();
         back_sub(A, m, fv);
@@ -628,7 +635,7 @@ __global__ __launch_bounds__(64) void k_cycle_small(CycleArgs a) {
                 AT(A, r, c) = v;
             }
         __syncthreads();
-        hh_qr(A, p, p, p + 1, hv);
+        hh_qr(A, p, p, p + 1, hv, a.k);
         for (int r = lane; r < p; r += 64) dv[r] = AT(A, r, p);
         __syncthreads();
         bool bad = !back_sub(A, p, dv);
@@ -659,7 +666,7 @@ __global__ __launch_bounds__(64) void k_cycle_small(CycleArgs a) {
             AT(A, r, c) = v;
         }
     __syncthreads();
-    hh_qr(A, p + 1, p, p + 2, hv);
+    hh_qr(A, p + 1, p, p + 2, hv, a.k);
     double2 bnew;
     bool bad = false;
     if (exact) {
@@ -872,7 +879,7 @@ __global__ __launch_bounds__(64) void k_proj_small(ProjArgs a) {
             AT(A, r, c) = v;
         }
     __syncthreads();
-    hh_qr(A, k + 1, kp, kp + 1, hv);
+    hh_qr(A, k + 1, kp, kp + 1, hv, k + 1);
     for (int r = lane; r < kp; r += 64) d1[r] = AT(A, r, kp);
     __syncthreads();
     bool bad = !back_sub(A, kp, d1);
@@ -907,7 +914,7 @@ __global__ __launch_bounds__(64) void k_proj_small(ProjArgs a) {
                 AT(A, r, c) = v;
             }
         __syncthreads();
-        hh_qr(A, kp, kp, kp + 1, hv);
+        hh_qr(A, kp, kp, kp + 1, hv, kp);
         for (int r = lane; r < kp; r += 64) di[r] = AT(A, r, kp);
         __syncthreads();
         if (!back_sub(A, kp, di)) bad = true;
