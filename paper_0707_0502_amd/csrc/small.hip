@@ -816,8 +816,24 @@ __global__ __launch_bounds__(64) void k_sstep_small(SstepArgs a) {
     const double2 th = a.thetas ? a.thetas[b] : a.theta;
     const double rho = a.rhos ? a.rhos[b] : a.rho;
     for (int r = lane; r <= a.m; r += 64) {
+        // (H_old M_a)[r][c] over all columns l < j, for every c of the block
+        // at once (each entry of row r read once; each sum still runs over l
+        // in order): after a deflated restart the leading (k+1) x k block of
+        // H_old is full, not Hessenberg
+        double2 hmv[BLK_MAX];
+#pragma unroll
+        for (int c = 0; c < BLK_MAX; ++c) hmv[c] = mk(0, 0);
+        if (r <= j)
+            for (int l = 0; l < j; ++l) {
+                const double2 h = H[(int64_t)l * a.ldh + r];
+#pragma unroll
+                for (int c = 1; c < BLK_MAX; ++c)
+                    if (c < bs) hmv[c] = cadd(hmv[c], cmul(h, Ch[l * BLK_MAX + c - 1]));
+            }
         double2 X[BLK_MAX];
-        for (int c = 0; c < bs; ++c) {
+#pragma unroll
+        for (int c = 0; c < BLK_MAX; ++c) {
+            if (c >= bs) break;
             // coordinates of z_{c+1} (Zc) and of z_c (Zh) on row r
             auto zc = [&](int cc) -> double2 {
                 if (r <= j) return Ch[r * BLK_MAX + cc];
@@ -826,15 +842,7 @@ __global__ __launch_bounds__(64) void k_sstep_small(SstepArgs a) {
             };
             const double2 zh = c == 0 ? mk(r == j ? 1.0 : 0.0, 0) : zc(c - 1);
             double2 t = cadd(cscale(zc(c), rho), cmul(th, zh));
-            if (c >= 1 && r <= j) {
-                // (H_old M_a)[r][c] over all columns l < j: after a deflated
-                // restart the leading (k+1) x k block of H_old is full, not
-                // Hessenberg
-                double2 hm = mk(0, 0);
-                for (int l = 0; l < j; ++l)
-                    hm = cadd(hm, cmul(H[(int64_t)l * a.ldh + r], Ch[l * BLK_MAX + c - 1]));
-                t = csub(t, hm);
-            }
+            if (c >= 1 && r <= j) t = csub(t, hmv[c]);
             // X[:, c] = (T[:, c] - sum_{l<c} X[:, l] Mb[l][c]) / Mb[c][c]
             for (int l = 0; l < c; ++l) {
                 const double2 mb = l == 0 ? Ch[j * BLK_MAX + c - 1] : R[(l - 1) * BLK_MAX + c - 1];
@@ -842,7 +850,9 @@ __global__ __launch_bounds__(64) void k_sstep_small(SstepArgs a) {
             }
             X[c] = c == 0 ? t : cdiv(t, R[(c - 1) * BLK_MAX + c - 1]);
         }
-        for (int c = 0; c < bs; ++c) H[(int64_t)(j + c) * a.ldh + r] = r <= j + c + 1 ? X[c] : mk(0, 0);
+#pragma unroll
+        for (int c = 0; c < BLK_MAX; ++c)
+            if (c < bs) H[(int64_t)(j + c) * a.ldh + r] = r <= j + c + 1 ? X[c] : mk(0, 0);
     }
 }
 
