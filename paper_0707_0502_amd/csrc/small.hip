@@ -865,9 +865,13 @@ void cycle_small(const CycleArgs& a, int nmem, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
+// One block per (shift, member): every block solves the base problem (the
+// shifted ones need d1 and y), block 0 stores it, block i >= 1 the system of
+// shift i, so the shifts' QR factorisations run side by side.
 __global__ __launch_bounds__(64) void k_proj_small(ProjArgs a) {
     const int lane = threadIdx.x;
-    const int b = blockIdx.x;
+    const int role = blockIdx.x;
+    const int b = blockIdx.y;
     if (a.act && !a.act[b]) return;
     const int k = a.k;
     const int kp = a.kp;   // leading columns used (k: the full projection)
@@ -904,11 +908,13 @@ __global__ __launch_bounds__(64) void k_proj_small(ProjArgs a) {
         y[r] = acc;
     }
     __syncthreads();
-    for (int r = lane; r <= k; r += 64) {
-        coef[r] = r < kp ? d1[r] : mk(0, 0);
-        coef[ns * (k + 1) + r] = mk(-y[r].x, -y[r].y);
-    }
-    for (int i = 1; i < ns; ++i) {
+    if (role == 0)
+        for (int r = lane; r <= k; r += 64) {
+            coef[r] = r < kp ? d1[r] : mk(0, 0);
+            coef[ns * (k + 1) + r] = mk(-y[r].x, -y[r].y);
+        }
+    if (role >= 1 && role < ns) {
+        const int i = role;
         const double2 si = sig[i], bi = beta[i];
         __syncthreads();
         // first kp rows: (H - sigma_i I) d_i = beta_i (H - sigma_1 I) d_1
@@ -938,11 +944,11 @@ __global__ __launch_bounds__(64) void k_proj_small(ProjArgs a) {
             if (lane == 0) gam[i] = cadd(gam[i], g);
         }
     }
-    if (lane == 0 && bad) a.flags[b] |= 1;
+    if (lane == 0 && bad) atomicOr(&a.flags[b], 1);
 }
 
 void proj_small(const ProjArgs& a, int nmem, hipStream_t st) {
-    hipLaunchKernelGGL(k_proj_small, dim3(nmem), dim3(64), 0, st, a);
+    hipLaunchKernelGGL(k_proj_small, dim3(a.ns, nmem), dim3(64), 0, st, a);
 }
 
 
